@@ -1,0 +1,458 @@
+/*
+ * MinMaxLTTB reference oracle -- TEST INFRASTRUCTURE ONLY.
+ *
+ * A plain, slow, scalar CPU statement of what the MinMaxLTTB downsampling
+ * path computes (Van Der Donckt, Van Der Donckt, Rademaker, Van Hoecke,
+ * "MinMaxLTTB: Leveraging MinMax-Preselection to Scale LTTB", 2023).
+ * Only the test suite, the smoke check and the benchmark's CPU-baseline leg
+ * load this library. The GPU library never links it, and the two share no
+ * code, header, table or helper.
+ *
+ * Build: gcc -O2 -ffp-contract=off -std=c11 -shared -fPIC, no fast-math.
+ * On x86-64 every `double` operation below is then one IEEE-754 binary64
+ * operation rounded to nearest-even, with no fused multiply-add.
+ *
+ * What the paper fixes:
+ *   - MinMax keeps, per bin, the points holding the minimum and the maximum
+ *     of y (section 2.2.1, Table 1).
+ *   - LTTB keeps, per bucket, the point spanning the largest triangle with
+ *     the point kept in the previous bucket and the mean (x, y) of the next
+ *     bucket; first and last points are kept (section 2.2.1, Fig. 3).
+ *   - MinMaxLTTB preselects r_ps * n_out points with MinMax, r_ps >= 2 an
+ *     integer, r_ps/2 min-max sub-buckets per LTTB bucket, adds the first and
+ *     last points, and runs LTTB on that set only (section 3).
+ *
+ * Readings where the paper is silent (each is also listed in the design
+ * notes and pinned by a test):
+ *   R1  number of MinMax bins nb = floor(n_out * r_ps / 2).
+ *   R2  MinMax bins cover the interior [1, n-1) with equal-index integer
+ *       boundaries 1 + floor(b * (n-2) / nb); empty bins are skipped.
+ *   R3  min and max ties go to the lowest index; values compare as IEEE
+ *       numbers (so -0.0 == +0.0); a bin whose min and max point coincide
+ *       contributes one index.
+ *   R4  the preselection P is the sorted distinct set {0, n-1} + all
+ *       per-bin argmin/argmax indices; LTTB then runs as plain LTTB over P
+ *       (sub-bucket alignment is not enforced).
+ *   R5  LTTB buckets: n_out-2 interior buckets over positions [1, m-1) with
+ *       boundaries 1 + floor(k * (m-2) / (n_out-2)).
+ *   R6  next-bucket mean: exact sum of the raw x (integers) and of y
+ *       (float32), each rounded once to binary64, then divided by the count
+ *       with one binary64 division. The last interior bucket uses the last
+ *       point alone.
+ *   R7  area (doubled, the 1/2 is dropped):
+ *         |(Xa - MX) * (Yj - Ya) - (Xa - Xj) * (MY - Ya)|
+ *       in binary64, each operation rounded separately, in this order.
+ *       X = x rounded to binary64 (x implicit: the index), Y = y widened.
+ *   R8  area ties go to the lowest index.
+ *   R9  n <= n_out returns every index; n < 1, n_out < 3 or r_ps < 2 is an
+ *       argument error. No other short-circuit: P is always computed.
+ *   R10 y must be finite; the oracle refuses non-finite input.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORC_OK 0
+#define ORC_EINVAL (-1)
+#define ORC_ENOTFINITE (-5)
+#define ORC_ENOMEM (-6)
+
+#define XK_IMPLICIT 0
+#define XK_INT64 1
+
+/* ------------------------------------------------------------------------ */
+/* Exact sums, rounded once to binary64 (reading R6).                        */
+/* A big unsigned integer, 32-bit words, least significant word first.       */
+/* ------------------------------------------------------------------------ */
+
+#define BIG_WORDS 16 /* 512 bits: float32 sums need < 2^(277+64) */
+
+typedef struct {
+    uint32_t w[BIG_WORDS];
+} big_t;
+
+static void big_zero(big_t *a) { memset(a, 0, sizeof(*a)); }
+
+/* a += v << shift, for v < 2^32 */
+static void big_add_u32_shifted(big_t *a, uint32_t v, int shift)
+{
+    int word = shift / 32;
+    int bit = shift % 32;
+    uint64_t wide = (uint64_t)v << bit; /* < 2^63 */
+    uint64_t carry = 0;
+    for (int i = word; i < BIG_WORDS; i++) {
+        uint64_t add = 0;
+        if (i == word)
+            add = wide & 0xffffffffu;
+        else if (i == word + 1)
+            add = wide >> 32;
+        uint64_t s = (uint64_t)a->w[i] + add + carry;
+        a->w[i] = (uint32_t)s;
+        carry = s >> 32;
+    }
+}
+
+static int big_cmp(const big_t *a, const big_t *b)
+{
+    for (int i = BIG_WORDS - 1; i >= 0; i--) {
+        if (a->w[i] != b->w[i])
+            return a->w[i] < b->w[i] ? -1 : 1;
+    }
+    return 0;
+}
+
+/* r = a - b, requires a >= b */
+static void big_sub(big_t *r, const big_t *a, const big_t *b)
+{
+    int64_t borrow = 0;
+    for (int i = 0; i < BIG_WORDS; i++) {
+        int64_t d = (int64_t)a->w[i] - (int64_t)b->w[i] - borrow;
+        borrow = 0;
+        if (d < 0) {
+            d += (int64_t)1 << 32;
+            borrow = 1;
+        }
+        r->w[i] = (uint32_t)d;
+    }
+}
+
+static int big_bit(const big_t *a, int i) { return (int)((a->w[i / 32] >> (i % 32)) & 1u); }
+
+/* The binary64 nearest to (negative ? -1 : 1) * a * 2^scale_exp, ties to
+ * even. The callers keep the result inside the normal binary64 range. */
+static double big_round_to_double(const big_t *a, int scale_exp, int negative)
+{
+    int top = -1;
+    for (int i = BIG_WORDS * 32 - 1; i >= 0; i--) {
+        if (big_bit(a, i)) {
+            top = i;
+            break;
+        }
+    }
+    if (top < 0)
+        return 0.0;
+    uint64_t mant = 0;
+    int low; /* weight (bit position) of the mantissa's last kept bit */
+    if (top <= 52) {
+        for (int i = top; i >= 0; i--)
+            mant = (mant << 1) | (uint64_t)big_bit(a, i);
+        low = 0;
+    } else {
+        low = top - 52;
+        for (int i = top; i >= low; i--)
+            mant = (mant << 1) | (uint64_t)big_bit(a, i);
+        int round_bit = big_bit(a, low - 1);
+        int sticky = 0;
+        for (int i = low - 2; i >= 0; i--)
+            sticky |= big_bit(a, i);
+        if (round_bit && (sticky || (mant & 1u)))
+            mant += 1; /* may reach 2^53: still exact in binary64 */
+    }
+    double r = ldexp((double)mant, low + scale_exp);
+    return negative ? -r : r;
+}
+
+/* RN(sum of v[0..c-1]) with the sum taken exactly. Every finite float32 is
+ * an integer multiple of 2^-149 of magnitude below 2^128, so the sum is an
+ * integer count of 2^-149 units; positive and negative parts are kept apart. */
+static double exact_sum_f32(const float *v, int64_t c)
+{
+    big_t pos, neg;
+    big_zero(&pos);
+    big_zero(&neg);
+    for (int64_t i = 0; i < c; i++) {
+        uint32_t bits;
+        memcpy(&bits, &v[i], 4);
+        uint32_t expo = (bits >> 23) & 0xffu;
+        uint32_t frac = bits & 0x7fffffu;
+        uint32_t mant;
+        int shift;
+        if (expo == 0) { /* zero or subnormal: frac * 2^-149 */
+            mant = frac;
+            shift = 0;
+        } else { /* normal: (2^23 + frac) * 2^(expo - 150) */
+            mant = frac | 0x800000u;
+            shift = (int)expo - 1;
+        }
+        if (bits >> 31)
+            big_add_u32_shifted(&neg, mant, shift);
+        else
+            big_add_u32_shifted(&pos, mant, shift);
+    }
+    big_t mag;
+    int negative = 0;
+    if (big_cmp(&pos, &neg) >= 0) {
+        big_sub(&mag, &pos, &neg);
+    } else {
+        big_sub(&mag, &neg, &pos);
+        negative = 1;
+    }
+    return big_round_to_double(&mag, -149, negative);
+}
+
+/* RN(sum of x[0..c-1]) with the sum taken exactly in 128-bit integers. */
+static double exact_sum_i64(const int64_t *x, int64_t c)
+{
+    __int128 s = 0;
+    for (int64_t i = 0; i < c; i++)
+        s += (__int128)x[i];
+    int negative = s < 0;
+    unsigned __int128 mag = negative ? (unsigned __int128)(-s) : (unsigned __int128)s;
+    big_t a;
+    big_zero(&a);
+    for (int i = 0; i < 4; i++)
+        a.w[i] = (uint32_t)(mag >> (32 * i));
+    return big_round_to_double(&a, 0, negative);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Boundaries                                                               */
+/* ------------------------------------------------------------------------ */
+
+/* floor(k * len / parts), exact */
+static int64_t floor_frac(int64_t k, int64_t len, int64_t parts)
+{
+    return (int64_t)(((__int128)k * (__int128)len) / (__int128)parts);
+}
+
+static int is_finite_f32(float v) { return isfinite(v); }
+
+/* ------------------------------------------------------------------------ */
+/* MinMax preselection (section 2.2.1 MinMax; section 3 step (i); R1-R4).    */
+/* ------------------------------------------------------------------------ */
+
+static int cmp_i64(const void *a, const void *b)
+{
+    int64_t x = *(const int64_t *)a, y = *(const int64_t *)b;
+    return (x > y) - (x < y);
+}
+
+/* Writes the sorted distinct preselection into P (capacity 2*nb+2) and its
+ * size into *m. */
+int oracle_minmax(const float *y, int64_t n, int64_t n_out, int32_t r_ps, int64_t *P, int64_t *m)
+{
+    if (n < 1 || n_out < 3 || r_ps < 2)
+        return ORC_EINVAL;
+    for (int64_t i = 0; i < n; i++)
+        if (!is_finite_f32(y[i]))
+            return ORC_ENOTFINITE;
+    int64_t cnt = 0;
+    if (n <= 2) {
+        for (int64_t i = 0; i < n; i++)
+            P[cnt++] = i;
+        *m = cnt;
+        return ORC_OK;
+    }
+    int64_t nb = (int64_t)(((__int128)n_out * r_ps) / 2); /* R1 */
+    int64_t L = n - 2;
+    P[cnt++] = 0;
+    for (int64_t b = 0; b < nb; b++) {
+        int64_t lo = 1 + floor_frac(b, L, nb); /* R2 */
+        int64_t hi = 1 + floor_frac(b + 1, L, nb);
+        if (lo == hi)
+            continue;
+        int64_t imin = lo, imax = lo;
+        for (int64_t i = lo + 1; i < hi; i++) {
+            if (y[i] < y[imin]) /* strict: lowest index wins ties (R3) */
+                imin = i;
+            if (y[i] > y[imax])
+                imax = i;
+        }
+        P[cnt++] = imin;
+        if (imax != imin)
+            P[cnt++] = imax;
+    }
+    P[cnt++] = n - 1;
+    qsort(P, (size_t)cnt, sizeof(int64_t), cmp_i64);
+    int64_t d = 0;
+    for (int64_t i = 0; i < cnt; i++)
+        if (d == 0 || P[i] != P[d - 1])
+            P[d++] = P[i];
+    *m = d;
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* LTTB over a point sequence (section 2.2.1 LTTB, Fig. 3; R5-R8).            */
+/* xs: raw integer abscissae of the m points, ys: their ordinates.           */
+/* ------------------------------------------------------------------------ */
+
+/* Next-bucket means for every interior bucket k = 0..B-1 (R6). */
+static void lttb_means(const int64_t *xs, const float *ys, int64_t m, int64_t n_out, double *MX, double *MY)
+{
+    int64_t B = n_out - 2;
+    for (int64_t k = 0; k < B; k++) {
+        int64_t g0, g1;
+        if (k < B - 1) {
+            g0 = 1 + floor_frac(k + 1, m - 2, B);
+            g1 = 1 + floor_frac(k + 2, m - 2, B);
+        } else {
+            g0 = m - 1;
+            g1 = m;
+        }
+        double c = (double)(g1 - g0);
+        MX[k] = exact_sum_i64(xs + g0, g1 - g0) / c;
+        MY[k] = exact_sum_f32(ys + g0, g1 - g0) / c;
+    }
+}
+
+/* Selected positions (0..m-1) into out[0..min(m, n_out)-1]. */
+static int lttb_positions(const int64_t *xs, const float *ys, int64_t m, int64_t n_out, int64_t *out)
+{
+    if (m <= n_out) {
+        for (int64_t i = 0; i < m; i++)
+            out[i] = i;
+        return ORC_OK;
+    }
+    int64_t B = n_out - 2;
+    double *MX = (double *)malloc(sizeof(double) * (size_t)B);
+    double *MY = (double *)malloc(sizeof(double) * (size_t)B);
+    if (!MX || !MY) {
+        free(MX);
+        free(MY);
+        return ORC_ENOMEM;
+    }
+    lttb_means(xs, ys, m, n_out, MX, MY);
+    int64_t a = 0;
+    out[0] = 0;
+    for (int64_t k = 0; k < B; k++) {
+        int64_t s0 = 1 + floor_frac(k, m - 2, B); /* R5 */
+        int64_t s1 = 1 + floor_frac(k + 1, m - 2, B);
+        double Xa = (double)xs[a];
+        double Ya = (double)ys[a];
+        double best = -1.0; /* every area is >= 0 */
+        int64_t sel = -1;
+        for (int64_t j = s0; j < s1; j++) {
+            double Xj = (double)xs[j];
+            double Yj = (double)ys[j];
+            double area = fabs((Xa - MX[k]) * (Yj - Ya) - (Xa - Xj) * (MY[k] - Ya)); /* R7 */
+            if (area > best) { /* strict: lowest index wins ties (R8) */
+                best = area;
+                sel = j;
+            }
+        }
+        out[k + 1] = sel;
+        a = sel;
+    }
+    out[n_out - 1] = m - 1;
+    free(MX);
+    free(MY);
+    return ORC_OK;
+}
+
+static int64_t *abscissae(int xk, const int64_t *x, int64_t n)
+{
+    int64_t *xs = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
+    if (!xs)
+        return NULL;
+    for (int64_t i = 0; i < n; i++)
+        xs[i] = (xk == XK_INT64) ? x[i] : i;
+    return xs;
+}
+
+static int check_x(int xk, const int64_t *x)
+{
+    if (xk == XK_IMPLICIT)
+        return x == NULL ? ORC_OK : ORC_EINVAL;
+    if (xk == XK_INT64)
+        return x != NULL ? ORC_OK : ORC_EINVAL;
+    return ORC_EINVAL;
+}
+
+/* Plain LTTB on all n points; out holds min(n, n_out) indices. */
+int oracle_lttb(int xk, const int64_t *x, const float *y, int64_t n, int64_t n_out, int64_t *out)
+{
+    if (n < 1 || n_out < 3 || check_x(xk, x) != ORC_OK)
+        return ORC_EINVAL;
+    for (int64_t i = 0; i < n; i++)
+        if (!is_finite_f32(y[i]))
+            return ORC_ENOTFINITE;
+    int64_t *xs = abscissae(xk, x, n);
+    if (!xs)
+        return ORC_ENOMEM;
+    int rc = lttb_positions(xs, y, n, n_out, out);
+    free(xs);
+    return rc;
+}
+
+/* MinMaxLTTB (section 3): MinMax preselection, then LTTB on the preselected
+ * points only; out holds min(n, n_out) indices into the original series. */
+int oracle_minmaxlttb(int xk, const int64_t *x, const float *y, int64_t n, int64_t n_out, int32_t r_ps, int64_t *out)
+{
+    if (n < 1 || n_out < 3 || r_ps < 2 || check_x(xk, x) != ORC_OK)
+        return ORC_EINVAL;
+    if (n <= n_out) {
+        for (int64_t i = 0; i < n; i++)
+            if (!is_finite_f32(y[i]))
+                return ORC_ENOTFINITE;
+        for (int64_t i = 0; i < n; i++)
+            out[i] = i;
+        return ORC_OK;
+    }
+    int64_t nb = (int64_t)(((__int128)n_out * r_ps) / 2);
+    int64_t cap = 2 * nb + 2;
+    int64_t *P = (int64_t *)malloc(sizeof(int64_t) * (size_t)cap);
+    if (!P)
+        return ORC_ENOMEM;
+    int64_t m = 0;
+    int rc = oracle_minmax(y, n, n_out, r_ps, P, &m);
+    if (rc != ORC_OK) {
+        free(P);
+        return rc;
+    }
+    int64_t *xs = (int64_t *)malloc(sizeof(int64_t) * (size_t)m);
+    float *ys = (float *)malloc(sizeof(float) * (size_t)m);
+    int64_t *pos = (int64_t *)malloc(sizeof(int64_t) * (size_t)n_out);
+    if (!xs || !ys || !pos) {
+        free(P);
+        free(xs);
+        free(ys);
+        free(pos);
+        return ORC_ENOMEM;
+    }
+    for (int64_t i = 0; i < m; i++) {
+        xs[i] = (xk == XK_INT64) ? x[P[i]] : P[i];
+        ys[i] = y[P[i]];
+    }
+    rc = lttb_positions(xs, ys, m, n_out, pos);
+    if (rc == ORC_OK) {
+        int64_t cnt = m < n_out ? m : n_out;
+        for (int64_t i = 0; i < cnt; i++)
+            out[i] = P[pos[i]];
+    }
+    free(P);
+    free(xs);
+    free(ys);
+    free(pos);
+    return rc;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Entry points exposed only so that tests can pin the pieces one by one.    */
+/* ------------------------------------------------------------------------ */
+
+/* Next-bucket means of LTTB over m points (R6); MX, MY hold n_out-2 values. */
+int oracle_lttb_means(int xk, const int64_t *x, const float *y, int64_t m, int64_t n_out, double *MX, double *MY)
+{
+    if (m <= n_out || n_out < 3 || check_x(xk, x) != ORC_OK)
+        return ORC_EINVAL;
+    int64_t *xs = abscissae(xk, x, m);
+    if (!xs)
+        return ORC_ENOMEM;
+    lttb_means(xs, y, m, n_out, MX, MY);
+    free(xs);
+    return ORC_OK;
+}
+
+int oracle_exact_sum_f32(const float *v, int64_t c, double *out)
+{
+    *out = exact_sum_f32(v, c);
+    return ORC_OK;
+}
+
+int oracle_exact_sum_i64(const int64_t *v, int64_t c, double *out)
+{
+    *out = exact_sum_i64(v, c);
+    return ORC_OK;
+}

@@ -1,0 +1,191 @@
+"""ctypes wrapper around the plain C oracle -- TEST INFRASTRUCTURE ONLY.
+
+Each function takes numpy arrays (y float32, x int64 or None for an implicit
+x = 0..n-1) and returns numpy int64 index arrays. See ``mmlttb_oracle.c`` for
+the definitions and the readings R1-R10 they follow.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+XK_IMPLICIT = 0
+XK_INT64 = 1
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "mmlttb_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+# No fast-math and no contraction: every double operation is one IEEE binary64
+# operation rounded to nearest-even.
+CFLAGS = ["-O2", "-std=gnu11", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared", "-Wall", "-Werror"]
+
+
+def lib_path() -> str:
+    return _LIB
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc into ``oracle/liboracle.so``."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["gcc", *CFLAGS, "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+class OracleError(RuntimeError):
+    def __init__(self, rc: int, what: str):
+        super().__init__(f"oracle {what} returned {rc}")
+        self.rc = rc
+
+
+_i64p = ctypes.POINTER(ctypes.c_int64)
+_f32p = ctypes.POINTER(ctypes.c_float)
+_f64p = ctypes.POINTER(ctypes.c_double)
+
+
+def _bind(path: str):
+    lib = ctypes.CDLL(path)
+    lib.oracle_minmax.argtypes = [_f32p, ctypes.c_int64, ctypes.c_int64, ctypes.c_int32, _i64p, _i64p]
+    lib.oracle_lttb.argtypes = [ctypes.c_int, _i64p, _f32p, ctypes.c_int64, ctypes.c_int64, _i64p]
+    lib.oracle_minmaxlttb.argtypes = [ctypes.c_int, _i64p, _f32p, ctypes.c_int64, ctypes.c_int64,
+                                      ctypes.c_int32, _i64p]
+    lib.oracle_lttb_means.argtypes = [ctypes.c_int, _i64p, _f32p, ctypes.c_int64, ctypes.c_int64, _f64p, _f64p]
+    lib.oracle_exact_sum_f32.argtypes = [_f32p, ctypes.c_int64, _f64p]
+    lib.oracle_exact_sum_i64.argtypes = [_i64p, ctypes.c_int64, _f64p]
+    for f in ("oracle_minmax", "oracle_lttb", "oracle_minmaxlttb", "oracle_lttb_means",
+              "oracle_exact_sum_f32", "oracle_exact_sum_i64"):
+        getattr(lib, f).restype = ctypes.c_int
+    return lib
+
+
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build(force=False)
+        _lib = _bind(_LIB)
+    return _lib
+
+
+def compile_variant(src_text: str, out_path: str):
+    """Compile a (test-modified) copy of the oracle source and return a module-like
+    namespace with minmax/lttb/minmaxlttb/lttb_means bound to it. Used only by the
+    test that plants mistakes in the oracle to show the pins catch them."""
+    c_path = out_path[:-3] + ".c"
+    with open(c_path, "w") as f:
+        f.write(src_text)
+    flags = [f for f in CFLAGS if f != "-Werror"]
+    subprocess.check_call(["gcc", *flags, "-w", "-o", out_path, c_path, "-lm"])
+    lib = _bind(out_path)
+
+    class _Variant:
+        pass
+
+    v = _Variant()
+    v.minmax = lambda y, n_out, r_ps: minmax(y, n_out, r_ps, _lib_override=lib)
+    v.lttb = lambda y, n_out, x=None: lttb(y, n_out, x, _lib_override=lib)
+    v.minmaxlttb = lambda y, n_out, r_ps, x=None: minmaxlttb(y, n_out, r_ps, x, _lib_override=lib)
+    v.lttb_means = lambda y, n_out, x=None: lttb_means(y, n_out, x, _lib_override=lib)
+    v.exact_sum_f32 = lambda a: exact_sum_f32(a, _lib_override=lib)
+    v.exact_sum_i64 = lambda a: exact_sum_i64(a, _lib_override=lib)
+    return v
+
+
+def source_text() -> str:
+    with open(_SRC) as f:
+        return f.read()
+
+
+def _f32(y) -> np.ndarray:
+    y = np.ascontiguousarray(y)
+    if y.dtype != np.float32:
+        raise TypeError("y must be float32")
+    return y
+
+
+def _x(x):
+    if x is None:
+        return XK_IMPLICIT, None, None
+    x = np.ascontiguousarray(x)
+    if x.dtype != np.int64:
+        raise TypeError("x must be int64")
+    return XK_INT64, x, x.ctypes.data_as(_i64p)
+
+
+def _ptr(a, t):
+    # a zero-length array still needs a valid pointer
+    return a.ctypes.data_as(t) if a.size else ctypes.cast(ctypes.create_string_buffer(16), t)
+
+
+def minmax(y, n_out: int, r_ps: int, _lib_override=None) -> np.ndarray:
+    """Sorted distinct MinMax preselection P (readings R1-R4)."""
+    y = _f32(y)
+    n = y.shape[0]
+    nb = (n_out * r_ps) // 2
+    P = np.empty(max(2 * nb + 2, n if n <= 2 else 0, 1), dtype=np.int64)
+    m = ctypes.c_int64(0)
+    rc = (_lib_override or _load()).oracle_minmax(_ptr(y, _f32p), n, n_out, r_ps, P.ctypes.data_as(_i64p), ctypes.byref(m))
+    if rc != 0:
+        raise OracleError(rc, "minmax")
+    return P[: m.value].copy()
+
+
+def lttb(y, n_out: int, x=None, _lib_override=None) -> np.ndarray:
+    """Plain LTTB over all points (readings R5-R9)."""
+    y = _f32(y)
+    xk, x, xp = _x(x)
+    n = y.shape[0]
+    out = np.empty(max(min(n, n_out), 1), dtype=np.int64)
+    rc = (_lib_override or _load()).oracle_lttb(xk, xp, _ptr(y, _f32p), n, n_out, out.ctypes.data_as(_i64p))
+    if rc != 0:
+        raise OracleError(rc, "lttb")
+    return out[: min(n, n_out)].copy()
+
+
+def minmaxlttb(y, n_out: int, r_ps: int, x=None, _lib_override=None) -> np.ndarray:
+    """MinMaxLTTB: MinMax preselection, then LTTB on the preselected points."""
+    y = _f32(y)
+    xk, x, xp = _x(x)
+    n = y.shape[0]
+    out = np.empty(max(min(n, n_out), 1), dtype=np.int64)
+    rc = (_lib_override or _load()).oracle_minmaxlttb(xk, xp, _ptr(y, _f32p), n, n_out, r_ps, out.ctypes.data_as(_i64p))
+    if rc != 0:
+        raise OracleError(rc, "minmaxlttb")
+    return out[: min(n, n_out)].copy()
+
+
+def lttb_means(y, n_out: int, x=None, _lib_override=None):
+    """(MX, MY) next-bucket means of LTTB over the given points (reading R6)."""
+    y = _f32(y)
+    xk, x, xp = _x(x)
+    m = y.shape[0]
+    B = n_out - 2
+    MX = np.empty(B, dtype=np.float64)
+    MY = np.empty(B, dtype=np.float64)
+    rc = (_lib_override or _load()).oracle_lttb_means(xk, xp, _ptr(y, _f32p), m, n_out, MX.ctypes.data_as(_f64p),
+                                   MY.ctypes.data_as(_f64p))
+    if rc != 0:
+        raise OracleError(rc, "lttb_means")
+    return MX, MY
+
+
+def exact_sum_f32(v, _lib_override=None) -> float:
+    v = _f32(v)
+    out = ctypes.c_double(0.0)
+    (_lib_override or _load()).oracle_exact_sum_f32(_ptr(v, _f32p), v.shape[0], ctypes.byref(out))
+    return out.value
+
+
+def exact_sum_i64(v, _lib_override=None) -> float:
+    v = np.ascontiguousarray(v, dtype=np.int64)
+    out = ctypes.c_double(0.0)
+    (_lib_override or _load()).oracle_exact_sum_i64(_ptr(v, _i64p), v.shape[0], ctypes.byref(out))
+    return out.value
