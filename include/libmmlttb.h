@@ -1,0 +1,150 @@
+/*
+ * libmmlttb -- MinMaxLTTB time-series downsampling on AMD Instinct MI355X (gfx950).
+ *
+ * MinMaxLTTB (Van Der Donckt et al., 2023) selects n_out points of a series
+ * (x, y) of n points for line-chart display in two steps (section 3):
+ *   (i)  MinMax preselection: in each of nb = floor(n_out * r_ps / 2) equal-index
+ *        bins over the interior points 1..n-2, keep the index of the minimum and
+ *        of the maximum of y (section 2.2.1, MinMax; r_ps/2 sub-buckets per LTTB
+ *        bucket, section 3), plus the first and the last point;
+ *   (ii) LTTB on the preselected points only: per bucket keep the point spanning
+ *        the largest triangle with the point kept in the previous bucket and the
+ *        mean (x, y) of the next bucket (section 2.2.1, LTTB; Fig. 3).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Buffers named x, y, out_idx, out_count, ws are DEVICE pointers owned by the
+ *   caller; segs_host is a HOST pointer. The library never allocates or frees
+ *   device memory inside these calls: scratch lives in the caller's workspace
+ *   `ws` of `ws_bytes` bytes, sized by the matching *_workspace_size call.
+ * - `stream` is a hipStream_t (NULL = the default stream). Work is enqueued on
+ *   it in order; calls return before the device finishes. ws must not be
+ *   reused by another call until the stream has passed this call.
+ * - y: float32[n], finite (precondition, not checked on the device).
+ * - x: with MMLTTB_X_IMPLICIT, x must be NULL and x_i = i; with MMLTTB_X_INT64,
+ *   x is int64[n], strictly increasing (precondition, not checked). x never
+ *   affects binning (bins are equal-index); it enters only the LTTB means and
+ *   areas, as binary64 values rounded from the integers.
+ * - Output indices are int64, ascending, into the series (segment-local in
+ *   batched mode). The selected values are y[idx] and x[idx]: exact copies.
+ * - Determinism: every output is a pure function of the inputs (no dependence
+ *   on launch geometry, tuning or timing); the CPU oracle gives the same
+ *   indices bit for bit.
+ * - Errors: arguments are checked on the host before anything is enqueued;
+ *   on error nothing is enqueued and the return is negative. A failed HIP
+ *   launch returns MMLTTB_EDEVICE. The message of the last error of the calling
+ *   thread is in mmlttb_last_error(). No C++ exception crosses this boundary.
+ * - Limits: 1 <= n <= 2^62; 3 <= n_out <= 2^31-1; 2 <= r_ps;
+ *   floor(n_out*r_ps/2) <= 2^31-1; each MinMax bin holds < 2^32 points.
+ */
+#ifndef LIBMMLTTB_H
+#define LIBMMLTTB_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    MMLTTB_OK = 0,
+    MMLTTB_EINVAL = -1,  /* bad argument; nothing enqueued */
+    MMLTTB_ENOMEM = -2,  /* ws_bytes below the required workspace size */
+    MMLTTB_EDEVICE = -3, /* a HIP call or kernel launch failed */
+    MMLTTB_ENOTSUP = -4  /* valid request this build does not handle */
+} mmlttb_status_t;
+
+typedef enum {
+    MMLTTB_X_IMPLICIT = 0, /* x_i = i, x == NULL */
+    MMLTTB_X_INT64 = 1     /* x is int64[n] */
+} mmlttb_xkind_t;
+
+/* One series of a batch (segment). offset: first element of the series in
+ * x_base/y_base; n, n_out, r_ps: as for mmlttb_minmaxlttb; out_offset: first
+ * slot of its min(n, n_out) output indices in out_idx_base. */
+typedef struct mmlttb_segment {
+    int64_t offset;
+    int64_t n;
+    int64_t n_out;
+    int32_t r_ps;
+    int32_t reserved; /* must be 0 */
+    int64_t out_offset;
+} mmlttb_segment_t;
+
+/* Library version string, static storage. */
+const char *mmlttb_version(void);
+
+/* Message of the last failed call on the calling thread ("" if none). */
+const char *mmlttb_last_error(void);
+
+/* Workspace bytes for mmlttb_minmax and mmlttb_minmaxlttb. The size depends
+ * on n_out and r_ps only, never on n: the method keeps O(n_out) state
+ * (Table 1, memory column; section 3.2). Returns 0 on invalid arguments. */
+size_t mmlttb_workspace_size(int64_t n, int64_t n_out, int32_t r_ps);
+
+/* Workspace bytes for mmlttb_lttb (next-bucket means and chain scratch);
+ * independent of n. Returns 0 on invalid arguments. */
+size_t mmlttb_lttb_workspace_size(int64_t n, int64_t n_out);
+
+/* MinMax preselection alone (section 2.2.1 MinMax; section 3 step (i)).
+ * Writes the sorted distinct preselected indices P = {0, n-1} plus, for each
+ * non-empty bin, the lowest index of its minimum and of its maximum of y
+ * (values compared as numbers, so -0.0 == +0.0) to out_idx[0..m-1] and m to
+ * the device scalar *out_count. out_idx capacity: 2*floor(n_out*r_ps/2) + 2
+ * (or n if smaller). x is validated but not read (bins are equal-index). */
+int mmlttb_minmax(int xk, const int64_t *x, const float *y, int64_t n, int64_t n_out, int32_t r_ps,
+                  int64_t *out_idx, int64_t *out_count, void *ws, size_t ws_bytes, void *stream);
+
+/* Plain LTTB over all n points (section 2.2.1 LTTB; Fig. 3): the comparator
+ * MinMaxLTTB is measured against. out_idx receives exactly min(n, n_out)
+ * indices: 0, one index per interior bucket, n-1. Interior buckets are the
+ * n_out-2 equal-index ranges 1 + floor(k*(n-2)/(n_out-2)); the next-bucket
+ * mean is the exact sum of x and of y, each rounded once to binary64, divided
+ * by the count (last bucket: the last point); the area is
+ * |(Xa-MX)*(Yj-Ya) - (Xa-Xj)*(MY-Ya)| in binary64, one rounding per operation,
+ * and ties go to the lowest index. n <= n_out returns 0..n-1. */
+int mmlttb_lttb(int xk, const int64_t *x, const float *y, int64_t n, int64_t n_out, int64_t *out_idx, void *ws,
+                size_t ws_bytes, void *stream);
+
+/* MinMaxLTTB (section 3): MinMax preselection (as mmlttb_minmax), then LTTB
+ * (as mmlttb_lttb) on the preselected points only, with buckets, means and
+ * areas taken over the preselected set. out_idx receives exactly
+ * min(n, n_out) indices into the original series. n <= n_out returns 0..n-1. */
+int mmlttb_minmaxlttb(int xk, const int64_t *x, const float *y, int64_t n, int64_t n_out, int32_t r_ps,
+                      int64_t *out_idx, void *ws, size_t ws_bytes, void *stream);
+
+/* Workspace bytes for mmlttb_minmaxlttb_batched over these segments (host
+ * array). Independent of the segment lengths. Returns 0 on invalid input. */
+size_t mmlttb_batched_workspace_size(const mmlttb_segment_t *segs_host, int64_t n_segs);
+
+/* MinMaxLTTB over many series in one call: segment s reads
+ * x_base[offset_s .. offset_s+n_s) (or implicit local x = 0..n_s-1) and
+ * y_base[offset_s ..], and writes min(n_s, n_out_s) SEGMENT-LOCAL indices to
+ * out_idx_base[out_offset_s ..]. Each segment's result equals
+ * mmlttb_minmaxlttb on that series alone. segs_host is copied into ws before
+ * the call returns. All segments are checked before anything is enqueued. */
+int mmlttb_minmaxlttb_batched(int xk, const int64_t *x_base, const float *y_base, const mmlttb_segment_t *segs_host,
+                              int64_t n_segs, int64_t *out_idx_base, void *ws, size_t ws_bytes, void *stream);
+
+/* Launch-geometry tuning of the MinMax stream (never changes results):
+ * unroll = 16-byte loads in flight per lane (1, 2, 4 or 8), chunk = points per
+ * work item (rounded up to a multiple of 256*unroll). A value of 0 keeps the
+ * current setting. Returns MMLTTB_EINVAL for other values. Not thread-safe
+ * with concurrent calls. */
+int mmlttb_set_tuning(int unroll, int64_t chunk);
+int mmlttb_get_tuning(int *unroll, int64_t *chunk);
+
+/* Kernel timing for measurement. When enabled, HIP events are recorded on the
+ * caller's stream around every launch of the named kernels; mmlttb_profile_read
+ * synchronises those events and returns the summed milliseconds and the
+ * launch count of `kernel` since the last reset. Not thread-safe; off by default. */
+int mmlttb_profile_enable(int on);
+int mmlttb_profile_reset(void);
+int mmlttb_profile_read(const char *kernel, double *total_ms, int64_t *launches);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LIBMMLTTB_H */

@@ -1,0 +1,20 @@
+"""libmmlttb: MinMaxLTTB time-series downsampling on AMD MI355X (gfx950).
+
+The compute path lives in ``libmmlttb.so`` (HIP kernels behind a C ABI, see
+``include/libmmlttb.h``); this package binds it with ctypes (``ops``), builds
+it (``build``), and holds the seeded synthetic inputs (``synth``). Importing
+the package does not load the library; the first call does, and raises if the
+library is not built.
+"""
+from .ops import (  # noqa: F401
+    lttb,
+    lttb_workspace_size,
+    minmax,
+    minmaxlttb,
+    profile_enable,
+    profile_read,
+    profile_reset,
+    workspace_size,
+    set_tuning,
+    get_tuning,
+)

@@ -1,0 +1,118 @@
+"""Python front end of libmmlttb on torch tensors (device memory + current stream).
+
+    idx = minmaxlttb(y, n_out=1000, r_ps=4)            # y: float32 cuda tensor
+    idx = minmaxlttb(y, n_out=2000, r_ps=4, x=x)       # x: int64 cuda tensor
+    P, m = minmax(y, n_out, r_ps)
+    idx = lttb(y, n_out, x=x)
+
+Each call only checks tensor types and passes pointers; the C library checks
+the arguments again and runs the whole path in HIP kernels on the current
+stream. Results are int64 device tensors of indices into the series.
+"""
+from __future__ import annotations
+
+import torch
+
+from . import _lib
+
+
+def _as_series(y, x):
+    if not isinstance(y, torch.Tensor) or y.dtype != torch.float32 or not y.is_cuda:
+        raise TypeError("y must be a float32 CUDA (HIP) tensor")
+    if y.dim() != 1 or not y.is_contiguous():
+        raise ValueError("y must be 1-D and contiguous")
+    if x is not None:
+        if not isinstance(x, torch.Tensor) or x.dtype != torch.int64 or x.device != y.device:
+            raise TypeError("x must be an int64 tensor on y's device")
+        if x.dim() != 1 or not x.is_contiguous() or x.numel() != y.numel():
+            raise ValueError("x must be 1-D, contiguous and as long as y")
+    return (_lib.X_INT64 if x is not None else _lib.X_IMPLICIT)
+
+
+def workspace_size(n: int, n_out: int, r_ps: int) -> int:
+    return int(_lib.load().mmlttb_workspace_size(n, n_out, r_ps))
+
+
+def lttb_workspace_size(n: int, n_out: int) -> int:
+    return int(_lib.load().mmlttb_lttb_workspace_size(n, n_out))
+
+
+def _workspace(nbytes: int, device, ws):
+    if ws is not None:
+        return ws
+    return torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=device)
+
+
+def minmax(y, n_out: int, r_ps: int, x=None, out=None, count=None, ws=None, sync: bool = True):
+    """MinMax preselection. Returns (P, m): P holds the sorted distinct indices in
+    P[:m]. With sync=False, m is returned as the device scalar tensor instead."""
+    lib = _lib.load()
+    xk = _as_series(y, x)
+    n = y.numel()
+    nb = n_out * r_ps // 2
+    cap = max(2 * nb + 2, min(n, 2), 1)
+    out = out if out is not None else torch.empty(cap, dtype=torch.int64, device=y.device)
+    count = count if count is not None else torch.empty(1, dtype=torch.int64, device=y.device)
+    ws = _workspace(lib.mmlttb_workspace_size(n, n_out, r_ps), y.device, ws)
+    _lib.check(lib.mmlttb_minmax(xk, _lib.ptr(x), y.data_ptr(), n, n_out, r_ps, out.data_ptr(), count.data_ptr(),
+                                 ws.data_ptr(), ws.numel(), _lib.stream_ptr()))
+    if not sync:
+        return out, count
+    m = int(count.item())
+    return out[:m], m
+
+
+def lttb(y, n_out: int, x=None, out=None, ws=None):
+    """Plain LTTB over every point (the comparator)."""
+    lib = _lib.load()
+    xk = _as_series(y, x)
+    n = y.numel()
+    out = out if out is not None else torch.empty(max(min(n, n_out), 1), dtype=torch.int64, device=y.device)
+    ws = _workspace(lib.mmlttb_lttb_workspace_size(n, n_out), y.device, ws)
+    _lib.check(lib.mmlttb_lttb(xk, _lib.ptr(x), y.data_ptr(), n, n_out, out.data_ptr(), ws.data_ptr(), ws.numel(),
+                               _lib.stream_ptr()))
+    return out[: min(n, n_out)]
+
+
+def minmaxlttb(y, n_out: int, r_ps: int, x=None, out=None, ws=None):
+    """MinMaxLTTB: MinMax preselection then LTTB on the preselected points."""
+    lib = _lib.load()
+    xk = _as_series(y, x)
+    n = y.numel()
+    out = out if out is not None else torch.empty(max(min(n, n_out), 1), dtype=torch.int64, device=y.device)
+    ws = _workspace(lib.mmlttb_workspace_size(n, n_out, r_ps), y.device, ws)
+    _lib.check(lib.mmlttb_minmaxlttb(xk, _lib.ptr(x), y.data_ptr(), n, n_out, r_ps, out.data_ptr(), ws.data_ptr(),
+                                     ws.numel(), _lib.stream_ptr()))
+    return out[: min(n, n_out)]
+
+
+def set_tuning(unroll: int = 0, chunk: int = 0):
+    """Launch geometry of the MinMax stream (results never depend on it)."""
+    _lib.check(_lib.load().mmlttb_set_tuning(unroll, chunk))
+
+
+def get_tuning():
+    import ctypes
+
+    u = ctypes.c_int(0)
+    c = ctypes.c_int64(0)
+    _lib.check(_lib.load().mmlttb_get_tuning(ctypes.byref(u), ctypes.byref(c)))
+    return u.value, c.value
+
+
+def profile_enable(on: bool = True):
+    _lib.check(_lib.load().mmlttb_profile_enable(1 if on else 0))
+
+
+def profile_reset():
+    _lib.check(_lib.load().mmlttb_profile_reset())
+
+
+def profile_read(kernel: str):
+    """(total milliseconds, launch count) of `kernel` since the last reset."""
+    import ctypes
+
+    ms = ctypes.c_double(0.0)
+    cnt = ctypes.c_int64(0)
+    _lib.check(_lib.load().mmlttb_profile_read(kernel.encode(), ctypes.byref(ms), ctypes.byref(cnt)))
+    return ms.value, cnt.value

@@ -1,0 +1,127 @@
+"""The C-ABI library loads and exports every declared symbol (CPU only; no
+compute call: only host-side argument checks and size queries, which return
+before any HIP call)."""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "libmmlttb.h")
+LIB = os.path.join(ROOT, "paper_2305_00332_amd", "libmmlttb.so")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[a-z_0-9]+\s*\*?\s*(mmlttb_[a-z_0-9]+)\s*\(", text, flags=re.M)
+    return sorted(set(names))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(LIB):
+        from paper_2305_00332_amd import build
+
+        build.build()
+    return ctypes.CDLL(LIB)
+
+
+def test_header_declares_the_four_calls():
+    names = declared_functions()
+    for f in ("mmlttb_minmax", "mmlttb_lttb", "mmlttb_minmaxlttb", "mmlttb_minmaxlttb_batched"):
+        assert f in names
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = declared_functions()
+    assert len(names) >= 10
+    for f in names:
+        assert hasattr(lib, f), f"{f} declared in libmmlttb.h but not exported"
+    out = subprocess.run(["nm", "-D", "--defined-only", LIB], capture_output=True, text=True).stdout
+    exported = set(re.findall(r"\bT (mmlttb_[a-z_0-9]+)$", out, flags=re.M))
+    assert set(names) <= exported
+
+
+def test_binding_lists_every_declared_symbol():
+    from paper_2305_00332_amd import _lib
+
+    assert set(declared_functions()) == set(_lib.EXPORTS)
+
+
+def test_library_was_built_for_gfx950():
+    data = open(LIB, "rb").read()
+    assert b"amdgcn-amd-amdhsa--gfx950" in data
+
+
+def _setup(lib):
+    lib.mmlttb_workspace_size.argtypes = [ctypes.c_int64, ctypes.c_int64, ctypes.c_int32]
+    lib.mmlttb_workspace_size.restype = ctypes.c_size_t
+    lib.mmlttb_lttb_workspace_size.argtypes = [ctypes.c_int64, ctypes.c_int64]
+    lib.mmlttb_lttb_workspace_size.restype = ctypes.c_size_t
+    lib.mmlttb_last_error.restype = ctypes.c_char_p
+    vp, i64, i32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32
+    lib.mmlttb_minmaxlttb.argtypes = [ctypes.c_int, vp, vp, i64, i64, i32, vp, vp, ctypes.c_size_t, vp]
+    lib.mmlttb_lttb.argtypes = [ctypes.c_int, vp, vp, i64, i64, vp, vp, ctypes.c_size_t, vp]
+    lib.mmlttb_minmax.argtypes = [ctypes.c_int, vp, vp, i64, i64, i32, vp, vp, vp, ctypes.c_size_t, vp]
+
+
+def test_workspace_size_does_not_depend_on_n(lib):
+    """Table 1: MinMaxLTTB keeps O(n_out) memory; the workspace never grows with n."""
+    _setup(lib)
+    for n_out, r_ps in [(1000, 4), (2000, 8), (4000, 4), (3, 2), (100, 3)]:
+        sizes = {lib.mmlttb_workspace_size(n, n_out, r_ps) for n in (10, 10 ** 6, 10 ** 9, 10 ** 12)}
+        assert len(sizes) == 1
+        s = sizes.pop()
+        assert 0 < s < 64 * n_out * r_ps + 4096
+        lt = {lib.mmlttb_lttb_workspace_size(n, n_out) for n in (10, 10 ** 6, 10 ** 9)}
+        assert len(lt) == 1
+
+
+def test_invalid_arguments_rejected_on_host(lib):
+    _setup(lib)
+    fake = ctypes.c_void_p(0x100000)  # never dereferenced: checks run first
+    ws = ctypes.c_void_p(0x200000)
+    cases = [
+        (0, None, fake, 0, 10, 4),        # n < 1
+        (0, None, fake, 100, 2, 4),       # n_out < 3
+        (0, None, fake, 100, 10, 1),      # r_ps < 2
+        (0, fake, fake, 100, 10, 4),      # x given with implicit x
+        (1, None, fake, 100, 10, 4),      # x missing with int64 x
+        (2, None, fake, 100, 10, 4),      # bad x kind
+        (0, None, None, 100, 10, 4),      # y NULL
+        (0, None, ctypes.c_void_p(0x100002), 100, 10, 4),  # misaligned y
+        (0, None, fake, 100, 2 ** 31, 4),  # n_out too large
+        (0, None, fake, 100, 2 ** 30, 4),  # too many bins
+    ]
+    for xk, x, y, n, n_out, r_ps in cases:
+        rc = lib.mmlttb_minmaxlttb(xk, x, y, n, n_out, r_ps, fake, ws, 1 << 30, None)
+        assert rc == -1, (xk, n, n_out, r_ps)
+        assert len(lib.mmlttb_last_error()) > 0
+    # workspace too small
+    rc = lib.mmlttb_minmaxlttb(0, None, fake, 10 ** 6, 1000, 4, fake, ws, 16, None)
+    assert rc == -2
+    assert b"workspace" in lib.mmlttb_last_error()
+    rc = lib.mmlttb_lttb(0, None, fake, 10 ** 6, 1000, fake, ws, 16, None)
+    assert rc == -2
+    rc = lib.mmlttb_minmax(0, None, fake, 10 ** 6, 1000, 4, fake, None, ws, 1 << 30, None)
+    assert rc == -1
+
+
+def test_oracle_shares_no_code_with_gpu_path():
+    """The oracle and the GPU library are independent: no source of one names the other."""
+    import glob
+
+    gpu_src = glob.glob(os.path.join(ROOT, "paper_2305_00332_amd", "**", "*.*"), recursive=True)
+    for f in gpu_src:
+        if f.endswith((".py", ".hip", ".hpp", ".cpp", ".h")):
+            text = open(f).read()
+            assert "oracle" not in text.lower() or f.endswith("synth.py"), f
+    for f in glob.glob(os.path.join(ROOT, "oracle", "*")):
+        if f.endswith((".py", ".c", ".h")):
+            text = open(f).read()
+            assert "paper_2305_00332_amd" not in text and "libmmlttb" not in text, f

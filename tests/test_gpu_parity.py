@@ -1,0 +1,173 @@
+"""GPU path == oracle, element by element (tolerance 0: indices are integers).
+
+Randomised small and medium shapes spanning several work items per bin and
+ragged tails, plus the edge cases of the method: tiny n, n_out at and around
+n, every point preselected, constant and tied series, signed zeros,
+subnormals, extreme magnitudes, epoch-nanosecond timestamps, misaligned
+series starts, and launch-geometry sweeps (results must not move)."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2305_00332_amd import ops, synth
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda"
+
+
+def _dev(y_np, offset=0):
+    """Device copy of y starting `offset` floats into its allocation (misaligned start)."""
+    buf = torch.empty(len(y_np) + offset, dtype=torch.float32, device=DEV)
+    buf[offset:] = torch.from_numpy(np.ascontiguousarray(y_np)).to(DEV)
+    return buf[offset:]
+
+
+def _devx(x_np):
+    return None if x_np is None else torch.from_numpy(np.ascontiguousarray(x_np)).to(DEV)
+
+
+KINDS = ["walk", "ties", "subnormal", "extreme", "composite", "constant"]
+
+
+def _series(kind, n, seed):
+    if kind == "walk":
+        return synth.to_numpy(synth.random_walk(n, seed))
+    if kind == "ties":
+        return synth.to_numpy(synth.ties_series(n, seed))
+    if kind == "subnormal":
+        return synth.to_numpy(synth.subnormal_series(n, seed))
+    if kind == "extreme":
+        return synth.to_numpy(synth.extreme_series(n, seed))
+    if kind == "composite":
+        return synth.to_numpy(synth.composite_series(n, seed, with_x=False)[1])
+    return np.full(n, -0.0 if seed % 2 else 3.5, dtype=np.float32)
+
+
+def _x_for(seed, n):
+    k = seed % 3
+    if k == 0:
+        return None
+    if k == 1:
+        return synth.to_numpy(synth.irregular_x(n, seed))
+    return synth.to_numpy(synth.epoch_x(n, seed))
+
+
+def _cases(count, seed0, nmax):
+    rng = np.random.default_rng(seed0)
+    out = []
+    for c in range(count):
+        n = int(np.exp(rng.uniform(0, np.log(nmax))))
+        n_out = int(rng.integers(3, max(4, min(n + 3, 3000))))
+        r_ps = int(rng.choice([2, 2, 3, 4, 4, 6, 8, 16]))
+        out.append((seed0 + c, KINDS[c % len(KINDS)], max(n, 1), n_out, r_ps, int(rng.integers(0, 4))))
+    return out
+
+
+def _check_minmax(y_np, n_out, r_ps, offset):
+    P, m = ops.minmax(_dev(y_np, offset), n_out, r_ps)
+    want = oracle.minmax(y_np, n_out, r_ps)
+    got = P.cpu().numpy()
+    assert m == len(want)
+    np.testing.assert_array_equal(got, want)
+
+
+def _check_mmlttb(y_np, n_out, r_ps, x_np, offset):
+    got = ops.minmaxlttb(_dev(y_np, offset), n_out, r_ps, x=_devx(x_np)).cpu().numpy()
+    want = oracle.minmaxlttb(y_np, n_out, r_ps, x_np)
+    np.testing.assert_array_equal(got, want)
+
+
+def _check_lttb(y_np, n_out, x_np, offset):
+    got = ops.lttb(_dev(y_np, offset), n_out, x=_devx(x_np)).cpu().numpy()
+    want = oracle.lttb(y_np, n_out, x_np)
+    np.testing.assert_array_equal(got, want)
+
+
+@pytest.mark.parametrize("case", _cases(120, 10_000, 200_000), ids=lambda c: f"s{c[0]}-{c[1]}-n{c[2]}-o{c[3]}-r{c[4]}-a{c[5]}")
+def test_minmax_random(case):
+    seed, kind, n, n_out, r_ps, off = case
+    _check_minmax(_series(kind, n, seed), n_out, r_ps, off)
+
+
+@pytest.mark.parametrize("case", _cases(120, 20_000, 200_000), ids=lambda c: f"s{c[0]}-{c[1]}-n{c[2]}-o{c[3]}-r{c[4]}-a{c[5]}")
+def test_minmaxlttb_random(case):
+    seed, kind, n, n_out, r_ps, off = case
+    _check_mmlttb(_series(kind, n, seed), n_out, r_ps, _x_for(seed, n), off)
+
+
+@pytest.mark.parametrize("case", _cases(60, 30_000, 100_000), ids=lambda c: f"s{c[0]}-{c[1]}-n{c[2]}-o{c[3]}-a{c[5]}")
+def test_lttb_random(case):
+    seed, kind, n, n_out, _r, off = case
+    _check_lttb(_series(kind, n, seed), n_out, _x_for(seed, n), off)
+
+
+EDGE = [
+    # (n, n_out, r_ps)
+    (1, 3, 2), (2, 3, 2), (3, 3, 2), (4, 3, 2), (5, 3, 2), (6, 3, 2), (5, 4, 2), (7, 5, 3),
+    (100, 99, 2), (100, 100, 2), (100, 101, 2), (100, 98, 2), (1000, 3, 2), (1000, 3, 200),
+    (10_001, 5000, 2), (10_000, 4999, 2), (4002, 1000, 4), (4003, 1000, 4), (4001, 1000, 4),
+    (65_537, 3, 2), (300_000, 7, 3), (1 << 20, 1000, 4), ((1 << 20) + 3, 1001, 5),
+]
+
+
+@pytest.mark.parametrize("n,n_out,r_ps", EDGE)
+@pytest.mark.parametrize("kind", ["walk", "ties", "constant", "subnormal"])
+def test_edge_shapes(n, n_out, r_ps, kind):
+    seed = n * 7 + n_out
+    y = _series(kind, n, seed)
+    x = _x_for(seed, n)
+    _check_minmax(y, n_out, r_ps, n % 4)
+    _check_mmlttb(y, n_out, r_ps, x, (n + 1) % 4)
+    if n <= 300_000:
+        _check_lttb(y, n_out, x, (n + 2) % 4)
+
+
+def test_signed_zero_and_planted_extremes():
+    n = 50_000
+    y = np.zeros(n, dtype=np.float32)
+    y[::3] = -0.0
+    y[777] = 5.0
+    y[778] = 5.0  # tie: 777 must win
+    y[40_000] = -7.0
+    y[40_001] = -7.0
+    for n_out, r_ps in [(10, 2), (100, 4), (1000, 8)]:
+        _check_minmax(y, n_out, r_ps, 1)
+        _check_mmlttb(y, n_out, r_ps, None, 2)
+
+
+@pytest.mark.parametrize("unroll,chunk", [(1, 256), (2, 512), (4, 1024), (4, 16384), (8, 2048), (8, 65536), (4, 1 << 22)])
+def test_results_do_not_depend_on_launch_geometry(unroll, chunk):
+    old = ops.get_tuning()
+    try:
+        ops.set_tuning(unroll, chunk)
+        for seed, n, n_out, r_ps in [(1, 2_000_003, 1000, 4), (2, 777_777, 97, 3), (3, 123_457, 4000, 8)]:
+            y = _series("ties" if seed == 2 else "walk", n, seed)
+            _check_minmax(y, n_out, r_ps, seed % 4)
+            _check_mmlttb(y, n_out, r_ps, None, 0)
+    finally:
+        ops.set_tuning(*old)
+
+
+def test_repeated_calls_identical():
+    y = _dev(_series("walk", 3_000_001, 9))
+    first = ops.minmaxlttb(y, 2000, 4).clone()
+    for _ in range(5):
+        assert torch.equal(ops.minmaxlttb(y, 2000, 4), first)
+
+
+def test_errors_on_gpu():
+    y = _dev(_series("walk", 1000, 1))
+    with pytest.raises(RuntimeError):
+        ops.minmaxlttb(y, 2, 4)
+    with pytest.raises(RuntimeError):
+        ops.minmaxlttb(y, 10, 1)
+    small = torch.empty(8, dtype=torch.uint8, device=DEV)
+    with pytest.raises(RuntimeError, match="workspace"):
+        ops.minmaxlttb(y, 100, 4, ws=small)
+    # a failed call leaves the next one unaffected
+    np.testing.assert_array_equal(ops.minmaxlttb(y, 100, 4).cpu().numpy(),
+                                  oracle.minmaxlttb(y.cpu().numpy(), 100, 4))

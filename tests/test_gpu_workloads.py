@@ -1,0 +1,68 @@
+"""Full-size workloads, GPU == oracle on every output index (tolerance 0).
+
+- one series of 1e6 points (random walk, implicit x), n_out=1000, r_ps=4,
+  MinMaxLTTB and whole-series LTTB;
+- one series of 1e8 points (random walk + 3 sinusoids + noise + spikes,
+  int64 irregular timestamps), n_out=2000, r_ps in {2, 4, 8}, plus
+  whole-series LTTB;
+- one series of 1e9 points (random walk, implicit x, 4 GB), n_out in
+  {1000, 4000}, r_ps=4 -- the launch configuration the benchmark times.
+Inputs are generated on the GPU from fixed seeds and copied to the host for
+the oracle."""
+from __future__ import annotations
+
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2305_00332_amd import ops, synth
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def test_one_million_points():
+    y = synth.random_walk(1_000_000, 1, device="cuda")
+    y_np = y.cpu().numpy()
+    got = ops.minmaxlttb(y, 1000, 4).cpu().numpy()
+    np.testing.assert_array_equal(got, oracle.minmaxlttb(y_np, 1000, 4))
+    P, m = ops.minmax(y, 1000, 4)
+    np.testing.assert_array_equal(P.cpu().numpy(), oracle.minmax(y_np, 1000, 4))
+    assert m == 4002
+    got_l = ops.lttb(y, 1000).cpu().numpy()
+    np.testing.assert_array_equal(got_l, oracle.lttb(y_np, 1000))
+
+
+def test_hundred_million_points_irregular_x():
+    _say("generating 1e8 composite series on the GPU")
+    x, y = synth.composite_series(100_000_000, 2, device="cuda")
+    y_np, x_np = y.cpu().numpy(), x.cpu().numpy()
+    for r_ps in (2, 4, 8):
+        _say(f"minmaxlttb n=1e8 n_out=2000 r_ps={r_ps}")
+        got = ops.minmaxlttb(y, 2000, r_ps, x=x).cpu().numpy()
+        np.testing.assert_array_equal(got, oracle.minmaxlttb(y_np, 2000, r_ps, x_np))
+    _say("lttb n=1e8 n_out=2000")
+    got_l = ops.lttb(y, 2000, x=x).cpu().numpy()
+    np.testing.assert_array_equal(got_l, oracle.lttb(y_np, 2000, x_np))
+
+
+def test_one_billion_points():
+    _say("generating 1e9 random walk on the GPU")
+    y = synth.random_walk(1_000_000_000, 3, device="cuda")
+    torch.cuda.synchronize()
+    y_np = y.cpu().numpy()
+    for n_out in (1000, 4000):
+        _say(f"minmaxlttb n=1e9 n_out={n_out} r_ps=4")
+        got = ops.minmaxlttb(y, n_out, 4).cpu().numpy()
+        np.testing.assert_array_equal(got, oracle.minmaxlttb(y_np, n_out, 4))
+    P, m = ops.minmax(y, 4000, 4)
+    np.testing.assert_array_equal(P.cpu().numpy(), oracle.minmax(y_np, 4000, 4))
+    del y
+    torch.cuda.empty_cache()
