@@ -107,7 +107,8 @@ def main():
     ops.profile_enable(False)
     ms_per_step = (t1 - t0) * 1e3 / args.steps
     kern = {}
-    for k in ("init_keys", "minmax_bin_reduce", "preselect_compact", "bucket_mean", "lttb_chain"):
+    for k in ("init_keys", "minmax_bin_reduce", "preselect_compact", "preselect_all", "bucket_mean",
+              "lttb_chain", "lttb_chain_seg"):
         tot, cnt = ops.profile_read(k)
         kern[k] = round(tot / cnt, 5) if cnt else None
     stable = bool(torch.equal(out, ref_out))

@@ -127,13 +127,16 @@ size_t mmlttb_batched_workspace_size(const mmlttb_segment_t *segs_host, int64_t 
 int mmlttb_minmaxlttb_batched(int xk, const int64_t *x_base, const float *y_base, const mmlttb_segment_t *segs_host,
                               int64_t n_segs, int64_t *out_idx_base, void *ws, size_t ws_bytes, void *stream);
 
-/* Launch-geometry tuning of the MinMax stream (never changes results):
- * unroll = 16-byte loads in flight per lane (1, 2, 4 or 8), chunk = points per
- * work item (rounded up to a multiple of 256*unroll). A value of 0 keeps the
- * current setting. Returns MMLTTB_EINVAL for other values. Not thread-safe
- * with concurrent calls. */
-int mmlttb_set_tuning(int unroll, int64_t chunk);
-int mmlttb_get_tuning(int *unroll, int64_t *chunk);
+/* Execution tuning (never changes results): unroll = 16-byte loads in flight
+ * per lane of the MinMax stream (1, 2, 4 or 8); chunk = points per MinMax work
+ * item (rounded up to a multiple of 256*unroll); chain = LTTB pass form:
+ * 1 sequential (one wave walks every bucket in order), 2 segmented (segments
+ * walked from every start point in parallel, then linked; used when buckets
+ * hold at most 64 points), 0 or unset = automatic (segmented when possible).
+ * A value of 0 keeps the current setting. Returns MMLTTB_EINVAL for other
+ * values. Process-wide; not thread-safe with concurrent calls. */
+int mmlttb_set_tuning(int unroll, int64_t chunk, int chain);
+int mmlttb_get_tuning(int *unroll, int64_t *chunk, int *chain);
 
 /* Kernel timing for measurement. When enabled, HIP events are recorded on the
  * caller's stream around every launch of the named kernels; mmlttb_profile_read

@@ -35,9 +35,12 @@ int ok()
 
 // ---------------------------------------------------------------- tuning
 
+enum ChainMode { kChainAuto = 0, kChainSequential = 1, kChainSegmented = 2 };
+
 struct Tuning {
     int unroll = 4;        // float4 loads per lane per batch in minmax_bin_reduce
     int64_t chunk = 16384; // points per minmax work item (multiple of 256 * unroll)
+    int chain = kChainAuto;
 };
 
 Tuning &tuning()
@@ -53,6 +56,11 @@ Tuning &tuning()
             long long c = atoll(e);
             if (c >= 256)
                 r.chunk = c;
+        }
+        if (const char *e = getenv("MMLTTB_CHAIN")) {
+            int c = atoi(e);
+            if (c >= 0 && c <= 2)
+                r.chain = c;
         }
         int64_t q = 256 * (int64_t)r.unroll;
         r.chunk = ((r.chunk + q - 1) / q) * q;
@@ -108,7 +116,7 @@ constexpr size_t kAlign = 256;
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 struct MmLayout {
-    size_t keys, m, P, XP, YP, MX, MY, total;
+    size_t keys, m, P, XP, YP, MX, MY, path, finals, start, counter, total;
 };
 
 MmLayout mm_layout(int64_t n_out, int32_t r_ps)
@@ -130,21 +138,35 @@ MmLayout mm_layout(int64_t n_out, int32_t r_ps)
     L.YP = take(4 * (size_t)cap);
     L.MX = take(8 * (size_t)B);
     L.MY = take(8 * (size_t)B);
+    L.path = take(seg_path_bytes(B));
+    L.finals = take(seg_finals_bytes(B));
+    L.start = take((size_t)seg_count(B));
+    L.counter = take(sizeof(unsigned int));
     L.total = off;
     return L;
 }
 
 struct LtLayout {
-    size_t MX, MY, total;
+    size_t MX, MY, path, finals, start, counter, total;
 };
 
 LtLayout lt_layout(int64_t n_out)
 {
     const int64_t B = n_out - 2;
     LtLayout L;
-    L.MX = 0;
-    L.MY = align_up(8 * (size_t)B);
-    L.total = L.MY + align_up(8 * (size_t)B);
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t o = off;
+        off = align_up(off + bytes);
+        return o;
+    };
+    L.MX = take(8 * (size_t)B);
+    L.MY = take(8 * (size_t)B);
+    L.path = take(seg_path_bytes(B));
+    L.finals = take(seg_finals_bytes(B));
+    L.start = take((size_t)seg_count(B));
+    L.counter = take(sizeof(unsigned int));
+    L.total = off;
     return L;
 }
 
@@ -214,6 +236,33 @@ MinMaxGeom minmax_geom(int64_t n, int64_t nb)
         g.chunks_per_bin = 1;
     g.n_items = nb * g.chunks_per_bin;
     return g;
+}
+
+bool use_segmented_chain(int64_t maxb_bound)
+{
+    const int mode = tuning().chain;
+    return mode != kChainSequential && maxb_bound <= kSegStarts;
+}
+
+SegChainArgs seg_args(void *ws, size_t path, size_t finals, size_t start, size_t counter, const int64_t *XP,
+                      const float *YP, const int64_t *m_ptr, int64_t m_const, int64_t B, const double *MX,
+                      const double *MY, int64_t maxb_bound)
+{
+    SegChainArgs a;
+    a.XP = XP;
+    a.YP = YP;
+    a.m_ptr = m_ptr;
+    a.m_const = m_const;
+    a.B = B;
+    a.MX = MX;
+    a.MY = MY;
+    a.path = at<uint8_t>(ws, path);
+    a.finals = at<uint8_t>(ws, finals);
+    a.start = at<uint8_t>(ws, start);
+    a.counter = at<unsigned int>(ws, counter);
+    a.S = seg_count(B);
+    a.stage_cap = (int)(kSegLen * maxb_bound);
+    return a;
 }
 
 // Preselection into P (and, when XP != NULL, the gathered XP/YP); m to *m_out.
@@ -311,12 +360,16 @@ int mmlttb_lttb(int xk, const int64_t *x, const float *y, int64_t n, int64_t n_o
     double *MX = at<double>(ws, L.MX), *MY = at<double>(ws, L.MY);
     const Split bk = make_split(n - 2, B);
     const int64_t maxb = bk.q + (bk.r ? 1 : 0);
+    unsigned int *counter = at<unsigned int>(ws, L.counter);
     if (maxb <= 64) {
-        MMLTTB_LAUNCH("bucket_mean", s, launch_bucket_mean_small(x, y, nullptr, n, B, MX, MY, s));
+        MMLTTB_LAUNCH("bucket_mean", s, launch_bucket_mean_small(x, y, nullptr, n, B, MX, MY, counter, s));
     } else {
-        MMLTTB_LAUNCH("bucket_mean_wide", s, launch_bucket_mean_wide(x, y, n, B, MX, MY, s));
+        MMLTTB_LAUNCH("bucket_mean_wide", s, launch_bucket_mean_wide(x, y, n, B, MX, MY, counter, s));
     }
-    if (maxb <= kChainStage) {
+    if (use_segmented_chain(maxb)) {
+        const SegChainArgs a = seg_args(ws, L.path, L.finals, L.start, L.counter, x, y, nullptr, n, B, MX, MY, maxb);
+        MMLTTB_LAUNCH("lttb_chain_seg", s, launch_lttb_chain_seg(a, nullptr, out_idx, s));
+    } else if (maxb <= kChainStage) {
         MMLTTB_LAUNCH("lttb_chain", s, launch_lttb_chain(x, y, nullptr, n, B, MX, MY, nullptr, out_idx, s));
     } else {
         MMLTTB_LAUNCH("lttb_chain_wide", s, launch_lttb_chain_wide(x, y, n, B, MX, MY, out_idx, s));
@@ -351,8 +404,17 @@ int mmlttb_minmaxlttb(int xk, const int64_t *x, const float *y, int64_t n, int64
     if (rc)
         return rc;
     const int64_t B = n_out - 2;
-    MMLTTB_LAUNCH("bucket_mean", s, launch_bucket_mean_small(XP, YP, m, 0, B, MX, MY, s));
-    MMLTTB_LAUNCH("lttb_chain", s, launch_lttb_chain(XP, YP, m, 0, B, MX, MY, P, out_idx, s));
+    unsigned int *counter = at<unsigned int>(ws, L.counter);
+    MMLTTB_LAUNCH("bucket_mean", s, launch_bucket_mean_small(XP, YP, m, 0, B, MX, MY, counter, s));
+    // preselected points per bucket: at most ceil((m-2)/B) with m - 2 <= 2*nb
+    const int64_t nb = n_out * (int64_t)r_ps / 2;
+    const int64_t maxb_bound = (2 * nb + B - 1) / B;
+    if (use_segmented_chain(maxb_bound)) {
+        const SegChainArgs a = seg_args(ws, L.path, L.finals, L.start, L.counter, XP, YP, m, 0, B, MX, MY, maxb_bound);
+        MMLTTB_LAUNCH("lttb_chain_seg", s, launch_lttb_chain_seg(a, P, out_idx, s));
+    } else {
+        MMLTTB_LAUNCH("lttb_chain", s, launch_lttb_chain(XP, YP, m, 0, B, MX, MY, P, out_idx, s));
+    }
     return ok();
 }
 
@@ -378,28 +440,33 @@ int mmlttb_minmaxlttb_batched(int xk, const int64_t *x_base, const float *y_base
     return fail(MMLTTB_ENOTSUP, "batched mode is not built yet");
 }
 
-int mmlttb_set_tuning(int unroll, int64_t chunk)
+int mmlttb_set_tuning(int unroll, int64_t chunk, int chain)
 {
     Tuning &t = tuning();
     if (unroll != 0 && unroll != 1 && unroll != 2 && unroll != 4 && unroll != 8)
         return fail(MMLTTB_EINVAL, "unroll must be 1, 2, 4 or 8");
     if (chunk != 0 && chunk < 256)
         return fail(MMLTTB_EINVAL, "chunk must be >= 256");
+    if (chain < 0 || chain > 2)
+        return fail(MMLTTB_EINVAL, "chain must be 0 (auto), 1 (sequential) or 2 (segmented)");
     if (unroll)
         t.unroll = unroll;
     if (chunk)
         t.chunk = chunk;
+    if (chain)
+        t.chain = chain;
     const int64_t q = 256 * (int64_t)t.unroll;
     t.chunk = ((t.chunk + q - 1) / q) * q;
     return ok();
 }
 
-int mmlttb_get_tuning(int *unroll, int64_t *chunk)
+int mmlttb_get_tuning(int *unroll, int64_t *chunk, int *chain)
 {
-    if (!unroll || !chunk)
+    if (!unroll || !chunk || !chain)
         return fail(MMLTTB_EINVAL, "NULL argument");
     *unroll = tuning().unroll;
     *chunk = tuning().chunk;
+    *chain = tuning().chain;
     return ok();
 }
 

@@ -21,6 +21,32 @@ struct MinMaxGeom {
 // LDS window of the sequential chain, in points.
 constexpr int kChainStage = 1024;
 
+// Segmented chain: buckets per segment, start points per segment (one lane
+// each, so buckets may hold at most this many points), segments per LDS
+// window while the last block links the segments.
+constexpr int kSegLen = 32;
+constexpr int kSegStarts = 64;
+constexpr int kChaseWindow = 256;
+
+struct SegChainArgs {
+    const int64_t *XP;     // raw x of the points (NULL: x = position)
+    const float *YP;       // y of the points
+    const int64_t *m_ptr;  // device point count (NULL: m_const)
+    int64_t m_const;
+    int64_t B;             // interior buckets
+    const double *MX, *MY; // next-bucket means
+    uint8_t *path;         // [S][kSegStarts][kSegLen]: pick offset inside its bucket
+    uint8_t *finals;       // [S][kSegStarts]: pick offset in the segment's last bucket
+    uint8_t *start;        // [S]: start lane of segment s on the chain from point 0
+    unsigned int *counter; // zeroed by the means kernel before the chain runs
+    int64_t S;             // segments
+    int stage_cap;         // LDS points per segment (kSegLen * bucket-size bound)
+};
+
+inline int64_t seg_count(int64_t B) { return (B + kSegLen - 1) / kSegLen; }
+inline size_t seg_path_bytes(int64_t B) { return (size_t)seg_count(B) * kSegStarts * kSegLen; }
+inline size_t seg_finals_bytes(int64_t B) { return (size_t)seg_count(B) * kSegStarts; }
+
 hipError_t launch_init_keys(unsigned long long *keys, int64_t nb, hipStream_t s);
 hipError_t launch_minmax_bin_reduce(const float *y, const MinMaxGeom &g, int unroll, unsigned long long *keys,
                                     hipStream_t s);
@@ -31,11 +57,12 @@ hipError_t launch_preselect_all(int64_t n, const int64_t *x, const float *y, int
 hipError_t launch_iota(int64_t *out, int64_t n, int64_t *count_out, hipStream_t s);
 
 hipError_t launch_bucket_mean_small(const int64_t *XP, const float *YP, const int64_t *m_ptr, int64_t m_const,
-                                    int64_t B, double *MX, double *MY, hipStream_t s);
+                                    int64_t B, double *MX, double *MY, unsigned int *zero_counter, hipStream_t s);
 hipError_t launch_bucket_mean_wide(const int64_t *X, const float *Y, int64_t m, int64_t B, double *MX, double *MY,
-                                   hipStream_t s);
+                                   unsigned int *zero_counter, hipStream_t s);
 hipError_t launch_lttb_chain(const int64_t *XP, const float *YP, const int64_t *m_ptr, int64_t m_const, int64_t B,
                              const double *MX, const double *MY, const int64_t *Pmap, int64_t *out, hipStream_t s);
+hipError_t launch_lttb_chain_seg(const SegChainArgs &a, const int64_t *Pmap, int64_t *out, hipStream_t s);
 hipError_t launch_lttb_chain_wide(const int64_t *X, const float *Y, int64_t m, int64_t B, const double *MX,
                                   const double *MY, int64_t *out, hipStream_t s);
 

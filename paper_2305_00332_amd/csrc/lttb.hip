@@ -63,9 +63,11 @@ __device__ inline void next_bucket_range(const Split &bk, int64_t m, int64_t k, 
 __global__ __launch_bounds__(256) void k_bucket_mean_small(const int64_t *__restrict__ XP, const float *__restrict__ YP,
                                                            const int64_t *__restrict__ m_ptr, int64_t m_const,
                                                            int64_t B, double *__restrict__ MX,
-                                                           double *__restrict__ MY)
+                                                           double *__restrict__ MY, unsigned int *zero_counter)
 {
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k == 0 && zero_counter)
+        *zero_counter = 0u;
     if (k >= B)
         return;
     const int64_t m = m_ptr ? *m_ptr : m_const;
@@ -88,9 +90,11 @@ __global__ __launch_bounds__(256) void k_bucket_mean_small(const int64_t *__rest
 // One workgroup (256 threads) per bucket (whole-series LTTB: large buckets).
 __global__ __launch_bounds__(256) void k_bucket_mean_wide(const int64_t *__restrict__ X, const float *__restrict__ Y,
                                                           int64_t m, int64_t B, double *__restrict__ MX,
-                                                          double *__restrict__ MY)
+                                                          double *__restrict__ MY, unsigned int *zero_counter)
 {
     __shared__ int64_t s_limb[4][9];
+    if (blockIdx.x == 0 && threadIdx.x == 0 && zero_counter)
+        *zero_counter = 0u;
     __shared__ int64_t s_xlo[4], s_xhi[4];
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     const Split bk = make_split(m - 2, B);
@@ -272,6 +276,124 @@ __global__ __launch_bounds__(256) void k_lttb_chain(const int64_t *__restrict__ 
     }
 }
 
+// Segmented chain (same picks as k_lttb_chain, in O(B / kSegLen + kSegLen)
+// dependent steps instead of B). Buckets are cut into segments of kSegLen.
+// Phase 1, one wave per segment: a segment's walk depends only on its start
+// point, which lies in the bucket just before the segment (point 0 for the
+// first segment); lane l walks the segment from start candidate l, with the
+// segment's points and means staged in LDS, and records each pick's offset
+// inside its bucket. Every walk evaluates the same binary64 area on the same
+// operands as the sequential pass, so a walk from the true start repeats the
+// sequential picks exactly. Phase 2, by the last block to finish (counted
+// with one atomic, no waiting): follow the true start through the segments
+// (start of segment s+1 = last pick of segment s from its start), one LDS
+// lookup per segment. k_lttb_chain_emit then writes every pick in parallel.
+__global__ __launch_bounds__(kSegStarts) void k_lttb_chain_seg(SegChainArgs a)
+{
+    extern __shared__ double lds[];
+    __shared__ uint8_t F[kChaseWindow * kSegStarts];
+    __shared__ unsigned int s_ticket;
+    const int lane = threadIdx.x;
+    const int64_t s = blockIdx.x;
+    const int64_t m = a.m_ptr ? *a.m_ptr : a.m_const;
+    const int64_t B = a.B;
+    const Split bk = make_split(m - 2, B);
+    const int64_t k0 = s * kSegLen, k1 = (k0 + kSegLen < B) ? k0 + kSegLen : B;
+    const int64_t p0 = 1 + split_lo(bk, k0), p1 = 1 + split_lo(bk, k1);
+    double *sx = lds, *sy = lds + a.stage_cap, *smx = lds + 2 * a.stage_cap, *smy = smx + kSegLen;
+    for (int64_t p = p0 + lane; p < p1; p += kSegStarts) {
+        sx[p - p0] = (double)(a.XP ? a.XP[p] : p);
+        sy[p - p0] = (double)a.YP[p];
+    }
+    for (int64_t k = k0 + lane; k < k1; k += kSegStarts) {
+        smx[k - k0] = a.MX[k];
+        smy[k - k0] = a.MY[k];
+    }
+    __syncthreads();
+
+    int64_t apos = 0;
+    if (s > 0) {
+        const int64_t sa = 1 + split_lo(bk, k0 - 1);
+        const int64_t ca = p0 - sa; // points of the bucket before the segment (<= kSegStarts)
+        apos = sa + (lane < ca ? lane : ca - 1);
+    }
+    double ax = (double)(a.XP ? a.XP[apos] : apos);
+    double ay = (double)a.YP[apos];
+    SplitWalker w;
+    w.init(bk, k0);
+    uint8_t *mypath = a.path + ((size_t)s * kSegStarts + lane) * kSegLen;
+    int bo = 0;
+    for (int64_t k = k0; k < k1; ++k) {
+        const int64_t s0 = 1 + w.lo, s1 = 1 + w.next_lo(bk);
+        w.advance(bk);
+        const double mx = smx[k - k0], my = smy[k - k0];
+        double best = -1.0, bx = ax, by = ay;
+        bo = 0;
+        for (int64_t j = s0; j < s1; ++j) {
+            const double xj = sx[j - p0], yj = sy[j - p0];
+            const double ar = lttb_area2(ax, ay, xj, yj, mx, my);
+            if (ar > best) { // strict: lowest position wins ties
+                best = ar;
+                bo = (int)(j - s0);
+                bx = xj;
+                by = yj;
+            }
+        }
+        ax = bx;
+        ay = by;
+        mypath[k - k0] = (uint8_t)bo;
+    }
+    a.finals[(size_t)s * kSegStarts + lane] = (uint8_t)bo;
+
+    __threadfence();
+    __syncthreads();
+    if (lane == 0)
+        s_ticket = atomicAdd(a.counter, 1u);
+    __syncthreads();
+    if (s_ticket != (unsigned int)(a.S - 1))
+        return;
+    __threadfence();
+    int cur = 0;
+    if (lane == 0)
+        a.start[0] = 0;
+    for (int64_t w0 = 0; w0 < a.S - 1; w0 += kChaseWindow) {
+        const int64_t w1 = (w0 + kChaseWindow < a.S - 1) ? w0 + kChaseWindow : a.S - 1;
+        const int64_t words = (w1 - w0) * kSegStarts / 4;
+        const uint32_t *src = reinterpret_cast<const uint32_t *>(a.finals + w0 * kSegStarts);
+        for (int64_t q = lane; q < words; q += kSegStarts)
+            reinterpret_cast<uint32_t *>(F)[q] = src[q];
+        __syncthreads();
+        if (lane == 0) {
+            for (int64_t t = w0; t < w1; ++t) {
+                cur = F[(t - w0) * kSegStarts + cur];
+                a.start[t + 1] = (uint8_t)cur;
+            }
+        }
+        __syncthreads();
+    }
+    if (lane == 0)
+        *a.counter = 0u;
+}
+
+__global__ __launch_bounds__(256) void k_lttb_chain_emit(SegChainArgs a, const int64_t *__restrict__ Pmap,
+                                                         int64_t *__restrict__ out)
+{
+    const int64_t m = a.m_ptr ? *a.m_ptr : a.m_const;
+    const Split bk = make_split(m - 2, a.B);
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < a.B; k += stride) {
+        const int64_t s = k / kSegLen;
+        const int l = a.start[s];
+        const int off = a.path[((size_t)s * kSegStarts + l) * kSegLen + (k - s * kSegLen)];
+        const int64_t sel = 1 + split_lo(bk, k) + off;
+        out[k + 1] = Pmap ? Pmap[sel] : sel;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        out[0] = Pmap ? Pmap[0] : 0;
+        out[a.B + 1] = Pmap ? Pmap[m - 1] : m - 1;
+    }
+}
+
 // Whole-series chain for wide buckets: one workgroup of 1024 threads computes
 // each bucket's areas together; per-wave winners meet in LDS.
 __global__ __launch_bounds__(1024) void k_lttb_chain_wide(const int64_t *__restrict__ X, const float *__restrict__ Y,
@@ -372,17 +494,31 @@ hipError_t launch_preselect_all(int64_t n, const int64_t *x, const float *y, int
 }
 
 hipError_t launch_bucket_mean_small(const int64_t *XP, const float *YP, const int64_t *m_ptr, int64_t m_const,
-                                    int64_t B, double *MX, double *MY, hipStream_t s)
+                                    int64_t B, double *MX, double *MY, unsigned int *zero_counter, hipStream_t s)
 {
     hipLaunchKernelGGL(k_bucket_mean_small, dim3(grid_for(B, 256, 1 << 30)), dim3(256), 0, s, XP, YP, m_ptr, m_const,
-                       B, MX, MY);
+                       B, MX, MY, zero_counter);
     return hipGetLastError();
 }
 
 hipError_t launch_bucket_mean_wide(const int64_t *X, const float *Y, int64_t m, int64_t B, double *MX, double *MY,
-                                   hipStream_t s)
+                                   unsigned int *zero_counter, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_bucket_mean_wide, dim3(grid_for(B, 1, 65536)), dim3(256), 0, s, X, Y, m, B, MX, MY);
+    hipLaunchKernelGGL(k_bucket_mean_wide, dim3(grid_for(B, 1, 65536)), dim3(256), 0, s, X, Y, m, B, MX, MY,
+                       zero_counter);
+    return hipGetLastError();
+}
+
+hipError_t launch_lttb_chain_seg(const SegChainArgs &a, const int64_t *Pmap, int64_t *out, hipStream_t s)
+{
+    if (a.S > 0x7fffffff)
+        return hipErrorInvalidConfiguration;
+    const size_t lds = (size_t)(2 * a.stage_cap + 2 * kSegLen) * sizeof(double);
+    hipLaunchKernelGGL(k_lttb_chain_seg, dim3((unsigned)a.S), dim3(kSegStarts), lds, s, a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        return e;
+    hipLaunchKernelGGL(k_lttb_chain_emit, dim3(grid_for(a.B, 256, 65536)), dim3(256), 0, s, a, Pmap, out);
     return hipGetLastError();
 }
 

@@ -86,18 +86,25 @@ def minmaxlttb(y, n_out: int, r_ps: int, x=None, out=None, ws=None):
     return out[: min(n, n_out)]
 
 
-def set_tuning(unroll: int = 0, chunk: int = 0):
-    """Launch geometry of the MinMax stream (results never depend on it)."""
-    _lib.check(_lib.load().mmlttb_set_tuning(unroll, chunk))
+CHAIN_AUTO, CHAIN_SEQUENTIAL, CHAIN_SEGMENTED = 0, 1, 2
+
+
+def set_tuning(unroll: int = 0, chunk: int = 0, chain: int = 0):
+    """Execution tuning (results never depend on it): MinMax loads in flight per
+    lane, points per MinMax work item, LTTB pass form (1 sequential, 2 segmented).
+    Zero keeps the current value."""
+    _lib.check(_lib.load().mmlttb_set_tuning(unroll, chunk, chain))
 
 
 def get_tuning():
+    """(unroll, chunk, chain)"""
     import ctypes
 
     u = ctypes.c_int(0)
     c = ctypes.c_int64(0)
-    _lib.check(_lib.load().mmlttb_get_tuning(ctypes.byref(u), ctypes.byref(c)))
-    return u.value, c.value
+    ch = ctypes.c_int(0)
+    _lib.check(_lib.load().mmlttb_get_tuning(ctypes.byref(u), ctypes.byref(c), ctypes.byref(ch)))
+    return u.value, c.value, ch.value
 
 
 def profile_enable(on: bool = True):

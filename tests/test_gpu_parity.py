@@ -30,6 +30,15 @@ def _devx(x_np):
     return None if x_np is None else torch.from_numpy(np.ascontiguousarray(x_np)).to(DEV)
 
 
+@pytest.fixture(params=[ops.CHAIN_SEQUENTIAL, ops.CHAIN_SEGMENTED], ids=["seqchain", "segchain"])
+def chain_mode(request):
+    """Both forms of the LTTB pass must give the oracle's picks."""
+    old = ops.get_tuning()
+    ops.set_tuning(0, 0, request.param)
+    yield request.param
+    ops.set_tuning(*old)
+
+
 KINDS = ["walk", "ties", "subnormal", "extreme", "composite", "constant"]
 
 
@@ -94,13 +103,13 @@ def test_minmax_random(case):
 
 
 @pytest.mark.parametrize("case", _cases(120, 20_000, 200_000), ids=lambda c: f"s{c[0]}-{c[1]}-n{c[2]}-o{c[3]}-r{c[4]}-a{c[5]}")
-def test_minmaxlttb_random(case):
+def test_minmaxlttb_random(case, chain_mode):
     seed, kind, n, n_out, r_ps, off = case
     _check_mmlttb(_series(kind, n, seed), n_out, r_ps, _x_for(seed, n), off)
 
 
 @pytest.mark.parametrize("case", _cases(60, 30_000, 100_000), ids=lambda c: f"s{c[0]}-{c[1]}-n{c[2]}-o{c[3]}-a{c[5]}")
-def test_lttb_random(case):
+def test_lttb_random(case, chain_mode):
     seed, kind, n, n_out, _r, off = case
     _check_lttb(_series(kind, n, seed), n_out, _x_for(seed, n), off)
 
@@ -116,7 +125,7 @@ EDGE = [
 
 @pytest.mark.parametrize("n,n_out,r_ps", EDGE)
 @pytest.mark.parametrize("kind", ["walk", "ties", "constant", "subnormal"])
-def test_edge_shapes(n, n_out, r_ps, kind):
+def test_edge_shapes(n, n_out, r_ps, kind, chain_mode):
     seed = n * 7 + n_out
     y = _series(kind, n, seed)
     x = _x_for(seed, n)
@@ -126,7 +135,7 @@ def test_edge_shapes(n, n_out, r_ps, kind):
         _check_lttb(y, n_out, x, (n + 2) % 4)
 
 
-def test_signed_zero_and_planted_extremes():
+def test_signed_zero_and_planted_extremes(chain_mode):
     n = 50_000
     y = np.zeros(n, dtype=np.float32)
     y[::3] = -0.0

@@ -28,7 +28,15 @@ def _say(msg):
     sys.stdout.flush()
 
 
-def test_one_million_points():
+@pytest.fixture(params=[ops.CHAIN_SEQUENTIAL, ops.CHAIN_SEGMENTED], ids=["seqchain", "segchain"])
+def chain_mode(request):
+    old = ops.get_tuning()
+    ops.set_tuning(0, 0, request.param)
+    yield request.param
+    ops.set_tuning(*old)
+
+
+def test_one_million_points(chain_mode):
     y = synth.random_walk(1_000_000, 1, device="cuda")
     y_np = y.cpu().numpy()
     got = ops.minmaxlttb(y, 1000, 4).cpu().numpy()
@@ -40,7 +48,7 @@ def test_one_million_points():
     np.testing.assert_array_equal(got_l, oracle.lttb(y_np, 1000))
 
 
-def test_hundred_million_points_irregular_x():
+def test_hundred_million_points_irregular_x(chain_mode):
     _say("generating 1e8 composite series on the GPU")
     x, y = synth.composite_series(100_000_000, 2, device="cuda")
     y_np, x_np = y.cpu().numpy(), x.cpu().numpy()
@@ -53,7 +61,7 @@ def test_hundred_million_points_irregular_x():
     np.testing.assert_array_equal(got_l, oracle.lttb(y_np, 2000, x_np))
 
 
-def test_one_billion_points():
+def test_one_billion_points(chain_mode):
     _say("generating 1e9 random walk on the GPU")
     y = synth.random_walk(1_000_000_000, 3, device="cuda")
     torch.cuda.synchronize()
