@@ -7,7 +7,10 @@ the package does not load the library; the first call does, and raises if the
 library is not built.
 """
 from .ops import (  # noqa: F401
+    batched_workspace_size,
     lttb,
+    minmaxlttb_batched,
+    segment_table,
     lttb_workspace_size,
     minmax,
     minmaxlttb,

@@ -2,6 +2,7 @@
 #include <stdarg.h>
 #include <stdio.h>
 #include <stdlib.h>
+#include <string.h>
 
 #include <map>
 #include <string>
@@ -287,6 +288,129 @@ int enqueue_preselect(const int64_t *x, const float *y, int64_t n, int64_t n_out
     return MMLTTB_OK;
 }
 
+// ---------------------------------------------------------------- batch plan
+
+struct BatchPlan {
+    BatchHeader h;
+    std::vector<BatchSeg> segs;
+    size_t total = 0;
+    bool any_seq = false;
+};
+
+// Validate every segment and lay the batch out in the workspace. The layout
+// depends on n_out, r_ps and the segment count only (not on lengths).
+int plan_batch(int xk, const mmlttb_segment_t *in, int64_t n_segs, BatchPlan &plan)
+{
+    (void)xk;
+    if (n_segs < 1)
+        return fail(MMLTTB_EINVAL, "n_segs must be >= 1");
+    if (!in)
+        return fail(MMLTTB_EINVAL, "segs_host must not be NULL");
+    const Tuning &tn = tuning();
+    plan.segs.resize((size_t)n_segs);
+    int64_t keys = 0, pslots = 0, bslots = 0, cslots = 0, large = 0, tiles = 0, cw = 0, max_stage = 0;
+    for (int64_t i = 0; i < n_segs; ++i) {
+        const mmlttb_segment_t &q = in[i];
+        BatchSeg &g = plan.segs[(size_t)i];
+        memset(&g, 0, sizeof(g));
+        if (q.reserved != 0)
+            return fail(MMLTTB_EINVAL, "segment %lld: reserved must be 0", (long long)i);
+        if (q.offset < 0 || q.out_offset < 0)
+            return fail(MMLTTB_EINVAL, "segment %lld: negative offset", (long long)i);
+        if (q.n < 1 || q.n > kMaxN)
+            return fail(MMLTTB_EINVAL, "segment %lld: n must be in [1, 2^62], got %lld", (long long)i, (long long)q.n);
+        if (q.n_out < 3 || q.n_out > kMaxI32)
+            return fail(MMLTTB_EINVAL, "segment %lld: n_out must be in [3, 2^31-1], got %lld", (long long)i,
+                        (long long)q.n_out);
+        int rc = check_rps(q.n, q.n_out, q.r_ps);
+        if (rc) {
+            std::string m = g_err;
+            return fail(rc, "segment %lld: %s", (long long)i, m.c_str());
+        }
+        const int64_t nb = q.n_out * (int64_t)q.r_ps / 2;
+        const int64_t B = q.n_out - 2;
+        const int64_t S = seg_count(B);
+        g.offset = q.offset;
+        g.n = q.n;
+        g.n_out = q.n_out;
+        g.out_offset = q.out_offset;
+        g.r_ps = q.r_ps;
+        g.key0 = keys;
+        keys += nb;
+        g.p0 = pslots;
+        pslots += 2 * nb + 2;
+        g.B = B;
+        g.b0 = bslots;
+        bslots += B;
+        g.c0 = cslots;
+        cslots += S;
+        g.mode = q.n <= q.n_out ? kSegIdentity : (nb >= q.n - 2 ? kSegAll : kSegMinMax);
+        const int64_t maxb_bound = (2 * nb + B - 1) / B;
+        g.seq = (tn.chain == kChainSequential || maxb_bound > kSegStarts) ? 1 : 0;
+        g.cw0 = cw;
+        g.cwn = 0;
+        if (g.mode != kSegIdentity) {
+            if (g.seq) {
+                plan.any_seq = true;
+            } else {
+                g.cwn = S;
+                cw += S;
+                g.stage_cap = (int32_t)(kSegLen * maxb_bound);
+                max_stage = g.stage_cap > max_stage ? g.stage_cap : max_stage;
+            }
+        }
+        g.li0 = large;
+        g.ti0 = tiles;
+        if (g.mode == kSegMinMax) {
+            g.bins = make_split(q.n - 2, nb);
+            const int64_t maxbin = g.bins.q + (g.bins.r ? 1 : 0);
+            if (maxbin <= kSmallBinMax) {
+                int64_t G = 256;
+                while (G * maxbin > kTilePoints)
+                    G >>= 1;
+                g.small = 1;
+                g.tile_bins = (int32_t)G;
+                g.tn = (nb + G - 1) / G;
+                tiles += g.tn;
+            } else {
+                g.chunk = tn.chunk;
+                g.chunks_per_bin = (maxbin + g.chunk - 1) / g.chunk;
+                g.ln = nb * g.chunks_per_bin;
+                large += g.ln;
+            }
+        }
+    }
+    BatchHeader &h = plan.h;
+    memset(&h, 0, sizeof(h));
+    h.n_segs = n_segs;
+    h.n_keys = keys;
+    h.n_large_items = large;
+    h.n_small_tiles = tiles;
+    h.n_chain_units = cw;
+    h.max_stage_cap = max_stage;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t o = off;
+        off = align_up(off + bytes);
+        return (int64_t)o;
+    };
+    take(sizeof(BatchHeader));
+    h.off_segs = take((size_t)n_segs * sizeof(BatchSeg));
+    h.off_keys = take(16 * (size_t)keys);
+    h.off_P = take(8 * (size_t)pslots);
+    h.off_XP = take(8 * (size_t)pslots);
+    h.off_YP = take(4 * (size_t)pslots);
+    h.off_m = take(8 * (size_t)n_segs);
+    h.off_MX = take(8 * (size_t)bslots);
+    h.off_MY = take(8 * (size_t)bslots);
+    h.off_path = take((size_t)cslots * kSegStarts * kSegLen);
+    h.off_finals = take((size_t)cslots * kSegStarts);
+    h.off_start = take((size_t)cslots);
+    h.off_counter = take(4 * (size_t)n_segs);
+    plan.total = off;
+    return MMLTTB_OK;
+}
+
 } // namespace
 
 extern "C" {
@@ -420,24 +544,76 @@ int mmlttb_minmaxlttb(int xk, const int64_t *x, const float *y, int64_t n, int64
 
 size_t mmlttb_batched_workspace_size(const mmlttb_segment_t *segs_host, int64_t n_segs)
 {
-    (void)segs_host;
-    (void)n_segs;
-    return 0;
+    BatchPlan plan;
+    if (plan_batch(MMLTTB_X_IMPLICIT, segs_host, n_segs, plan) != MMLTTB_OK)
+        return 0;
+    return plan.total;
 }
 
 int mmlttb_minmaxlttb_batched(int xk, const int64_t *x_base, const float *y_base, const mmlttb_segment_t *segs_host,
                               int64_t n_segs, int64_t *out_idx_base, void *ws, size_t ws_bytes, void *stream)
 {
-    (void)xk;
-    (void)x_base;
-    (void)y_base;
-    (void)segs_host;
-    (void)n_segs;
-    (void)out_idx_base;
-    (void)ws;
-    (void)ws_bytes;
-    (void)stream;
-    return fail(MMLTTB_ENOTSUP, "batched mode is not built yet");
+    if (xk != MMLTTB_X_IMPLICIT && xk != MMLTTB_X_INT64)
+        return fail(MMLTTB_EINVAL, "xk must be MMLTTB_X_IMPLICIT (0) or MMLTTB_X_INT64 (1), got %d", xk);
+    if (xk == MMLTTB_X_IMPLICIT && x_base)
+        return fail(MMLTTB_EINVAL, "x_base must be NULL with MMLTTB_X_IMPLICIT");
+    if (xk == MMLTTB_X_INT64 && !x_base)
+        return fail(MMLTTB_EINVAL, "x_base must not be NULL with MMLTTB_X_INT64");
+    if (!y_base || !out_idx_base)
+        return fail(MMLTTB_EINVAL, "y_base and out_idx_base must not be NULL");
+    if (((uintptr_t)y_base & 3u) || ((uintptr_t)x_base & 7u) || ((uintptr_t)out_idx_base & 7u))
+        return fail(MMLTTB_EINVAL, "y_base must be 4-byte, x_base and out_idx_base 8-byte aligned");
+    BatchPlan plan;
+    int rc = plan_batch(xk, segs_host, n_segs, plan);
+    if (rc)
+        return rc;
+    if (!ws)
+        return fail(MMLTTB_EINVAL, "ws must not be NULL");
+    if (ws_bytes < plan.total)
+        return fail(MMLTTB_ENOMEM, "workspace of %zu bytes is below the %zu required", ws_bytes, plan.total);
+    hipStream_t s = (hipStream_t)stream;
+    const BatchHeader &h = plan.h;
+    // header + segment table, copied before this call returns
+    std::vector<char> staging(h.off_keys);
+    memcpy(staging.data(), &h, sizeof(h));
+    memcpy(staging.data() + h.off_segs, plan.segs.data(), plan.segs.size() * sizeof(BatchSeg));
+    hipError_t e = hipMemcpyAsync(ws, staging.data(), staging.size(), hipMemcpyHostToDevice, s);
+    if (e != hipSuccess)
+        return fail(MMLTTB_EDEVICE, "segment table copy failed: %s", hipGetErrorString(e));
+    BatchPtrs b;
+    b.segs = at<BatchSeg>(ws, h.off_segs);
+    b.n_segs = n_segs;
+    b.xk = xk;
+    b.x_base = x_base;
+    b.y_base = y_base;
+    b.out_base = out_idx_base;
+    b.keys = at<unsigned long long>(ws, h.off_keys);
+    b.P = at<int64_t>(ws, h.off_P);
+    b.XP = at<int64_t>(ws, h.off_XP);
+    b.YP = at<float>(ws, h.off_YP);
+    b.m = at<int64_t>(ws, h.off_m);
+    b.MX = at<double>(ws, h.off_MX);
+    b.MY = at<double>(ws, h.off_MY);
+    b.path = at<uint8_t>(ws, h.off_path);
+    b.finals = at<uint8_t>(ws, h.off_finals);
+    b.start = at<uint8_t>(ws, h.off_start);
+    b.counter = at<unsigned int>(ws, h.off_counter);
+    b.n_keys = h.n_keys;
+    b.n_large_items = h.n_large_items;
+    b.n_small_tiles = h.n_small_tiles;
+    b.n_chain_units = h.n_chain_units;
+    b.stage_cap_max = (int)(h.max_stage_cap > 0 ? h.max_stage_cap : kSegLen);
+    MMLTTB_LAUNCH("batch_init", s, launch_batch_init(b, s));
+    MMLTTB_LAUNCH("batch_minmax_large", s, launch_batch_large(b, tuning().unroll, s));
+    MMLTTB_LAUNCH("batch_minmax_small", s, launch_batch_small(b, s));
+    MMLTTB_LAUNCH("batch_compact", s, launch_batch_compact(b, s));
+    MMLTTB_LAUNCH("batch_means", s, launch_batch_means(b, s));
+    MMLTTB_LAUNCH("batch_chain", s, launch_batch_chain(b, s));
+    if (plan.any_seq) {
+        MMLTTB_LAUNCH("batch_chain_seq", s, launch_batch_chain_seq(b, s));
+    }
+    MMLTTB_LAUNCH("batch_emit", s, launch_batch_emit(b, s));
+    return ok();
 }
 
 int mmlttb_set_tuning(int unroll, int64_t chunk, int chain)

@@ -43,6 +43,75 @@ struct SegChainArgs {
     int stage_cap;         // LDS points per segment (kSegLen * bucket-size bound)
 };
 
+// ---------------------------------------------------------------- batched
+
+enum SegMode : int32_t { kSegIdentity = 0, kSegAll = 1, kSegMinMax = 2 };
+
+// Small-bin tiles: a workgroup of kTileThreads stages up to kTilePoints
+// consecutive points (whole bins) in LDS; a power-of-two group of lanes
+// reduces each bin. Bins of at most kSmallBinMax points take this path.
+constexpr int kTileThreads = 256;
+constexpr int kTilePoints = 4096;
+constexpr int kSmallBinMax = 1024;
+
+// One series of a batch as planned on the host (copied to the workspace).
+struct BatchSeg {
+    int64_t offset;     // first element in x_base / y_base
+    int64_t n, n_out, out_offset;
+    int32_t r_ps, mode; // SegMode
+    Split bins;         // interior split into nb bins (kSegMinMax)
+    int64_t chunk;      // large bins: points per work item
+    int64_t chunks_per_bin;
+    int32_t small;      // 1: bins reduced by LDS tiles
+    int32_t tile_bins;  // small: bins per tile (power of two, 4..256)
+    int64_t li0, ln;    // large-bin items: start and count in the flat item space
+    int64_t ti0, tn;    // small-bin tiles: start and count in the flat tile space
+    int64_t key0;       // pooled key pairs
+    int64_t p0;         // pooled P / XP / YP slots
+    int64_t B;          // interior LTTB buckets (n_out - 2)
+    int64_t b0;         // pooled MX / MY slots
+    int64_t c0;         // pooled chain-segment slots (path / finals / start)
+    int64_t cw0, cwn;   // chain walk units in the flat chain space (cwn = 0: sequential chain)
+    int32_t stage_cap;  // LDS points per chain segment
+    int32_t seq;        // 1: sequential chain
+};
+
+struct BatchHeader {
+    int64_t n_segs;
+    int64_t n_keys;
+    int64_t n_large_items, n_small_tiles, n_chain_units;
+    int64_t max_stage_cap;
+    int64_t off_segs, off_keys, off_P, off_XP, off_YP, off_m, off_MX, off_MY, off_path, off_finals, off_start,
+        off_counter;
+};
+
+struct BatchPtrs {
+    const BatchSeg *segs;
+    int64_t n_segs;
+    int xk;
+    const int64_t *x_base;
+    const float *y_base;
+    int64_t *out_base;
+    unsigned long long *keys;
+    int64_t *P, *XP;
+    float *YP;
+    int64_t *m;
+    double *MX, *MY;
+    uint8_t *path, *finals, *start;
+    unsigned int *counter;
+    int64_t n_keys, n_large_items, n_small_tiles, n_chain_units;
+    int stage_cap_max;
+};
+
+hipError_t launch_batch_init(const BatchPtrs &b, hipStream_t s);
+hipError_t launch_batch_large(const BatchPtrs &b, int unroll, hipStream_t s);
+hipError_t launch_batch_small(const BatchPtrs &b, hipStream_t s);
+hipError_t launch_batch_compact(const BatchPtrs &b, hipStream_t s);
+hipError_t launch_batch_means(const BatchPtrs &b, hipStream_t s);
+hipError_t launch_batch_chain(const BatchPtrs &b, hipStream_t s);
+hipError_t launch_batch_chain_seq(const BatchPtrs &b, hipStream_t s);
+hipError_t launch_batch_emit(const BatchPtrs &b, hipStream_t s);
+
 inline int64_t seg_count(int64_t B) { return (B + kSegLen - 1) / kSegLen; }
 inline size_t seg_path_bytes(int64_t B) { return (size_t)seg_count(B) * kSegStarts * kSegLen; }
 inline size_t seg_finals_bytes(int64_t B) { return (size_t)seg_count(B) * kSegStarts; }

@@ -14,6 +14,7 @@
 // the candidate with the largest doubled area
 // |(Xa - MX)(Yj - Ya) - (Xa - Xj)(MY - Ya)| (binary64, no contraction) wins,
 // the lowest position on ties, and becomes a.
+#include "chain_device.hpp"
 #include "device_common.hpp"
 #include "kernels.hpp"
 
@@ -48,17 +49,6 @@ __global__ __launch_bounds__(256) void k_preselect_all(int64_t n, const int64_t 
 
 // ------------------------------------------------------------------ means
 
-__device__ inline void next_bucket_range(const Split &bk, int64_t m, int64_t k, int64_t &g0, int64_t &g1)
-{
-    if (k < bk.parts - 1) {
-        g0 = 1 + split_lo(bk, k + 1);
-        g1 = 1 + split_lo(bk, k + 2);
-    } else {
-        g0 = m - 1;
-        g1 = m;
-    }
-}
-
 // One thread per bucket (preselected points: a handful per bucket).
 __global__ __launch_bounds__(256) void k_bucket_mean_small(const int64_t *__restrict__ XP, const float *__restrict__ YP,
                                                            const int64_t *__restrict__ m_ptr, int64_t m_const,
@@ -72,19 +62,7 @@ __global__ __launch_bounds__(256) void k_bucket_mean_small(const int64_t *__rest
         return;
     const int64_t m = m_ptr ? *m_ptr : m_const;
     const Split bk = make_split(m - 2, B);
-    int64_t g0, g1;
-    next_bucket_range(bk, m, k, g0, g1);
-    I64ExactSum sx;
-    F32ExactSum sy;
-    sx.clear();
-    sy.clear();
-    for (int64_t i = g0; i < g1; ++i) {
-        sx.add(XP ? XP[i] : i);
-        sy.add(YP[i]);
-    }
-    const double c = (double)(g1 - g0);
-    MX[k] = sx.round() / c;
-    MY[k] = sy.round() / c;
+    bucket_mean_one(XP, YP, bk, m, k, MX[k], MY[k]);
 }
 
 // One workgroup (256 threads) per bucket (whole-series LTTB: large buckets).
@@ -293,85 +271,19 @@ __global__ __launch_bounds__(kSegStarts) void k_lttb_chain_seg(SegChainArgs a)
     extern __shared__ double lds[];
     __shared__ uint8_t F[kChaseWindow * kSegStarts];
     __shared__ unsigned int s_ticket;
-    const int lane = threadIdx.x;
-    const int64_t s = blockIdx.x;
     const int64_t m = a.m_ptr ? *a.m_ptr : a.m_const;
-    const int64_t B = a.B;
-    const Split bk = make_split(m - 2, B);
-    const int64_t k0 = s * kSegLen, k1 = (k0 + kSegLen < B) ? k0 + kSegLen : B;
-    const int64_t p0 = 1 + split_lo(bk, k0), p1 = 1 + split_lo(bk, k1);
-    double *sx = lds, *sy = lds + a.stage_cap, *smx = lds + 2 * a.stage_cap, *smy = smx + kSegLen;
-    for (int64_t p = p0 + lane; p < p1; p += kSegStarts) {
-        sx[p - p0] = (double)(a.XP ? a.XP[p] : p);
-        sy[p - p0] = (double)a.YP[p];
-    }
-    for (int64_t k = k0 + lane; k < k1; k += kSegStarts) {
-        smx[k - k0] = a.MX[k];
-        smy[k - k0] = a.MY[k];
-    }
-    __syncthreads();
-
-    int64_t apos = 0;
-    if (s > 0) {
-        const int64_t sa = 1 + split_lo(bk, k0 - 1);
-        const int64_t ca = p0 - sa; // points of the bucket before the segment (<= kSegStarts)
-        apos = sa + (lane < ca ? lane : ca - 1);
-    }
-    double ax = (double)(a.XP ? a.XP[apos] : apos);
-    double ay = (double)a.YP[apos];
-    SplitWalker w;
-    w.init(bk, k0);
-    uint8_t *mypath = a.path + ((size_t)s * kSegStarts + lane) * kSegLen;
-    int bo = 0;
-    for (int64_t k = k0; k < k1; ++k) {
-        const int64_t s0 = 1 + w.lo, s1 = 1 + w.next_lo(bk);
-        w.advance(bk);
-        const double mx = smx[k - k0], my = smy[k - k0];
-        double best = -1.0, bx = ax, by = ay;
-        bo = 0;
-        for (int64_t j = s0; j < s1; ++j) {
-            const double xj = sx[j - p0], yj = sy[j - p0];
-            const double ar = lttb_area2(ax, ay, xj, yj, mx, my);
-            if (ar > best) { // strict: lowest position wins ties
-                best = ar;
-                bo = (int)(j - s0);
-                bx = xj;
-                by = yj;
-            }
-        }
-        ax = bx;
-        ay = by;
-        mypath[k - k0] = (uint8_t)bo;
-    }
-    a.finals[(size_t)s * kSegStarts + lane] = (uint8_t)bo;
-
+    const Split bk = make_split(m - 2, a.B);
+    seg_walk(a.XP, a.YP, bk, a.MX, a.MY, (int64_t)blockIdx.x, a.stage_cap, lds, a.path, a.finals);
     __threadfence();
     __syncthreads();
-    if (lane == 0)
+    if (threadIdx.x == 0)
         s_ticket = atomicAdd(a.counter, 1u);
     __syncthreads();
     if (s_ticket != (unsigned int)(a.S - 1))
         return;
     __threadfence();
-    int cur = 0;
-    if (lane == 0)
-        a.start[0] = 0;
-    for (int64_t w0 = 0; w0 < a.S - 1; w0 += kChaseWindow) {
-        const int64_t w1 = (w0 + kChaseWindow < a.S - 1) ? w0 + kChaseWindow : a.S - 1;
-        const int64_t words = (w1 - w0) * kSegStarts / 4;
-        const uint32_t *src = reinterpret_cast<const uint32_t *>(a.finals + w0 * kSegStarts);
-        for (int64_t q = lane; q < words; q += kSegStarts)
-            reinterpret_cast<uint32_t *>(F)[q] = src[q];
-        __syncthreads();
-        if (lane == 0) {
-            for (int64_t t = w0; t < w1; ++t) {
-                cur = F[(t - w0) * kSegStarts + cur];
-                a.start[t + 1] = (uint8_t)cur;
-            }
-        }
-        __syncthreads();
-    }
-    if (lane == 0)
+    seg_link(a.finals, a.start, a.S, F);
+    if (threadIdx.x == 0)
         *a.counter = 0u;
 }
 
@@ -382,10 +294,7 @@ __global__ __launch_bounds__(256) void k_lttb_chain_emit(SegChainArgs a, const i
     const Split bk = make_split(m - 2, a.B);
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < a.B; k += stride) {
-        const int64_t s = k / kSegLen;
-        const int l = a.start[s];
-        const int off = a.path[((size_t)s * kSegStarts + l) * kSegLen + (k - s * kSegLen)];
-        const int64_t sel = 1 + split_lo(bk, k) + off;
+        const int64_t sel = seg_pick(a.path, a.start, bk, k);
         out[k + 1] = Pmap ? Pmap[sel] : sel;
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) {

@@ -86,6 +86,49 @@ def minmaxlttb(y, n_out: int, r_ps: int, x=None, out=None, ws=None):
     return out[: min(n, n_out)]
 
 
+def segment_table(segs):
+    """Build the C segment array from (offset, n, n_out, r_ps) tuples; output
+    slots are packed in order. Returns (ctypes array, out_offsets, total_out)."""
+    arr = (_lib.Segment * len(segs))()
+    out_offsets = []
+    pos = 0
+    for i, (offset, n, n_out, r_ps) in enumerate(segs):
+        arr[i].offset = int(offset)
+        arr[i].n = int(n)
+        arr[i].n_out = int(n_out)
+        arr[i].r_ps = int(r_ps)
+        arr[i].reserved = 0
+        arr[i].out_offset = pos
+        out_offsets.append(pos)
+        pos += min(int(n), int(n_out))
+    return arr, out_offsets, pos
+
+
+def batched_workspace_size(segs) -> int:
+    arr, _, _ = segment_table(segs)
+    return int(_lib.load().mmlttb_batched_workspace_size(arr, len(segs)))
+
+
+def minmaxlttb_batched(y_base, segs, x_base=None, out=None, ws=None, table=None):
+    """MinMaxLTTB over many series in one call.
+
+    y_base (and x_base) hold the series back to back; segs lists
+    (offset, n, n_out, r_ps) per series. Returns (out, out_offsets): series i's
+    min(n, n_out) segment-local indices are out[out_offsets[i]:...]."""
+    lib = _lib.load()
+    if not isinstance(y_base, torch.Tensor) or y_base.dtype != torch.float32 or not y_base.is_cuda:
+        raise TypeError("y_base must be a float32 CUDA (HIP) tensor")
+    if x_base is not None and (x_base.dtype != torch.int64 or x_base.device != y_base.device):
+        raise TypeError("x_base must be an int64 tensor on y_base's device")
+    arr, out_offsets, total = table if table is not None else segment_table(segs)
+    xk = _lib.X_INT64 if x_base is not None else _lib.X_IMPLICIT
+    out = out if out is not None else torch.empty(max(total, 1), dtype=torch.int64, device=y_base.device)
+    ws = _workspace(lib.mmlttb_batched_workspace_size(arr, len(arr)), y_base.device, ws)
+    _lib.check(lib.mmlttb_minmaxlttb_batched(xk, _lib.ptr(x_base), y_base.data_ptr(), arr, len(arr), out.data_ptr(),
+                                             ws.data_ptr(), ws.numel(), _lib.stream_ptr()))
+    return out, out_offsets
+
+
 CHAIN_AUTO, CHAIN_SEQUENTIAL, CHAIN_SEGMENTED = 0, 1, 2
 
 

@@ -116,6 +116,25 @@ def choice(values, count: int, seed: int) -> np.ndarray:
     return rng.choice(np.asarray(values), size=count)
 
 
+def batch_series(lengths, seed: int, device="cpu", with_x: bool = True, noise_sigma: float = 0.5):
+    """Series of the given lengths stored back to back: y = random walk + N(0, 0.5^2)
+    noise (one walk across the whole buffer, so each series is a walk segment),
+    x = one strictly increasing irregular int64 timeline (each series a slice).
+    Returns (x, y, offsets)."""
+    lengths = np.asarray(lengths, dtype=np.int64)
+    offsets = np.concatenate([[0], np.cumsum(lengths)[:-1]]).astype(np.int64)
+    total = int(lengths.sum())
+    y = random_walk(total, seed, device=device)
+    g = _gen(seed + 5_000_011, device)
+    for lo in range(0, total, _CHUNK):
+        hi = min(total, lo + _CHUNK)
+        noise = torch.randn(hi - lo, generator=g, dtype=torch.float64, device=device) * noise_sigma
+        y[lo:hi] = (y[lo:hi].to(torch.float64) + noise).to(torch.float32)
+        del noise
+    x = irregular_x(total, seed + 6_000_011, device=device) if with_x else None
+    return x, y, offsets
+
+
 # ---------------------------------------------------------------- edge cases
 
 def ties_series(n: int, seed: int, levels: int = 5, device="cpu") -> torch.Tensor:
