@@ -64,6 +64,14 @@ def main():
     ap.add_argument("--seed", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-reps", type=int, default=3)
+    ap.add_argument("--skip-headline", action="store_true")
+    ap.add_argument("--skip-batched", action="store_true")
+    ap.add_argument("--skip-served", action="store_true")
+    ap.add_argument("--batch-series", type=int, default=4096)
+    ap.add_argument("--pool-series", type=int, default=512)
+    ap.add_argument("--rates", type=str, default="100,500,1000,2000,5000")
+    ap.add_argument("--serve-seconds", type=float, default=2.0)
+    ap.add_argument("--burst", type=int, default=2000)
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -71,6 +79,25 @@ def main():
               "(the design notes describe how the work would shard).", file=sys.stderr)
         sys.exit(2)
 
+    import torch
+
+    from paper_2305_00332_amd import _lib
+
+    torch.cuda.set_device(0)
+    _lib.load()
+    result = {"metric": METRIC}
+    if not args.skip_headline:
+        result.update(bench_headline(args))
+    if not args.skip_batched:
+        result["batched"] = bench_batched(args)
+    if not args.skip_served:
+        result["served"] = bench_served(args)
+    print(json.dumps(result), flush=True)
+
+
+def bench_headline(args):
+    """One 1e9-point series: MinMaxLTTB steps, the stream kernel's roofline,
+    the CPU oracle baseline and parity."""
     import numpy as np
     import torch
 
@@ -107,7 +134,7 @@ def main():
     ops.profile_enable(False)
     ms_per_step = (t1 - t0) * 1e3 / args.steps
     kern = {}
-    for k in ("init_keys", "minmax_bin_reduce", "preselect_compact", "preselect_all", "bucket_mean",
+    for k in ("init_keys", "minmax_bin_reduce", "preselect_compact_means", "preselect_all", "bucket_mean",
               "lttb_chain", "lttb_chain_seg"):
         tot, cnt = ops.profile_read(k)
         kern[k] = round(tot / cnt, 5) if cnt else None
@@ -122,7 +149,6 @@ def main():
                 "traffic": traffic, "algorithmic_bytes": alg_bytes, "avg_ms": mm_ms}
 
     result = {
-        "metric": METRIC,
         "value": round(n / (ms_per_step * 1e-3) / 1e9, 3),
         "unit": "Gpts/s",
         "n_gpus": 1,
@@ -158,7 +184,151 @@ def main():
                                   "sample": f"the full workload (n={n}) run {len(times)} times single-threaded, "
                                             f"median {t:.3f} s"}
         result["parity_vs_oracle"] = bool(np.array_equal(out.cpu().numpy(), want))
-    print(json.dumps(result), flush=True)
+        del y_np
+    del y, ws
+    torch.cuda.empty_cache()
+    return result
+
+
+def bench_batched(args):
+    """Many series of uneven length: one batched call vs one call per series."""
+    import numpy as np
+    import torch
+
+    from paper_2305_00332_amd import ops, synth
+
+    count = args.batch_series
+    lengths = synth.batch_lengths(count, 1e3, 1e7, 4)
+    n_outs = synth.choice([200, 500, 1000, 2000], count, 40)
+    log(f"batched: generating {count} series, {int(lengths.sum())} points")
+    x, y, offsets = synth.batch_series(lengths, 4, device="cuda")
+    torch.cuda.synchronize()
+    segs = [(int(o), int(n), int(no), 4) for o, n, no in zip(offsets, lengths, n_outs)]
+    table = ops.segment_table(segs)
+    out = torch.empty(max(table[2], 1), dtype=torch.int64, device="cuda")
+    ws = torch.empty(ops.batched_workspace_size(segs), dtype=torch.uint8, device="cuda")
+    for _ in range(2):
+        ops.minmaxlttb_batched(y, segs, x_base=x, out=out, ws=ws, table=table)
+    torch.cuda.synchronize()
+    reps = 5
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        ops.minmaxlttb_batched(y, segs, x_base=x, out=out, ws=ws, table=table)
+    torch.cuda.synchronize()
+    t_batched = (time.perf_counter() - t0) / reps
+    ops.profile_enable(True)
+    ops.profile_reset()
+    ops.minmaxlttb_batched(y, segs, x_base=x, out=out, ws=ws, table=table)
+    torch.cuda.synchronize()
+    ops.profile_enable(False)
+    kern = {}
+    for k in ("batch_init", "batch_minmax_large", "batch_minmax_small", "batch_compact_means",
+              "batch_chain", "batch_chain_seq", "batch_link_emit"):
+        tot, cnt = ops.profile_read(k)
+        if cnt:
+            kern[k] = round(tot / cnt, 4)
+    log("batched: plain per-series calls")
+    plain = torch.empty_like(out)
+    ws1 = torch.empty(max(ops.workspace_size(1, no, 4) for no in (200, 500, 1000, 2000)), dtype=torch.uint8,
+                      device="cuda")
+    outoff = table[1]
+
+    def run_plain():
+        for i, (o, n, no, r) in enumerate(segs):
+            k = min(n, no)
+            ops.minmaxlttb(y[o: o + n], no, r, x=x[o: o + n], out=plain[outoff[i]: outoff[i] + k], ws=ws1)
+
+    run_plain()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    run_plain()
+    torch.cuda.synchronize()
+    t_plain = time.perf_counter() - t0
+    pts = int(lengths.sum())
+    res = {"workload": f"{count} series, lengths log-uniform in [1e3, 1e7] (seed 4), float32 random walk + "
+                       f"N(0, 0.5^2), int64 irregular x; n_out in {{200, 500, 1000, 2000}}, r_ps=4",
+           "points": pts, "ms": round(t_batched * 1e3, 4), "gpts_per_s": round(pts / t_batched / 1e9, 3),
+           "plain_ms": round(t_plain * 1e3, 4), "plain_gpts_per_s": round(pts / t_plain / 1e9, 3),
+           "speedup_vs_plain": round(t_plain / t_batched, 3), "kernel_ms": kern,
+           "identical_to_plain": bool(torch.equal(out[: table[2]], plain[: table[2]]))}
+    del x, y, out, plain, ws, ws1
+    torch.cuda.empty_cache()
+    return res
+
+
+def bench_served(args):
+    """Poisson request streams against a resident pool: continuous batching
+    vs one single-series call per request, p50/p99 latency and Gpts/s."""
+    import numpy as np
+    import torch
+
+    from paper_2305_00332_amd import synth
+    from paper_2305_00332_amd.serve import GpuExecutor, PlainGpuExecutor, Scheduler, latency_summary, \
+        poisson_requests
+
+    count = args.pool_series
+    lengths = synth.batch_lengths(count, 1e4, 1e8, 5)
+    log(f"served: generating pool of {count} series, {int(lengths.sum())} points")
+    x, y, offsets = synth.batch_series(lengths, 5, device="cuda", sinusoids=True)
+    torch.cuda.synchronize()
+    rates = [float(r) for r in args.rates.split(",") if r]
+    per_rate = {}
+    identical = True
+    for rate in rates:
+        n_req = max(100, int(rate * args.serve_seconds))
+        reqs = poisson_requests(rate, n_req, lengths, seed=50 + int(rate))
+        warm = poisson_requests(rate, 50, lengths, seed=7)
+        entry = {}
+        results = {}
+        for name, ex_cls, slots, max_batch in (("batched", GpuExecutor, 3, None), ("plain", PlainGpuExecutor, 4, 1)):
+            ex = ex_cls(y, offsets, lengths, x=x, n_slots=slots)
+            Scheduler(ex, n_slots=slots, ws_budget=1 << 30, max_batch=max_batch).run_open_loop(warm, timeout=120)
+            sched = Scheduler(ex, n_slots=slots, ws_budget=1 << 30, max_batch=max_batch)
+            log(f"served: rate {rate:g}/s, {n_req} requests, {name}")
+            fresh = [type(r)(r.rid, r.series, r.lo, r.hi, r.n_out, r.r_ps, r.arrival) for r in reqs]
+            done = sched.run_open_loop(fresh, timeout=300)
+            s = latency_summary(done)
+            if name == "batched":
+                s["mean_batch"] = round(float(np.mean(sched.batch_sizes)), 2)
+                s["max_in_flight"] = sched.max_in_flight
+            entry[name] = s
+            results[name] = {r.rid: r.result for r in done}
+        identical = identical and all(np.array_equal(results["batched"][k], results["plain"][k])
+                                      for k in results["batched"])
+        b, p = entry["batched"], entry["plain"]
+        entry["p99_speedup_vs_plain"] = round(p["p99_ms"] / b["p99_ms"], 3) if b.get("p99_ms") else None
+        entry["throughput_ratio_vs_plain"] = round(b["gpts_per_s"] / p["gpts_per_s"], 3) if p.get("gpts_per_s") else None
+        per_rate[f"{rate:g}"] = entry
+    # saturation: a burst of requests all arriving at t=0, served to completion
+    burst_n = args.burst
+    burst = poisson_requests(1e12, burst_n, lengths, seed=77)
+    burst_entry = {}
+    burst_results = {}
+    for name, ex_cls, slots, max_batch in (("batched", GpuExecutor, 3, 256), ("plain", PlainGpuExecutor, 4, 1)):
+        ex = ex_cls(y, offsets, lengths, x=x, n_slots=slots)
+        fresh = [type(r)(r.rid, r.series, r.lo, r.hi, r.n_out, r.r_ps, 0.0) for r in burst]
+        Scheduler(ex, n_slots=slots, ws_budget=1 << 30, max_batch=max_batch).run_open_loop(fresh[:64], timeout=120)
+        fresh = [type(r)(r.rid, r.series, r.lo, r.hi, r.n_out, r.r_ps, 0.0) for r in burst]
+        sched = Scheduler(ex, n_slots=slots, ws_budget=1 << 30, max_batch=max_batch)
+        log(f"served: burst of {burst_n} requests, {name}")
+        done = sched.run_open_loop(fresh, timeout=300)
+        s = latency_summary(done)
+        s["steps"] = sched.steps_launched
+        burst_entry[name] = s
+        burst_results[name] = {r.rid: r.result for r in done}
+    identical = identical and all(np.array_equal(burst_results["batched"][k], burst_results["plain"][k])
+                                  for k in burst_results["batched"])
+    burst_entry["throughput_ratio_vs_plain"] = round(burst_entry["batched"]["gpts_per_s"] /
+                                                     burst_entry["plain"]["gpts_per_s"], 3)
+    res = {"workload": f"pool of {count} series resident in HBM, lengths log-uniform in [1e4, 1e8] (seed 5), "
+                       f"float32 random walk + sinusoids + noise, int64 irregular x; Poisson arrivals; per request "
+                       f"a series, a log-uniform sub-range, n_out uniform in [100, 4000], r_ps in {{2, 4}}",
+           "pool_points": int(lengths.sum()), "seconds_per_rate": args.serve_seconds, "rates": per_rate,
+           "burst": burst_entry,
+           "identical_to_plain": bool(identical)}
+    del x, y
+    torch.cuda.empty_cache()
+    return res
 
 
 if __name__ == "__main__":

@@ -117,7 +117,7 @@ constexpr size_t kAlign = 256;
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 struct MmLayout {
-    size_t keys, m, P, XP, YP, MX, MY, path, finals, start, counter, total;
+    size_t keys, m, P, XP, YP, MX, MY, path, finals, start, total;
 };
 
 MmLayout mm_layout(int64_t n_out, int32_t r_ps)
@@ -142,13 +142,12 @@ MmLayout mm_layout(int64_t n_out, int32_t r_ps)
     L.path = take(seg_path_bytes(B));
     L.finals = take(seg_finals_bytes(B));
     L.start = take((size_t)seg_count(B));
-    L.counter = take(sizeof(unsigned int));
     L.total = off;
     return L;
 }
 
 struct LtLayout {
-    size_t MX, MY, path, finals, start, counter, total;
+    size_t MX, MY, path, finals, start, total;
 };
 
 LtLayout lt_layout(int64_t n_out)
@@ -166,7 +165,6 @@ LtLayout lt_layout(int64_t n_out)
     L.path = take(seg_path_bytes(B));
     L.finals = take(seg_finals_bytes(B));
     L.start = take((size_t)seg_count(B));
-    L.counter = take(sizeof(unsigned int));
     L.total = off;
     return L;
 }
@@ -245,7 +243,7 @@ bool use_segmented_chain(int64_t maxb_bound)
     return mode != kChainSequential && maxb_bound <= kSegStarts;
 }
 
-SegChainArgs seg_args(void *ws, size_t path, size_t finals, size_t start, size_t counter, const int64_t *XP,
+SegChainArgs seg_args(void *ws, size_t path, size_t finals, size_t start, const int64_t *XP,
                       const float *YP, const int64_t *m_ptr, int64_t m_const, int64_t B, const double *MX,
                       const double *MY, int64_t maxb_bound)
 {
@@ -260,7 +258,6 @@ SegChainArgs seg_args(void *ws, size_t path, size_t finals, size_t start, size_t
     a.path = at<uint8_t>(ws, path);
     a.finals = at<uint8_t>(ws, finals);
     a.start = at<uint8_t>(ws, start);
-    a.counter = at<unsigned int>(ws, counter);
     a.S = seg_count(B);
     a.stage_cap = (int)(kSegLen * maxb_bound);
     return a;
@@ -382,6 +379,21 @@ int plan_batch(int xk, const mmlttb_segment_t *in, int64_t n_segs, BatchPlan &pl
     }
     BatchHeader &h = plan.h;
     memset(&h, 0, sizeof(h));
+    auto owner_table = [&](int32_t *table, int64_t total, auto start_of) {
+        if (total <= 0)
+            return;
+        int64_t s = 0;
+        for (int q = 0; q <= kOwnerTable; ++q) {
+            int64_t unit = (int64_t)(((__int128)q * total) / kOwnerTable);
+            unit = unit < total - 1 ? unit : total - 1;
+            while (s + 1 < n_segs && start_of(plan.segs[(size_t)s + 1]) <= unit)
+                ++s;
+            table[q] = (int32_t)s;
+        }
+    };
+    owner_table(h.own_large, large, [](const BatchSeg &g) { return g.li0; });
+    owner_table(h.own_small, tiles, [](const BatchSeg &g) { return g.ti0; });
+    owner_table(h.own_chain, cw, [](const BatchSeg &g) { return g.cw0; });
     h.n_segs = n_segs;
     h.n_keys = keys;
     h.n_large_items = large;
@@ -406,7 +418,6 @@ int plan_batch(int xk, const mmlttb_segment_t *in, int64_t n_segs, BatchPlan &pl
     h.off_path = take((size_t)cslots * kSegStarts * kSegLen);
     h.off_finals = take((size_t)cslots * kSegStarts);
     h.off_start = take((size_t)cslots);
-    h.off_counter = take(4 * (size_t)n_segs);
     plan.total = off;
     return MMLTTB_OK;
 }
@@ -484,14 +495,13 @@ int mmlttb_lttb(int xk, const int64_t *x, const float *y, int64_t n, int64_t n_o
     double *MX = at<double>(ws, L.MX), *MY = at<double>(ws, L.MY);
     const Split bk = make_split(n - 2, B);
     const int64_t maxb = bk.q + (bk.r ? 1 : 0);
-    unsigned int *counter = at<unsigned int>(ws, L.counter);
     if (maxb <= 64) {
-        MMLTTB_LAUNCH("bucket_mean", s, launch_bucket_mean_small(x, y, nullptr, n, B, MX, MY, counter, s));
+        MMLTTB_LAUNCH("bucket_mean", s, launch_bucket_mean_small(x, y, nullptr, n, B, MX, MY, s));
     } else {
-        MMLTTB_LAUNCH("bucket_mean_wide", s, launch_bucket_mean_wide(x, y, n, B, MX, MY, counter, s));
+        MMLTTB_LAUNCH("bucket_mean_wide", s, launch_bucket_mean_wide(x, y, n, B, MX, MY, s));
     }
     if (use_segmented_chain(maxb)) {
-        const SegChainArgs a = seg_args(ws, L.path, L.finals, L.start, L.counter, x, y, nullptr, n, B, MX, MY, maxb);
+        const SegChainArgs a = seg_args(ws, L.path, L.finals, L.start, x, y, nullptr, n, B, MX, MY, maxb);
         MMLTTB_LAUNCH("lttb_chain_seg", s, launch_lttb_chain_seg(a, nullptr, out_idx, s));
     } else if (maxb <= kChainStage) {
         MMLTTB_LAUNCH("lttb_chain", s, launch_lttb_chain(x, y, nullptr, n, B, MX, MY, nullptr, out_idx, s));
@@ -524,17 +534,23 @@ int mmlttb_minmaxlttb(int xk, const int64_t *x, const float *y, int64_t n, int64
     int64_t *P = at<int64_t>(ws, L.P), *XP = at<int64_t>(ws, L.XP), *m = at<int64_t>(ws, L.m);
     float *YP = at<float>(ws, L.YP);
     double *MX = at<double>(ws, L.MX), *MY = at<double>(ws, L.MY);
-    rc = enqueue_preselect(x, y, n, n_out, r_ps, ws, L, P, XP, YP, m, s);
-    if (rc)
-        return rc;
     const int64_t B = n_out - 2;
-    unsigned int *counter = at<unsigned int>(ws, L.counter);
-    MMLTTB_LAUNCH("bucket_mean", s, launch_bucket_mean_small(XP, YP, m, 0, B, MX, MY, counter, s));
-    // preselected points per bucket: at most ceil((m-2)/B) with m - 2 <= 2*nb
     const int64_t nb = n_out * (int64_t)r_ps / 2;
+    if (nb >= n - 2) { // every bin holds at most one point: P is every index
+        MMLTTB_LAUNCH("preselect_all", s, launch_preselect_all(n, x, y, P, XP, YP, m, s));
+        MMLTTB_LAUNCH("bucket_mean", s, launch_bucket_mean_small(XP, YP, m, 0, B, MX, MY, s));
+    } else {
+        unsigned long long *keys = at<unsigned long long>(ws, L.keys);
+        const MinMaxGeom g = minmax_geom(n, nb);
+        MMLTTB_LAUNCH("init_keys", s, launch_init_keys(keys, nb, s));
+        MMLTTB_LAUNCH("minmax_bin_reduce", s, launch_minmax_bin_reduce(y, g, tuning().unroll, keys, s));
+        MMLTTB_LAUNCH("preselect_compact_means", s,
+                      launch_preselect_compact_means(keys, g.bins, n, x, y, P, XP, YP, m, B, MX, MY, s));
+    }
+    // preselected points per bucket: at most ceil((m-2)/B) with m - 2 <= 2*nb
     const int64_t maxb_bound = (2 * nb + B - 1) / B;
     if (use_segmented_chain(maxb_bound)) {
-        const SegChainArgs a = seg_args(ws, L.path, L.finals, L.start, L.counter, XP, YP, m, 0, B, MX, MY, maxb_bound);
+        const SegChainArgs a = seg_args(ws, L.path, L.finals, L.start, XP, YP, m, 0, B, MX, MY, maxb_bound);
         MMLTTB_LAUNCH("lttb_chain_seg", s, launch_lttb_chain_seg(a, P, out_idx, s));
     } else {
         MMLTTB_LAUNCH("lttb_chain", s, launch_lttb_chain(XP, YP, m, 0, B, MX, MY, P, out_idx, s));
@@ -581,6 +597,7 @@ int mmlttb_minmaxlttb_batched(int xk, const int64_t *x_base, const float *y_base
     if (e != hipSuccess)
         return fail(MMLTTB_EDEVICE, "segment table copy failed: %s", hipGetErrorString(e));
     BatchPtrs b;
+    b.hdr = at<BatchHeader>(ws, 0);
     b.segs = at<BatchSeg>(ws, h.off_segs);
     b.n_segs = n_segs;
     b.xk = xk;
@@ -597,22 +614,26 @@ int mmlttb_minmaxlttb_batched(int xk, const int64_t *x_base, const float *y_base
     b.path = at<uint8_t>(ws, h.off_path);
     b.finals = at<uint8_t>(ws, h.off_finals);
     b.start = at<uint8_t>(ws, h.off_start);
-    b.counter = at<unsigned int>(ws, h.off_counter);
     b.n_keys = h.n_keys;
     b.n_large_items = h.n_large_items;
     b.n_small_tiles = h.n_small_tiles;
     b.n_chain_units = h.n_chain_units;
     b.stage_cap_max = (int)(h.max_stage_cap > 0 ? h.max_stage_cap : kSegLen);
-    MMLTTB_LAUNCH("batch_init", s, launch_batch_init(b, s));
-    MMLTTB_LAUNCH("batch_minmax_large", s, launch_batch_large(b, tuning().unroll, s));
-    MMLTTB_LAUNCH("batch_minmax_small", s, launch_batch_small(b, s));
-    MMLTTB_LAUNCH("batch_compact", s, launch_batch_compact(b, s));
-    MMLTTB_LAUNCH("batch_means", s, launch_batch_means(b, s));
+    if (h.n_large_items > 0) {
+        MMLTTB_LAUNCH("batch_init", s, launch_batch_init(b, s));
+        MMLTTB_LAUNCH("batch_minmax_large", s, launch_batch_large(b, tuning().unroll, s));
+    }
+    if (h.n_small_tiles > 0) {
+        MMLTTB_LAUNCH("batch_minmax_small", s, launch_batch_small(b, s));
+    }
+    MMLTTB_LAUNCH("batch_compact_means", s, launch_batch_compact_means(b, s));
     MMLTTB_LAUNCH("batch_chain", s, launch_batch_chain(b, s));
     if (plan.any_seq) {
         MMLTTB_LAUNCH("batch_chain_seq", s, launch_batch_chain_seq(b, s));
     }
-    MMLTTB_LAUNCH("batch_emit", s, launch_batch_emit(b, s));
+    if (h.n_chain_units > 0) {
+        MMLTTB_LAUNCH("batch_link_emit", s, launch_batch_link_emit(b, s));
+    }
     return ok();
 }
 

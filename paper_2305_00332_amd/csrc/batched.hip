@@ -1,25 +1,26 @@
 // Batched MinMaxLTTB: many series of uneven length in one call.
 //
 // The host plans every series into a BatchSeg (mode, bins, work ranges, pooled
-// workspace slots) and copies the table into the workspace. Persistent
-// kernels then walk flat work spaces; each workgroup (or wave) takes one
-// contiguous range of work units, finds the series of its first unit by a
-// binary search over the per-series starts and steps forward from there.
+// workspace slots) and copies the table into the workspace. The stream and
+// chain kernels launch one wave or workgroup per unit of a flat work space
+// (the hardware balances uneven units); a unit finds its series through a
+// coarse owner table and a short binary search. Per-series kernels loop over
+// the series with a grid-stride.
 //
-//   init      keys of every series to their identities, link counters to 0
+//   init      keys to their identities (only when large-bin series exist)
 //   large     series whose bins hold > kSmallBinMax points: one wave per
 //             (bin, chunk) item, as in the single-series stream (16-byte
 //             loads, atomic key merge)
 //   small     series with small bins: a workgroup stages a tile of whole bins
 //             (<= kTilePoints points) in LDS; a power-of-two lane group
 //             reduces each bin and stores its keys
-//   compact   one workgroup per series: P, X_P, Y_P, m (identity series write
-//             their output here)
-//   means     one workgroup per series: exact next-bucket means
-//   chain     segmented chain: one wave per (series, chain segment) walks from
-//             every start; the last wave of each series links its segments
+//   compact_means  one workgroup per series: P, X_P, Y_P, m, then the exact
+//             next-bucket means (identity series write their output here)
+//   chain     segmented chain, walks: one wave per (series, chain segment)
+//             walks the segment from every start point
 //   chain_seq sequential chain for series whose buckets exceed kSegStarts
-//   emit      one workgroup per series: picks mapped through P to the output
+//   link_emit one workgroup per series: links its chain segments and writes
+//             the picks mapped through P to the output
 //
 // Each series' result equals the single-series call on it alone: the same
 // bins, keys, exact means and binary64 areas, evaluated in the same order.
@@ -30,12 +31,15 @@
 
 namespace mmlttb {
 
-// Last series whose start (in one flat space) is <= i. Series with no work in
-// that space start where the next series starts, so this is the owner.
+// Series owning unit i of a flat work space: the last series whose start is
+// <= i (series with no work there start where the next one starts), searched
+// between two neighbouring entries of the space's coarse owner table.
 template <class StartOf>
-__device__ inline int64_t find_owner(const BatchSeg *segs, int64_t n_segs, int64_t i, StartOf start_of)
+__device__ inline int64_t find_owner(const BatchSeg *__restrict__ segs, const int32_t *__restrict__ table,
+                                     int64_t total, int64_t i, StartOf start_of)
 {
-    int64_t lo = 0, hi = n_segs - 1;
+    const int64_t q = (i * kOwnerTable) / total;
+    int64_t lo = table[q], hi = table[q + 1];
     while (lo < hi) {
         const int64_t mid = (lo + hi + 1) >> 1;
         if (start_of(segs[mid]) <= i)
@@ -54,8 +58,6 @@ __global__ __launch_bounds__(256) void k_batch_init(BatchPtrs b)
         b.keys[2 * i] = ~0ull;
         b.keys[2 * i + 1] = 0ull;
     }
-    for (int64_t i = t; i < b.n_segs; i += stride)
-        b.counter[i] = 0u;
 }
 
 template <int U>
@@ -63,34 +65,28 @@ __global__ __launch_bounds__(256) void k_batch_large(BatchPtrs b)
 {
     const int lane = threadIdx.x & (kWave - 1);
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
-    const int64_t W = (int64_t)gridDim.x * (blockDim.x / kWave);
-    const int64_t w = (int64_t)blockIdx.x * (blockDim.x / kWave) + wave;
+    const int64_t i = (int64_t)blockIdx.x * (blockDim.x / kWave) + wave;
     const int64_t total = b.n_large_items;
-    const int64_t per = (total + W - 1) / W;
-    const int64_t i0 = w * per, i1 = (i0 + per < total) ? i0 + per : total;
-    if (i0 >= i1)
+    if (i >= total)
         return;
-    int64_t s = find_owner(b.segs, b.n_segs, i0, [](const BatchSeg &g) { return g.li0; });
-    for (int64_t i = i0; i < i1; ++i) {
-        while (i >= b.segs[s].li0 + b.segs[s].ln)
-            ++s;
-        const BatchSeg &g = b.segs[s];
-        const int64_t li = i - g.li0;
-        const int64_t bb = li / g.chunks_per_bin;
-        const int64_t j = li - bb * g.chunks_per_bin;
-        const int64_t blo = 1 + split_lo(g.bins, bb);
-        const int64_t bhi = 1 + split_lo(g.bins, bb + 1);
-        const int64_t lo = blo + j * g.chunk;
-        if (lo >= bhi)
-            continue;
-        const int64_t hi = (lo + g.chunk < bhi) ? lo + g.chunk : bhi;
-        float vmin, vmax;
-        int64_t imin, imax;
-        wave_reduce_range<U>(b.y_base + g.offset, lo, hi, lane, vmin, imin, vmax, imax);
-        if (lane == 0) {
-            atomicMin(&b.keys[2 * (g.key0 + bb)], pack_min_key(vmin, imin - blo));
-            atomicMax(&b.keys[2 * (g.key0 + bb) + 1], pack_max_key(vmax, imax - blo));
-        }
+    const int64_t s = find_owner(b.segs, b.hdr->own_large, total, i, [](const BatchSeg &g) { return g.li0; });
+    const BatchSeg &g = b.segs[s];
+    const int64_t li = i - g.li0;
+    const int64_t bb = li / g.chunks_per_bin;
+    const int64_t j = li - bb * g.chunks_per_bin;
+    const int64_t blo = 1 + split_lo(g.bins, bb);
+    const int64_t bhi = 1 + split_lo(g.bins, bb + 1);
+    const int64_t lo = blo + j * g.chunk;
+    if (lo >= bhi)
+        return;
+    const int64_t hi = (lo + g.chunk < bhi) ? lo + g.chunk : bhi;
+    unsigned long long *keys = b.keys + 2 * (g.key0 + bb);
+    float vmin, vmax;
+    int64_t imin, imax;
+    wave_reduce_range<U>(b.y_base + g.offset, lo, hi, lane, vmin, imin, vmax, imax);
+    if (lane == 0) {
+        atomicMin(&keys[0], pack_min_key(vmin, imin - blo));
+        atomicMax(&keys[1], pack_max_key(vmax, imax - blo));
     }
 }
 
@@ -98,17 +94,13 @@ __global__ __launch_bounds__(kTileThreads) void k_batch_small(BatchPtrs b)
 {
     __shared__ float tile[kTilePoints];
     const int tid = threadIdx.x;
-    const int64_t T = gridDim.x;
+    const int64_t t = blockIdx.x;
     const int64_t total = b.n_small_tiles;
-    const int64_t per = (total + T - 1) / T;
-    const int64_t t0 = (int64_t)blockIdx.x * per, t1 = (t0 + per < total) ? t0 + per : total;
-    if (t0 >= t1)
+    if (t >= total)
         return;
-    int64_t s = find_owner(b.segs, b.n_segs, t0, [](const BatchSeg &g) { return g.ti0; });
     const float kInf = __int_as_float(0x7f800000);
-    for (int64_t t = t0; t < t1; ++t) {
-        while (t >= b.segs[s].ti0 + b.segs[s].tn)
-            ++s;
+    {
+        const int64_t s = find_owner(b.segs, b.hdr->own_small, total, t, [](const BatchSeg &g) { return g.ti0; });
         const BatchSeg &g = b.segs[s];
         const int G = g.tile_bins;
         const int tpb = kTileThreads / G; // lanes per bin: power of two <= 64
@@ -117,9 +109,44 @@ __global__ __launch_bounds__(kTileThreads) void k_batch_small(BatchPtrs b)
         const int64_t bb1 = (bb0 + G < nb) ? bb0 + G : nb;
         const int64_t lo = 1 + split_lo(g.bins, bb0), hi = 1 + split_lo(g.bins, bb1);
         const float *__restrict__ y = b.y_base + g.offset;
-        __syncthreads(); // the previous tile's readers are done
-        for (int64_t q = tid; q < hi - lo; q += kTileThreads)
-            tile[q] = y[lo + q];
+        // Stage [lo, hi): 16-byte loads of the aligned body, all issued before
+        // any use, plus at most 3 head and 3 tail points.
+        const uint64_t addr = (uint64_t)(uintptr_t)(y + lo);
+        int64_t head = (int64_t)(((16u - (unsigned)(addr & 15u)) & 15u) >> 2);
+        head = head < hi - lo ? head : hi - lo;
+        const int64_t body = lo + head;
+        const int64_t nvec = (hi - body) >> 2;
+        const int64_t tail0 = body + 4 * nvec;
+        const f32x4 *__restrict__ v4 = reinterpret_cast<const f32x4 *>(y + body);
+        constexpr int kVecPerThread = kTilePoints / 4 / kTileThreads;
+        f32x4 d[kVecPerThread];
+#pragma unroll
+        for (int u = 0; u < kVecPerThread; ++u) {
+            const int64_t q = tid + (int64_t)u * kTileThreads;
+            if (q < nvec)
+                d[u] = __builtin_nontemporal_load(v4 + q);
+        }
+        float hv = 0.0f;
+        int64_t hq = -1;
+        if (tid < head)
+            hq = lo + tid;
+        else if (tid >= 4 && tid < 4 + (hi - tail0))
+            hq = tail0 + (tid - 4);
+        if (hq >= 0)
+            hv = y[hq];
+#pragma unroll
+        for (int u = 0; u < kVecPerThread; ++u) {
+            const int64_t q = tid + (int64_t)u * kTileThreads;
+            if (q < nvec) {
+                float *dst = tile + (body - lo) + 4 * q;
+                dst[0] = d[u].x;
+                dst[1] = d[u].y;
+                dst[2] = d[u].z;
+                dst[3] = d[u].w;
+            }
+        }
+        if (hq >= 0)
+            tile[hq - lo] = hv;
         __syncthreads();
         const int64_t bin = bb0 + tid / tpb;
         const int sub = tid % tpb;
@@ -161,9 +188,12 @@ __global__ __launch_bounds__(kTileThreads) void k_batch_small(BatchPtrs b)
     }
 }
 
-__global__ __launch_bounds__(1024) void k_batch_compact(BatchPtrs b)
+// One workgroup per series: compaction, then the next-bucket means over P.
+// Identity series (n <= n_out) write their output here.
+__global__ __launch_bounds__(1024) void k_batch_compact_means(BatchPtrs b)
 {
     __shared__ int wave_tot[17];
+    __shared__ int64_t s_m;
     const int tid = threadIdx.x;
     for (int64_t s = blockIdx.x; s < b.n_segs; s += gridDim.x) {
         const BatchSeg &g = b.segs[s];
@@ -186,56 +216,62 @@ __global__ __launch_bounds__(1024) void k_batch_compact(BatchPtrs b)
             }
             if (tid == 0)
                 b.m[s] = n;
-            continue;
+        } else {
+            compact_keys(b.keys + 2 * g.key0, g.bins, n, x, y, P, XP, YP, b.m + s, wave_tot);
         }
-        compact_keys(b.keys + 2 * g.key0, g.bins, n, x, y, P, XP, YP, b.m + s, wave_tot);
-    }
-}
-
-__global__ __launch_bounds__(256) void k_batch_means(BatchPtrs b)
-{
-    for (int64_t s = blockIdx.x; s < b.n_segs; s += gridDim.x) {
-        const BatchSeg &g = b.segs[s];
-        if (g.mode == kSegIdentity)
-            continue;
-        const int64_t m = b.m[s];
+        __threadfence_block();
+        __syncthreads();
+        if (tid == 0)
+            s_m = b.m[s];
+        __syncthreads();
+        const int64_t m = s_m;
         const Split bk = make_split(m - 2, g.B);
-        for (int64_t k = threadIdx.x; k < g.B; k += blockDim.x)
-            bucket_mean_one(b.XP + g.p0, b.YP + g.p0, bk, m, k, b.MX[g.b0 + k], b.MY[g.b0 + k]);
+        for (int64_t k = tid; k < g.B; k += blockDim.x)
+            bucket_mean_one(XP, YP, bk, m, k, b.MX[g.b0 + k], b.MY[g.b0 + k]);
+        __syncthreads();
     }
 }
 
+// Segmented chain, phase 1: one wave per (series, chain segment) walks the
+// segment from every start point (seg_walk).
 __global__ __launch_bounds__(kSegStarts) void k_batch_chain(BatchPtrs b)
 {
     extern __shared__ double lds[];
-    __shared__ uint8_t F[kChaseWindow * kSegStarts];
-    __shared__ unsigned int s_ticket;
-    const int64_t T = gridDim.x;
+    const int64_t u = blockIdx.x;
     const int64_t total = b.n_chain_units;
-    const int64_t per = (total + T - 1) / T;
-    const int64_t u0 = (int64_t)blockIdx.x * per, u1 = (u0 + per < total) ? u0 + per : total;
-    if (u0 >= u1)
+    if (u >= total)
         return;
-    int64_t s = find_owner(b.segs, b.n_segs, u0, [](const BatchSeg &g) { return g.cw0; });
-    for (int64_t u = u0; u < u1; ++u) {
-        while (u >= b.segs[s].cw0 + b.segs[s].cwn)
-            ++s;
+    const int64_t s = find_owner(b.segs, b.hdr->own_chain, total, u, [](const BatchSeg &g) { return g.cw0; });
+    const BatchSeg &g = b.segs[s];
+    const int64_t m = b.m[s];
+    const Split bk = make_split(m - 2, g.B);
+    seg_walk(b.XP + g.p0, b.YP + g.p0, bk, b.MX + g.b0, b.MY + g.b0, u - g.cw0, g.stage_cap, lds,
+             b.path + (size_t)g.c0 * kSegStarts * kSegLen, b.finals + (size_t)g.c0 * kSegStarts);
+}
+
+// Segmented chain, phases 2 and 3: one workgroup per series links its
+// segments (seg_link) and writes every pick mapped through P.
+__global__ __launch_bounds__(1024) void k_batch_link_emit(BatchPtrs b)
+{
+    __shared__ uint8_t F[kChaseWindow * kSegStarts];
+    for (int64_t s = blockIdx.x; s < b.n_segs; s += gridDim.x) {
         const BatchSeg &g = b.segs[s];
+        if (g.mode == kSegIdentity || g.seq)
+            continue;
         const int64_t m = b.m[s];
         const Split bk = make_split(m - 2, g.B);
-        uint8_t *path = b.path + (size_t)g.c0 * kSegStarts * kSegLen;
-        uint8_t *finals = b.finals + (size_t)g.c0 * kSegStarts;
-        __syncthreads(); // LDS of the previous unit is no longer read
-        seg_walk(b.XP + g.p0, b.YP + g.p0, bk, b.MX + g.b0, b.MY + g.b0, u - g.cw0, g.stage_cap, lds, path, finals);
-        __threadfence();
-        __syncthreads();
-        if (threadIdx.x == 0)
-            s_ticket = atomicAdd(&b.counter[s], 1u);
-        __syncthreads();
-        if (s_ticket == (unsigned int)(g.cwn - 1)) {
-            __threadfence();
-            seg_link(finals, b.start + g.c0, g.cwn, F);
+        const uint8_t *path = b.path + (size_t)g.c0 * kSegStarts * kSegLen;
+        uint8_t *start = b.start + g.c0;
+        seg_link(b.finals + (size_t)g.c0 * kSegStarts, start, g.cwn, F);
+        const int64_t *P = b.P + g.p0;
+        int64_t *out = b.out_base + g.out_offset;
+        for (int64_t k = threadIdx.x; k < g.B; k += blockDim.x)
+            out[k + 1] = P[seg_pick(path, start, bk, k)];
+        if (threadIdx.x == 0) {
+            out[0] = P[0];
+            out[g.B + 1] = P[m - 1];
         }
+        __syncthreads();
     }
 }
 
@@ -292,26 +328,6 @@ __global__ __launch_bounds__(kWave) void k_batch_chain_seq(BatchPtrs b)
     }
 }
 
-__global__ __launch_bounds__(256) void k_batch_emit(BatchPtrs b)
-{
-    for (int64_t s = blockIdx.x; s < b.n_segs; s += gridDim.x) {
-        const BatchSeg &g = b.segs[s];
-        if (g.mode == kSegIdentity || g.seq)
-            continue;
-        const int64_t m = b.m[s];
-        const Split bk = make_split(m - 2, g.B);
-        const int64_t *P = b.P + g.p0;
-        int64_t *out = b.out_base + g.out_offset;
-        const uint8_t *path = b.path + (size_t)g.c0 * kSegStarts * kSegLen;
-        for (int64_t k = threadIdx.x; k < g.B; k += blockDim.x)
-            out[k + 1] = P[seg_pick(path, b.start + g.c0, bk, k)];
-        if (threadIdx.x == 0) {
-            out[0] = P[0];
-            out[g.B + 1] = P[m - 1];
-        }
-    }
-}
-
 // ------------------------------------------------------------------ launches
 
 static unsigned cap_grid(int64_t want, int64_t cap)
@@ -321,8 +337,7 @@ static unsigned cap_grid(int64_t want, int64_t cap)
 
 hipError_t launch_batch_init(const BatchPtrs &b, hipStream_t s)
 {
-    const int64_t work = b.n_keys > b.n_segs ? b.n_keys : b.n_segs;
-    hipLaunchKernelGGL(k_batch_init, dim3(cap_grid((work + 255) / 256, 8192)), dim3(256), 0, s, b);
+    hipLaunchKernelGGL(k_batch_init, dim3(cap_grid((b.n_keys + 255) / 256, 8192)), dim3(256), 0, s, b);
     return hipGetLastError();
 }
 
@@ -330,7 +345,7 @@ hipError_t launch_batch_large(const BatchPtrs &b, int unroll, hipStream_t s)
 {
     if (b.n_large_items == 0)
         return hipSuccess;
-    const unsigned grid = cap_grid((b.n_large_items + 3) / 4, 8192);
+    const unsigned grid = cap_grid((b.n_large_items + 3) / 4, 0x7fffffff);
     switch (unroll) {
     case 1:
         hipLaunchKernelGGL(k_batch_large<1>, dim3(grid), dim3(256), 0, s, b);
@@ -352,19 +367,13 @@ hipError_t launch_batch_small(const BatchPtrs &b, hipStream_t s)
 {
     if (b.n_small_tiles == 0)
         return hipSuccess;
-    hipLaunchKernelGGL(k_batch_small, dim3(cap_grid(b.n_small_tiles, 4096)), dim3(kTileThreads), 0, s, b);
+    hipLaunchKernelGGL(k_batch_small, dim3(cap_grid(b.n_small_tiles, 0x7fffffff)), dim3(kTileThreads), 0, s, b);
     return hipGetLastError();
 }
 
-hipError_t launch_batch_compact(const BatchPtrs &b, hipStream_t s)
+hipError_t launch_batch_compact_means(const BatchPtrs &b, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_batch_compact, dim3(cap_grid(b.n_segs, 4096)), dim3(1024), 0, s, b);
-    return hipGetLastError();
-}
-
-hipError_t launch_batch_means(const BatchPtrs &b, hipStream_t s)
-{
-    hipLaunchKernelGGL(k_batch_means, dim3(cap_grid(b.n_segs, 8192)), dim3(256), 0, s, b);
+    hipLaunchKernelGGL(k_batch_compact_means, dim3(cap_grid(b.n_segs, 4096)), dim3(1024), 0, s, b);
     return hipGetLastError();
 }
 
@@ -373,7 +382,7 @@ hipError_t launch_batch_chain(const BatchPtrs &b, hipStream_t s)
     if (b.n_chain_units == 0)
         return hipSuccess;
     const size_t lds = (size_t)(2 * b.stage_cap_max + 2 * kSegLen) * sizeof(double);
-    hipLaunchKernelGGL(k_batch_chain, dim3(cap_grid(b.n_chain_units, 16384)), dim3(kSegStarts), lds, s, b);
+    hipLaunchKernelGGL(k_batch_chain, dim3(cap_grid(b.n_chain_units, 0x7fffffff)), dim3(kSegStarts), lds, s, b);
     return hipGetLastError();
 }
 
@@ -383,9 +392,9 @@ hipError_t launch_batch_chain_seq(const BatchPtrs &b, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_batch_emit(const BatchPtrs &b, hipStream_t s)
+hipError_t launch_batch_link_emit(const BatchPtrs &b, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_batch_emit, dim3(cap_grid(b.n_segs, 8192)), dim3(256), 0, s, b);
+    hipLaunchKernelGGL(k_batch_link_emit, dim3(cap_grid(b.n_segs, 4096)), dim3(1024), 0, s, b);
     return hipGetLastError();
 }
 

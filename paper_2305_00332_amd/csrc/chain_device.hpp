@@ -107,24 +107,25 @@ __device__ inline void seg_walk(const int64_t *__restrict__ XP, const float *__r
 }
 
 // Phase 2: follow the true start through the segments. The start of segment
-// t+1 is the last pick of segment t walked from its own start. One LDS lookup
-// per segment (finals staged in LDS windows of kChaseWindow segments).
-// Call with one full wave after an acquire fence; F holds kChaseWindow *
-// kSegStarts bytes of LDS.
+// t+1 is the last pick of segment t walked from its own start: one LDS lookup
+// per segment, by thread 0, with the finals staged in LDS windows of
+// kChaseWindow segments by the whole workgroup. Runs in a later kernel than
+// the walks, so their finals are visible without any fence. The starts go to
+// `start` (global) and are visible to the whole workgroup on return.
 __device__ inline void seg_link(const uint8_t *finals, uint8_t *start, int64_t S, uint8_t *F)
 {
-    const int lane = threadIdx.x;
+    const int tid = threadIdx.x;
     int cur = 0;
-    if (lane == 0)
+    if (tid == 0)
         start[0] = 0;
     for (int64_t w0 = 0; w0 < S - 1; w0 += kChaseWindow) {
         const int64_t w1 = (w0 + kChaseWindow < S - 1) ? w0 + kChaseWindow : S - 1;
         const int64_t words = (w1 - w0) * kSegStarts / 4;
         const uint32_t *src = reinterpret_cast<const uint32_t *>(finals + w0 * kSegStarts);
-        for (int64_t q = lane; q < words; q += kSegStarts)
+        for (int64_t q = tid; q < words; q += blockDim.x)
             reinterpret_cast<uint32_t *>(F)[q] = src[q];
         __syncthreads();
-        if (lane == 0) {
+        if (tid == 0) {
             for (int64_t t = w0; t < w1; ++t) {
                 cur = F[(t - w0) * kSegStarts + cur];
                 start[t + 1] = (uint8_t)cur;
@@ -132,6 +133,8 @@ __device__ inline void seg_link(const uint8_t *finals, uint8_t *start, int64_t S
         }
         __syncthreads();
     }
+    __threadfence_block();
+    __syncthreads();
 }
 
 // Phase 3 for one bucket: position of the pick of bucket k.

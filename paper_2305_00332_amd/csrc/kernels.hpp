@@ -23,10 +23,10 @@ constexpr int kChainStage = 1024;
 
 // Segmented chain: buckets per segment, start points per segment (one lane
 // each, so buckets may hold at most this many points), segments per LDS
-// window while the last block links the segments.
+// window while the segments are linked.
 constexpr int kSegLen = 32;
 constexpr int kSegStarts = 64;
-constexpr int kChaseWindow = 256;
+constexpr int kChaseWindow = 512;
 
 struct SegChainArgs {
     const int64_t *XP;     // raw x of the points (NULL: x = position)
@@ -38,7 +38,6 @@ struct SegChainArgs {
     uint8_t *path;         // [S][kSegStarts][kSegLen]: pick offset inside its bucket
     uint8_t *finals;       // [S][kSegStarts]: pick offset in the segment's last bucket
     uint8_t *start;        // [S]: start lane of segment s on the chain from point 0
-    unsigned int *counter; // zeroed by the means kernel before the chain runs
     int64_t S;             // segments
     int stage_cap;         // LDS points per segment (kSegLen * bucket-size bound)
 };
@@ -76,16 +75,23 @@ struct BatchSeg {
     int32_t seq;        // 1: sequential chain
 };
 
+// Coarse owner tables: entry q (0..kOwnerTable) holds the series owning unit
+// min(total - 1, floor(q * total / kOwnerTable)) of a flat work space; unit i
+// with q = floor(i * kOwnerTable / total) is owned by a series between
+// entries q and q + 1.
+constexpr int kOwnerTable = 1024;
+
 struct BatchHeader {
     int64_t n_segs;
     int64_t n_keys;
     int64_t n_large_items, n_small_tiles, n_chain_units;
     int64_t max_stage_cap;
-    int64_t off_segs, off_keys, off_P, off_XP, off_YP, off_m, off_MX, off_MY, off_path, off_finals, off_start,
-        off_counter;
+    int64_t off_segs, off_keys, off_P, off_XP, off_YP, off_m, off_MX, off_MY, off_path, off_finals, off_start;
+    int32_t own_large[kOwnerTable + 1], own_small[kOwnerTable + 1], own_chain[kOwnerTable + 1];
 };
 
 struct BatchPtrs {
+    const BatchHeader *hdr; // device copy of the header (owner tables)
     const BatchSeg *segs;
     int64_t n_segs;
     int xk;
@@ -98,7 +104,6 @@ struct BatchPtrs {
     int64_t *m;
     double *MX, *MY;
     uint8_t *path, *finals, *start;
-    unsigned int *counter;
     int64_t n_keys, n_large_items, n_small_tiles, n_chain_units;
     int stage_cap_max;
 };
@@ -106,11 +111,10 @@ struct BatchPtrs {
 hipError_t launch_batch_init(const BatchPtrs &b, hipStream_t s);
 hipError_t launch_batch_large(const BatchPtrs &b, int unroll, hipStream_t s);
 hipError_t launch_batch_small(const BatchPtrs &b, hipStream_t s);
-hipError_t launch_batch_compact(const BatchPtrs &b, hipStream_t s);
-hipError_t launch_batch_means(const BatchPtrs &b, hipStream_t s);
+hipError_t launch_batch_compact_means(const BatchPtrs &b, hipStream_t s);
 hipError_t launch_batch_chain(const BatchPtrs &b, hipStream_t s);
+hipError_t launch_batch_link_emit(const BatchPtrs &b, hipStream_t s);
 hipError_t launch_batch_chain_seq(const BatchPtrs &b, hipStream_t s);
-hipError_t launch_batch_emit(const BatchPtrs &b, hipStream_t s);
 
 inline int64_t seg_count(int64_t B) { return (B + kSegLen - 1) / kSegLen; }
 inline size_t seg_path_bytes(int64_t B) { return (size_t)seg_count(B) * kSegStarts * kSegLen; }
@@ -121,14 +125,17 @@ hipError_t launch_minmax_bin_reduce(const float *y, const MinMaxGeom &g, int unr
                                     hipStream_t s);
 hipError_t launch_preselect_compact(const unsigned long long *keys, const Split &bins, int64_t n, const int64_t *x,
                                     const float *y, int64_t *P, int64_t *XP, float *YP, int64_t *m_out, hipStream_t s);
+hipError_t launch_preselect_compact_means(const unsigned long long *keys, const Split &bins, int64_t n,
+                                          const int64_t *x, const float *y, int64_t *P, int64_t *XP, float *YP,
+                                          int64_t *m_out, int64_t B, double *MX, double *MY, hipStream_t s);
 hipError_t launch_preselect_all(int64_t n, const int64_t *x, const float *y, int64_t *P, int64_t *XP, float *YP,
                                 int64_t *m_out, hipStream_t s);
 hipError_t launch_iota(int64_t *out, int64_t n, int64_t *count_out, hipStream_t s);
 
 hipError_t launch_bucket_mean_small(const int64_t *XP, const float *YP, const int64_t *m_ptr, int64_t m_const,
-                                    int64_t B, double *MX, double *MY, unsigned int *zero_counter, hipStream_t s);
+                                    int64_t B, double *MX, double *MY, hipStream_t s);
 hipError_t launch_bucket_mean_wide(const int64_t *X, const float *Y, int64_t m, int64_t B, double *MX, double *MY,
-                                   unsigned int *zero_counter, hipStream_t s);
+                                   hipStream_t s);
 hipError_t launch_lttb_chain(const int64_t *XP, const float *YP, const int64_t *m_ptr, int64_t m_const, int64_t B,
                              const double *MX, const double *MY, const int64_t *Pmap, int64_t *out, hipStream_t s);
 hipError_t launch_lttb_chain_seg(const SegChainArgs &a, const int64_t *Pmap, int64_t *out, hipStream_t s);

@@ -53,11 +53,9 @@ __global__ __launch_bounds__(256) void k_preselect_all(int64_t n, const int64_t 
 __global__ __launch_bounds__(256) void k_bucket_mean_small(const int64_t *__restrict__ XP, const float *__restrict__ YP,
                                                            const int64_t *__restrict__ m_ptr, int64_t m_const,
                                                            int64_t B, double *__restrict__ MX,
-                                                           double *__restrict__ MY, unsigned int *zero_counter)
+                                                           double *__restrict__ MY)
 {
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k == 0 && zero_counter)
-        *zero_counter = 0u;
     if (k >= B)
         return;
     const int64_t m = m_ptr ? *m_ptr : m_const;
@@ -68,11 +66,9 @@ __global__ __launch_bounds__(256) void k_bucket_mean_small(const int64_t *__rest
 // One workgroup (256 threads) per bucket (whole-series LTTB: large buckets).
 __global__ __launch_bounds__(256) void k_bucket_mean_wide(const int64_t *__restrict__ X, const float *__restrict__ Y,
                                                           int64_t m, int64_t B, double *__restrict__ MX,
-                                                          double *__restrict__ MY, unsigned int *zero_counter)
+                                                          double *__restrict__ MY)
 {
     __shared__ int64_t s_limb[4][9];
-    if (blockIdx.x == 0 && threadIdx.x == 0 && zero_counter)
-        *zero_counter = 0u;
     __shared__ int64_t s_xlo[4], s_xhi[4];
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     const Split bk = make_split(m - 2, B);
@@ -256,48 +252,30 @@ __global__ __launch_bounds__(256) void k_lttb_chain(const int64_t *__restrict__ 
 
 // Segmented chain (same picks as k_lttb_chain, in O(B / kSegLen + kSegLen)
 // dependent steps instead of B). Buckets are cut into segments of kSegLen.
-// Phase 1, one wave per segment: a segment's walk depends only on its start
-// point, which lies in the bucket just before the segment (point 0 for the
-// first segment); lane l walks the segment from start candidate l, with the
-// segment's points and means staged in LDS, and records each pick's offset
-// inside its bucket. Every walk evaluates the same binary64 area on the same
-// operands as the sequential pass, so a walk from the true start repeats the
-// sequential picks exactly. Phase 2, by the last block to finish (counted
-// with one atomic, no waiting): follow the true start through the segments
-// (start of segment s+1 = last pick of segment s from its start), one LDS
-// lookup per segment. k_lttb_chain_emit then writes every pick in parallel.
+// k_lttb_chain_seg (one wave per segment) walks each segment from every
+// possible start point (seg_walk); k_lttb_chain_link_emit (one workgroup)
+// then follows the true start from point 0 through the segments (seg_link)
+// and writes every pick, mapped through Pmap when given.
 __global__ __launch_bounds__(kSegStarts) void k_lttb_chain_seg(SegChainArgs a)
 {
     extern __shared__ double lds[];
-    __shared__ uint8_t F[kChaseWindow * kSegStarts];
-    __shared__ unsigned int s_ticket;
     const int64_t m = a.m_ptr ? *a.m_ptr : a.m_const;
     const Split bk = make_split(m - 2, a.B);
     seg_walk(a.XP, a.YP, bk, a.MX, a.MY, (int64_t)blockIdx.x, a.stage_cap, lds, a.path, a.finals);
-    __threadfence();
-    __syncthreads();
-    if (threadIdx.x == 0)
-        s_ticket = atomicAdd(a.counter, 1u);
-    __syncthreads();
-    if (s_ticket != (unsigned int)(a.S - 1))
-        return;
-    __threadfence();
-    seg_link(a.finals, a.start, a.S, F);
-    if (threadIdx.x == 0)
-        *a.counter = 0u;
 }
 
-__global__ __launch_bounds__(256) void k_lttb_chain_emit(SegChainArgs a, const int64_t *__restrict__ Pmap,
-                                                         int64_t *__restrict__ out)
+__global__ __launch_bounds__(1024) void k_lttb_chain_link_emit(SegChainArgs a, const int64_t *__restrict__ Pmap,
+                                                               int64_t *__restrict__ out)
 {
+    __shared__ uint8_t F[kChaseWindow * kSegStarts];
     const int64_t m = a.m_ptr ? *a.m_ptr : a.m_const;
     const Split bk = make_split(m - 2, a.B);
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < a.B; k += stride) {
+    seg_link(a.finals, a.start, a.S, F);
+    for (int64_t k = threadIdx.x; k < a.B; k += blockDim.x) {
         const int64_t sel = seg_pick(a.path, a.start, bk, k);
         out[k + 1] = Pmap ? Pmap[sel] : sel;
     }
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (threadIdx.x == 0) {
         out[0] = Pmap ? Pmap[0] : 0;
         out[a.B + 1] = Pmap ? Pmap[m - 1] : m - 1;
     }
@@ -403,18 +381,17 @@ hipError_t launch_preselect_all(int64_t n, const int64_t *x, const float *y, int
 }
 
 hipError_t launch_bucket_mean_small(const int64_t *XP, const float *YP, const int64_t *m_ptr, int64_t m_const,
-                                    int64_t B, double *MX, double *MY, unsigned int *zero_counter, hipStream_t s)
+                                    int64_t B, double *MX, double *MY, hipStream_t s)
 {
     hipLaunchKernelGGL(k_bucket_mean_small, dim3(grid_for(B, 256, 1 << 30)), dim3(256), 0, s, XP, YP, m_ptr, m_const,
-                       B, MX, MY, zero_counter);
+                       B, MX, MY);
     return hipGetLastError();
 }
 
 hipError_t launch_bucket_mean_wide(const int64_t *X, const float *Y, int64_t m, int64_t B, double *MX, double *MY,
-                                   unsigned int *zero_counter, hipStream_t s)
+                                   hipStream_t s)
 {
-    hipLaunchKernelGGL(k_bucket_mean_wide, dim3(grid_for(B, 1, 65536)), dim3(256), 0, s, X, Y, m, B, MX, MY,
-                       zero_counter);
+    hipLaunchKernelGGL(k_bucket_mean_wide, dim3(grid_for(B, 1, 65536)), dim3(256), 0, s, X, Y, m, B, MX, MY);
     return hipGetLastError();
 }
 
@@ -422,12 +399,12 @@ hipError_t launch_lttb_chain_seg(const SegChainArgs &a, const int64_t *Pmap, int
 {
     if (a.S > 0x7fffffff)
         return hipErrorInvalidConfiguration;
-    const size_t lds = (size_t)(2 * a.stage_cap + 2 * kSegLen) * sizeof(double);
+    const size_t lds = (size_t)(2 * a.stage_cap + 2 * kSegLen) * sizeof(double); // points and means of a segment
     hipLaunchKernelGGL(k_lttb_chain_seg, dim3((unsigned)a.S), dim3(kSegStarts), lds, s, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess)
         return e;
-    hipLaunchKernelGGL(k_lttb_chain_emit, dim3(grid_for(a.B, 256, 65536)), dim3(256), 0, s, a, Pmap, out);
+    hipLaunchKernelGGL(k_lttb_chain_link_emit, dim3(1), dim3(1024), 0, s, a, Pmap, out);
     return hipGetLastError();
 }
 

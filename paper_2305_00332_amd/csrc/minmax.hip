@@ -14,6 +14,7 @@
 // low 32 bits = offset of the index inside its bin (min key) or its
 // complement (max key), so a larger value wins the max, a smaller the min,
 // and among equal values the lowest index wins both.
+#include "chain_device.hpp"
 #include "device_common.hpp"
 #include "kernels.hpp"
 #include "minmax_device.hpp"
@@ -72,6 +73,27 @@ __global__ __launch_bounds__(1024) void k_preselect_compact(const unsigned long 
     compact_keys(keys, bins, n, x, y, P, XP, YP, m_out, wave_tot);
 }
 
+// Compaction followed, in the same workgroup, by the next-bucket means over P
+// (one thread per bucket).
+__global__ __launch_bounds__(1024) void k_preselect_compact_means(
+    const unsigned long long *__restrict__ keys, Split bins, int64_t n, const int64_t *__restrict__ x,
+    const float *__restrict__ y, int64_t *__restrict__ P, int64_t *__restrict__ XP, float *__restrict__ YP,
+    int64_t *__restrict__ m_out, int64_t B, double *__restrict__ MX, double *__restrict__ MY)
+{
+    __shared__ int wave_tot[17];
+    __shared__ int64_t s_m;
+    compact_keys(keys, bins, n, x, y, P, XP, YP, m_out, wave_tot);
+    __threadfence_block();
+    __syncthreads();
+    if (threadIdx.x == 0)
+        s_m = *m_out;
+    __syncthreads();
+    const int64_t m = s_m;
+    const Split bk = make_split(m - 2, B);
+    for (int64_t k = threadIdx.x; k < B; k += blockDim.x)
+        bucket_mean_one(XP, YP, bk, m, k, MX[k], MY[k]);
+}
+
 // ---------------------------------------------------------------- launches
 
 hipError_t launch_init_keys(unsigned long long *keys, int64_t nb, hipStream_t s)
@@ -103,6 +125,15 @@ hipError_t launch_minmax_bin_reduce(const float *y, const MinMaxGeom &g, int unr
         hipLaunchKernelGGL(k_minmax_bin_reduce<4>, dim3((unsigned)blocks), dim3(256), 0, s, y, g, keys);
         break;
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_preselect_compact_means(const unsigned long long *keys, const Split &bins, int64_t n,
+                                          const int64_t *x, const float *y, int64_t *P, int64_t *XP, float *YP,
+                                          int64_t *m_out, int64_t B, double *MX, double *MY, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_preselect_compact_means, dim3(1), dim3(1024), 0, s, keys, bins, n, x, y, P, XP, YP, m_out, B,
+                       MX, MY);
     return hipGetLastError();
 }
 

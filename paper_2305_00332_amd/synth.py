@@ -116,9 +116,11 @@ def choice(values, count: int, seed: int) -> np.ndarray:
     return rng.choice(np.asarray(values), size=count)
 
 
-def batch_series(lengths, seed: int, device="cpu", with_x: bool = True, noise_sigma: float = 0.5):
+def batch_series(lengths, seed: int, device="cpu", with_x: bool = True, noise_sigma: float = 0.5,
+                 sinusoids: bool = False, periods=(1e3, 1e5, 1e7), amplitude: float = 10.0):
     """Series of the given lengths stored back to back: y = random walk + N(0, 0.5^2)
     noise (one walk across the whole buffer, so each series is a walk segment),
+    optionally + sinusoids of the given periods (in samples of the buffer),
     x = one strictly increasing irregular int64 timeline (each series a slice).
     Returns (x, y, offsets)."""
     lengths = np.asarray(lengths, dtype=np.int64)
@@ -128,9 +130,15 @@ def batch_series(lengths, seed: int, device="cpu", with_x: bool = True, noise_si
     g = _gen(seed + 5_000_011, device)
     for lo in range(0, total, _CHUNK):
         hi = min(total, lo + _CHUNK)
-        noise = torch.randn(hi - lo, generator=g, dtype=torch.float64, device=device) * noise_sigma
-        y[lo:hi] = (y[lo:hi].to(torch.float64) + noise).to(torch.float32)
-        del noise
+        v = y[lo:hi].to(torch.float64) + torch.randn(hi - lo, generator=g, dtype=torch.float64,
+                                                      device=device) * noise_sigma
+        if sinusoids:
+            i = torch.arange(lo, hi, dtype=torch.float64, device=device)
+            for p, ph in zip(periods, (0.3, 1.7, 4.1)):
+                v.add_(torch.sin(i * (2 * math.pi / p) + ph) * amplitude)
+            del i
+        y[lo:hi] = v.to(torch.float32)
+        del v
     x = irregular_x(total, seed + 6_000_011, device=device) if with_x else None
     return x, y, offsets
 
