@@ -25,7 +25,8 @@ sys.path.insert(0, ROOT)
 METRIC = "Gpts/s & HBM GB/s, MinMaxLTTB n=1e9; batched/served vs plain; p50/p99 ms"
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "minmax_bin_reduce_traffic.json")
-KERNEL_SOURCES = [os.path.join(ROOT, "paper_2305_00332_amd", "csrc", f) for f in ("minmax.hip", "device_common.hpp")]
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2305_00332_amd", "csrc", f)
+                  for f in ("minmax.hip", "minmax_device.hpp", "device_common.hpp")]
 
 
 def log(msg):
@@ -72,6 +73,8 @@ def main():
     ap.add_argument("--rates", type=str, default="100,500,1000,2000,5000")
     ap.add_argument("--serve-seconds", type=float, default=2.0)
     ap.add_argument("--burst", type=int, default=2000)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run a plain 1 GiB device copy (the reference kernel for HBM counter scaling)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -88,6 +91,14 @@ def main():
     result = {"metric": METRIC}
     if not args.skip_headline:
         result.update(bench_headline(args))
+    if args.calibrate_copy:
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        result["copy_calibration_bytes"] = {"read": 1 << 30, "write": 1 << 30}
+        del src, dst
     if not args.skip_batched:
         result["batched"] = bench_batched(args)
     if not args.skip_served:
