@@ -67,6 +67,7 @@ def main():
     ap.add_argument("--cpu-reps", type=int, default=3)
     ap.add_argument("--skip-headline", action="store_true")
     ap.add_argument("--skip-batched", action="store_true")
+    ap.add_argument("--skip-comparator", action="store_true")
     ap.add_argument("--skip-served", action="store_true")
     ap.add_argument("--batch-series", type=int, default=4096)
     ap.add_argument("--pool-series", type=int, default=512)
@@ -99,6 +100,8 @@ def main():
         torch.cuda.synchronize()
         result["copy_calibration_bytes"] = {"read": 1 << 30, "write": 1 << 30}
         del src, dst
+    if not args.skip_comparator:
+        result["comparator"] = bench_comparator(args)
     if not args.skip_batched:
         result["batched"] = bench_batched(args)
     if not args.skip_served:
@@ -201,6 +204,56 @@ def bench_headline(args):
     return result
 
 
+def bench_comparator(args):
+    """Whole-series LTTB vs MinMaxLTTB on one 1e8-point series (random walk +
+    sinusoids + noise + spikes, int64 irregular timestamps), n_out=2000: GPU
+    times for both, and the oracle's single-thread CPU times for both (the
+    paper's comparison, section 3.2), every output checked against the oracle."""
+    import numpy as np
+    import torch
+
+    import oracle
+    from paper_2305_00332_amd import ops, synth
+
+    n, n_out = 100_000_000, 2000
+    log(f"comparator: generating {n} points")
+    x, y = synth.composite_series(n, 2, device="cuda")
+    torch.cuda.synchronize()
+    y_np, x_np = y.cpu().numpy(), x.cpu().numpy()
+
+    def gpu_time(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            out = fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / reps, out
+
+    res = {"workload": f"one series, n={n}, float32 random walk + 3 sinusoids + noise + 0.01% spikes (seed 2), "
+                       f"int64 irregular x; n_out={n_out}", "n": n, "n_out": n_out}
+    log("comparator: GPU whole-series LTTB")
+    t_l, out_l = gpu_time(lambda: ops.lttb(y, n_out, x=x), 3)
+    c0 = time.perf_counter()
+    want_l = oracle.lttb(y_np, n_out, x_np)
+    t_lc = time.perf_counter() - c0
+    res["lttb"] = {"gpu_ms": round(t_l * 1e3, 4), "gpu_gpts_per_s": round(n / t_l / 1e9, 3),
+                   "cpu_oracle_s": round(t_lc, 3), "parity_vs_oracle": bool(np.array_equal(out_l.cpu().numpy(), want_l))}
+    for r_ps in (2, 4, 8):
+        log(f"comparator: MinMaxLTTB r_ps={r_ps}")
+        t_m, out_m = gpu_time(lambda: ops.minmaxlttb(y, n_out, r_ps, x=x), 10)
+        c0 = time.perf_counter()
+        want_m = oracle.minmaxlttb(y_np, n_out, r_ps, x_np)
+        t_mc = time.perf_counter() - c0
+        res[f"minmaxlttb_r{r_ps}"] = {
+            "gpu_ms": round(t_m * 1e3, 4), "gpu_gpts_per_s": round(n / t_m / 1e9, 3), "cpu_oracle_s": round(t_mc, 3),
+            "gpu_speedup_vs_gpu_lttb": round(t_l / t_m, 2), "cpu_speedup_vs_cpu_lttb": round(t_lc / t_mc, 2),
+            "parity_vs_oracle": bool(np.array_equal(out_m.cpu().numpy(), want_m))}
+    del x, y, y_np, x_np
+    torch.cuda.empty_cache()
+    return res
+
+
 def bench_batched(args):
     """Many series of uneven length: one batched call vs one call per series."""
     import numpy as np
@@ -238,6 +291,42 @@ def bench_batched(args):
         tot, cnt = ops.profile_read(k)
         if cnt:
             kern[k] = round(tot / cnt, 4)
+    # the same batch replayed from a captured graph (a dashboard refreshing the same series)
+    gstream = torch.cuda.Stream()
+    ops.set_graph_cache(2)
+    with torch.cuda.stream(gstream):
+        for _ in range(2):
+            ops.minmaxlttb_batched(y, segs, x_base=x, out=out, ws=ws, table=table)
+    gstream.synchronize()
+    t0 = time.perf_counter()
+    with torch.cuda.stream(gstream):
+        for _ in range(reps):
+            ops.minmaxlttb_batched(y, segs, x_base=x, out=out, ws=ws, table=table)
+    gstream.synchronize()
+    t_graph = (time.perf_counter() - t0) / reps
+    graph_stats = ops.graph_cache_stats()
+    ops.set_graph_cache(0)
+    # a serving-sized batch of 16 series: eager vs graph replay
+    small = segs[:16]
+    small_table = ops.segment_table(small)
+    small_out = torch.empty(max(small_table[2], 1), dtype=torch.int64, device="cuda")
+    small_ws = torch.empty(ops.batched_workspace_size(small), dtype=torch.uint8, device="cuda")
+
+    def time_small(graph):
+        ops.set_graph_cache(2 if graph else 0)
+        with torch.cuda.stream(gstream):
+            for _ in range(3):
+                ops.minmaxlttb_batched(y, small, x_base=x, out=small_out, ws=small_ws, table=small_table)
+        gstream.synchronize()
+        t0 = time.perf_counter()
+        with torch.cuda.stream(gstream):
+            for _ in range(50):
+                ops.minmaxlttb_batched(y, small, x_base=x, out=small_out, ws=small_ws, table=small_table)
+        gstream.synchronize()
+        ops.set_graph_cache(0)
+        return (time.perf_counter() - t0) / 50
+
+    t_small_eager, t_small_graph = time_small(False), time_small(True)
     log("batched: plain per-series calls")
     plain = torch.empty_like(out)
     ws1 = torch.empty(max(ops.workspace_size(1, no, 4) for no in (200, 500, 1000, 2000)), dtype=torch.uint8,
@@ -261,6 +350,9 @@ def bench_batched(args):
            "points": pts, "ms": round(t_batched * 1e3, 4), "gpts_per_s": round(pts / t_batched / 1e9, 3),
            "plain_ms": round(t_plain * 1e3, 4), "plain_gpts_per_s": round(pts / t_plain / 1e9, 3),
            "speedup_vs_plain": round(t_plain / t_batched, 3), "kernel_ms": kern,
+           "graph_replay_ms": round(t_graph * 1e3, 4), "graph_stats": list(graph_stats),
+           "small_batch_16": {"eager_ms": round(t_small_eager * 1e3, 4), "graph_ms": round(t_small_graph * 1e3, 4),
+                              "points": int(sum(n for _, n, _, _ in small))},
            "identical_to_plain": bool(torch.equal(out[: table[2]], plain[: table[2]]))}
     del x, y, out, plain, ws, ws1
     torch.cuda.empty_cache()

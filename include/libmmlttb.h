@@ -127,6 +127,19 @@ size_t mmlttb_batched_workspace_size(const mmlttb_segment_t *segs_host, int64_t 
 int mmlttb_minmaxlttb_batched(int xk, const int64_t *x_base, const float *y_base, const mmlttb_segment_t *segs_host,
                               int64_t n_segs, int64_t *out_idx_base, void *ws, size_t ws_bytes, void *stream);
 
+/* Graph replay of batched calls. With max_graphs > 0, a batched call on a
+ * non-default stream is captured into a HIP graph (segment-table upload from
+ * a pinned host copy plus every kernel) the first time its exact arguments are
+ * seen (pointers, stream, x kind, tuning, segment table), and replayed by
+ * later calls with the same arguments; at most max_graphs graphs are kept
+ * (least recently used evicted, after its last replay completes). The cache
+ * holds pinned HOST memory only. 0 (the default) disables it and releases
+ * every graph. Process-wide; not thread-safe with concurrent calls.
+ * mmlttb_graph_cache_stats reports entries held, replays and captures since
+ * the cache was last disabled. */
+int mmlttb_set_graph_cache(int max_graphs);
+int mmlttb_graph_cache_stats(int64_t *entries, int64_t *hits, int64_t *captures);
+
 /* Execution tuning (never changes results): unroll = 16-byte loads in flight
  * per lane of the MinMax stream (1, 2, 4 or 8); chunk = points per MinMax work
  * item (rounded up to a multiple of 256*unroll); chain = LTTB pass form:

@@ -19,5 +19,7 @@ from .ops import (  # noqa: F401
     profile_reset,
     workspace_size,
     set_tuning,
+    set_graph_cache,
+    graph_cache_stats,
     get_tuning,
 )

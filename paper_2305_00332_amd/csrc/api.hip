@@ -422,6 +422,155 @@ int plan_batch(int xk, const mmlttb_segment_t *in, int64_t n_segs, BatchPlan &pl
     return MMLTTB_OK;
 }
 
+// ---------------------------------------------------------------- batch launch
+
+void fill_table(char *dst, const BatchPlan &plan)
+{
+    const BatchHeader &h = plan.h;
+    memset(dst, 0, (size_t)h.off_keys);
+    memcpy(dst, &h, sizeof(h));
+    memcpy(dst + h.off_segs, plan.segs.data(), plan.segs.size() * sizeof(BatchSeg));
+}
+
+// Enqueue the batched kernels; the header and segment table are already
+// (being) copied into ws on stream s.
+int enqueue_batch(const BatchPlan &plan, int xk, const int64_t *x_base, const float *y_base, int64_t *out_idx_base,
+                  void *ws, hipStream_t s)
+{
+    const BatchHeader &h = plan.h;
+    BatchPtrs b;
+    b.hdr = at<BatchHeader>(ws, 0);
+    b.segs = at<BatchSeg>(ws, h.off_segs);
+    b.n_segs = h.n_segs;
+    b.xk = xk;
+    b.x_base = x_base;
+    b.y_base = y_base;
+    b.out_base = out_idx_base;
+    b.keys = at<unsigned long long>(ws, h.off_keys);
+    b.P = at<int64_t>(ws, h.off_P);
+    b.XP = at<int64_t>(ws, h.off_XP);
+    b.YP = at<float>(ws, h.off_YP);
+    b.m = at<int64_t>(ws, h.off_m);
+    b.MX = at<double>(ws, h.off_MX);
+    b.MY = at<double>(ws, h.off_MY);
+    b.path = at<uint8_t>(ws, h.off_path);
+    b.finals = at<uint8_t>(ws, h.off_finals);
+    b.start = at<uint8_t>(ws, h.off_start);
+    b.n_keys = h.n_keys;
+    b.n_large_items = h.n_large_items;
+    b.n_small_tiles = h.n_small_tiles;
+    b.n_chain_units = h.n_chain_units;
+    b.stage_cap_max = (int)(h.max_stage_cap > 0 ? h.max_stage_cap : kSegLen);
+    if (h.n_large_items > 0) {
+        MMLTTB_LAUNCH("batch_init", s, launch_batch_init(b, s));
+        MMLTTB_LAUNCH("batch_minmax_large", s, launch_batch_large(b, tuning().unroll, s));
+    }
+    if (h.n_small_tiles > 0) {
+        MMLTTB_LAUNCH("batch_minmax_small", s, launch_batch_small(b, s));
+    }
+    MMLTTB_LAUNCH("batch_compact_means", s, launch_batch_compact_means(b, s));
+    MMLTTB_LAUNCH("batch_chain", s, launch_batch_chain(b, s));
+    if (plan.any_seq) {
+        MMLTTB_LAUNCH("batch_chain_seq", s, launch_batch_chain_seq(b, s));
+    }
+    if (h.n_chain_units > 0) {
+        MMLTTB_LAUNCH("batch_link_emit", s, launch_batch_link_emit(b, s));
+    }
+    return MMLTTB_OK;
+}
+
+// ---------------------------------------------------------------- graph cache
+// Captured batched calls, keyed by everything that shapes the launch sequence
+// and its arguments: pointers, stream, x kind, tuning and the segment table.
+
+struct GraphEntry {
+    uint64_t hash = 0;
+    std::vector<char> key;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipEvent_t done = nullptr; // recorded after the entry's latest launch
+    void *pinned = nullptr;    // header + segment table, source of the upload node
+    uint64_t last_use = 0;
+};
+
+int g_graph_cap = 0;
+std::vector<GraphEntry> g_graphs;
+uint64_t g_graph_clock = 0;
+int64_t g_graph_hits = 0, g_graph_captures = 0;
+
+uint64_t fnv1a(const std::vector<char> &v)
+{
+    uint64_t h = 1469598103934665603ull;
+    for (char c : v) {
+        h ^= (unsigned char)c;
+        h *= 1099511628211ull;
+    }
+    return h;
+}
+
+std::vector<char> graph_key(int xk, const int64_t *x_base, const float *y_base, const mmlttb_segment_t *segs,
+                            int64_t n_segs, int64_t *out, void *ws, size_t ws_bytes, hipStream_t s)
+{
+    const Tuning &t = tuning();
+    struct Head {
+        int xk, unroll, chain, pad;
+        int64_t chunk, n_segs;
+        const void *x, *y, *out, *ws, *stream;
+        size_t ws_bytes;
+    } head{xk, t.unroll, t.chain, 0, t.chunk, n_segs, x_base, y_base, out, ws, (const void *)s, ws_bytes};
+    std::vector<char> k(sizeof(head) + (size_t)n_segs * sizeof(mmlttb_segment_t));
+    memcpy(k.data(), &head, sizeof(head));
+    memcpy(k.data() + sizeof(head), segs, (size_t)n_segs * sizeof(mmlttb_segment_t));
+    return k;
+}
+
+GraphEntry *graph_find(uint64_t hash, const std::vector<char> &key)
+{
+    for (auto &e : g_graphs) {
+        if (e.hash == hash && e.key == key) {
+            e.last_use = ++g_graph_clock;
+            ++g_graph_hits;
+            return &e;
+        }
+    }
+    return nullptr;
+}
+
+void graph_release(GraphEntry &e)
+{
+    if (e.done)
+        (void)hipEventSynchronize(e.done); // its last replay no longer reads the pinned table
+    if (e.exec)
+        (void)hipGraphExecDestroy(e.exec);
+    if (e.graph)
+        (void)hipGraphDestroy(e.graph);
+    if (e.done)
+        (void)hipEventDestroy(e.done);
+    if (e.pinned)
+        (void)hipHostFree(e.pinned);
+}
+
+void graph_evict_oldest()
+{
+    if (g_graphs.empty())
+        return;
+    size_t oldest = 0;
+    for (size_t i = 1; i < g_graphs.size(); ++i)
+        if (g_graphs[i].last_use < g_graphs[oldest].last_use)
+            oldest = i;
+    graph_release(g_graphs[oldest]);
+    g_graphs.erase(g_graphs.begin() + (long)oldest);
+}
+
+void graph_insert(GraphEntry &&e)
+{
+    while (!g_graphs.empty() && (int)g_graphs.size() >= g_graph_cap)
+        graph_evict_oldest();
+    e.last_use = ++g_graph_clock;
+    ++g_graph_captures;
+    g_graphs.push_back(std::move(e));
+}
+
 } // namespace
 
 extern "C" {
@@ -579,61 +728,103 @@ int mmlttb_minmaxlttb_batched(int xk, const int64_t *x_base, const float *y_base
         return fail(MMLTTB_EINVAL, "y_base and out_idx_base must not be NULL");
     if (((uintptr_t)y_base & 3u) || ((uintptr_t)x_base & 7u) || ((uintptr_t)out_idx_base & 7u))
         return fail(MMLTTB_EINVAL, "y_base must be 4-byte, x_base and out_idx_base 8-byte aligned");
+    if (n_segs < 1 || !segs_host)
+        return fail(MMLTTB_EINVAL, "n_segs must be >= 1 and segs_host not NULL");
+    if (!ws)
+        return fail(MMLTTB_EINVAL, "ws must not be NULL");
+    hipStream_t s = (hipStream_t)stream;
+    const bool use_graph = g_graph_cap > 0 && s != nullptr;
+    std::vector<char> key;
+    uint64_t hash = 0;
+    if (use_graph) {
+        key = graph_key(xk, x_base, y_base, segs_host, n_segs, out_idx_base, ws, ws_bytes, s);
+        hash = fnv1a(key);
+        if (GraphEntry *ge = graph_find(hash, key)) {
+            hipError_t e = hipGraphLaunch(ge->exec, s);
+            if (e == hipSuccess)
+                e = hipEventRecord(ge->done, s);
+            if (e != hipSuccess)
+                return fail(MMLTTB_EDEVICE, "graph replay failed: %s", hipGetErrorString(e));
+            return ok();
+        }
+    }
     BatchPlan plan;
     int rc = plan_batch(xk, segs_host, n_segs, plan);
     if (rc)
         return rc;
-    if (!ws)
-        return fail(MMLTTB_EINVAL, "ws must not be NULL");
     if (ws_bytes < plan.total)
         return fail(MMLTTB_ENOMEM, "workspace of %zu bytes is below the %zu required", ws_bytes, plan.total);
-    hipStream_t s = (hipStream_t)stream;
     const BatchHeader &h = plan.h;
-    // header + segment table, copied before this call returns
-    std::vector<char> staging(h.off_keys);
-    memcpy(staging.data(), &h, sizeof(h));
-    memcpy(staging.data() + h.off_segs, plan.segs.data(), plan.segs.size() * sizeof(BatchSeg));
-    hipError_t e = hipMemcpyAsync(ws, staging.data(), staging.size(), hipMemcpyHostToDevice, s);
+    const size_t table_bytes = (size_t)h.off_keys;
+    if (!use_graph) {
+        // header + segment table from pageable memory: copied before this call returns
+        std::vector<char> staging(table_bytes);
+        fill_table(staging.data(), plan);
+        hipError_t e = hipMemcpyAsync(ws, staging.data(), table_bytes, hipMemcpyHostToDevice, s);
+        if (e != hipSuccess)
+            return fail(MMLTTB_EDEVICE, "segment table copy failed: %s", hipGetErrorString(e));
+        rc = enqueue_batch(plan, xk, x_base, y_base, out_idx_base, ws, s);
+        return rc ? rc : ok();
+    }
+    // capture: table upload from a pinned copy owned by the graph entry, then the kernels
+    GraphEntry ge;
+    ge.hash = hash;
+    ge.key = std::move(key);
+    if (hipHostMalloc(&ge.pinned, table_bytes, hipHostMallocDefault) != hipSuccess)
+        return fail(MMLTTB_EDEVICE, "pinned table allocation failed");
+    fill_table(static_cast<char *>(ge.pinned), plan);
+    const bool prof = g_prof;
+    g_prof = false; // no timing events inside a capture
+    hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(ws, ge.pinned, table_bytes, hipMemcpyHostToDevice, s);
+    rc = (e == hipSuccess) ? enqueue_batch(plan, xk, x_base, y_base, out_idx_base, ws, s) : MMLTTB_EDEVICE;
+    hipGraph_t graph = nullptr;
+    hipError_t ec = hipStreamEndCapture(s, &graph);
+    g_prof = prof;
+    if (e != hipSuccess || rc != MMLTTB_OK || ec != hipSuccess || !graph) {
+        if (graph)
+            (void)hipGraphDestroy(graph);
+        (void)hipHostFree(ge.pinned);
+        return fail(MMLTTB_EDEVICE, "graph capture failed: %s", hipGetErrorString(e != hipSuccess ? e : ec));
+    }
+    ge.graph = graph;
+    e = hipGraphInstantiate(&ge.exec, graph, nullptr, nullptr, 0);
+    if (e == hipSuccess)
+        e = hipEventCreateWithFlags(&ge.done, hipEventDisableTiming);
+    if (e != hipSuccess) {
+        (void)hipGraphDestroy(graph);
+        (void)hipHostFree(ge.pinned);
+        return fail(MMLTTB_EDEVICE, "graph instantiation failed: %s", hipGetErrorString(e));
+    }
+    e = hipGraphLaunch(ge.exec, s);
+    if (e == hipSuccess)
+        e = hipEventRecord(ge.done, s);
+    graph_insert(std::move(ge));
     if (e != hipSuccess)
-        return fail(MMLTTB_EDEVICE, "segment table copy failed: %s", hipGetErrorString(e));
-    BatchPtrs b;
-    b.hdr = at<BatchHeader>(ws, 0);
-    b.segs = at<BatchSeg>(ws, h.off_segs);
-    b.n_segs = n_segs;
-    b.xk = xk;
-    b.x_base = x_base;
-    b.y_base = y_base;
-    b.out_base = out_idx_base;
-    b.keys = at<unsigned long long>(ws, h.off_keys);
-    b.P = at<int64_t>(ws, h.off_P);
-    b.XP = at<int64_t>(ws, h.off_XP);
-    b.YP = at<float>(ws, h.off_YP);
-    b.m = at<int64_t>(ws, h.off_m);
-    b.MX = at<double>(ws, h.off_MX);
-    b.MY = at<double>(ws, h.off_MY);
-    b.path = at<uint8_t>(ws, h.off_path);
-    b.finals = at<uint8_t>(ws, h.off_finals);
-    b.start = at<uint8_t>(ws, h.off_start);
-    b.n_keys = h.n_keys;
-    b.n_large_items = h.n_large_items;
-    b.n_small_tiles = h.n_small_tiles;
-    b.n_chain_units = h.n_chain_units;
-    b.stage_cap_max = (int)(h.max_stage_cap > 0 ? h.max_stage_cap : kSegLen);
-    if (h.n_large_items > 0) {
-        MMLTTB_LAUNCH("batch_init", s, launch_batch_init(b, s));
-        MMLTTB_LAUNCH("batch_minmax_large", s, launch_batch_large(b, tuning().unroll, s));
-    }
-    if (h.n_small_tiles > 0) {
-        MMLTTB_LAUNCH("batch_minmax_small", s, launch_batch_small(b, s));
-    }
-    MMLTTB_LAUNCH("batch_compact_means", s, launch_batch_compact_means(b, s));
-    MMLTTB_LAUNCH("batch_chain", s, launch_batch_chain(b, s));
-    if (plan.any_seq) {
-        MMLTTB_LAUNCH("batch_chain_seq", s, launch_batch_chain_seq(b, s));
-    }
-    if (h.n_chain_units > 0) {
-        MMLTTB_LAUNCH("batch_link_emit", s, launch_batch_link_emit(b, s));
-    }
+        return fail(MMLTTB_EDEVICE, "graph launch failed: %s", hipGetErrorString(e));
+    return ok();
+}
+
+int mmlttb_set_graph_cache(int max_graphs)
+{
+    if (max_graphs < 0)
+        return fail(MMLTTB_EINVAL, "max_graphs must be >= 0");
+    g_graph_cap = max_graphs;
+    while ((int)g_graphs.size() > g_graph_cap)
+        graph_evict_oldest();
+    if (max_graphs == 0)
+        g_graph_hits = g_graph_captures = 0;
+    return ok();
+}
+
+int mmlttb_graph_cache_stats(int64_t *entries, int64_t *hits, int64_t *captures)
+{
+    if (!entries || !hits || !captures)
+        return fail(MMLTTB_EINVAL, "NULL argument");
+    *entries = (int64_t)g_graphs.size();
+    *hits = g_graph_hits;
+    *captures = g_graph_captures;
     return ok();
 }
 

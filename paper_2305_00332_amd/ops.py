@@ -129,6 +129,21 @@ def minmaxlttb_batched(y_base, segs, x_base=None, out=None, ws=None, table=None)
     return out, out_offsets
 
 
+def set_graph_cache(max_graphs: int):
+    """Capture batched calls on non-default streams into HIP graphs and replay
+    repeated ones (0 disables and releases the cache)."""
+    _lib.check(_lib.load().mmlttb_set_graph_cache(int(max_graphs)))
+
+
+def graph_cache_stats():
+    """(entries, replays, captures)"""
+    import ctypes
+
+    v = [ctypes.c_int64(0) for _ in range(3)]
+    _lib.check(_lib.load().mmlttb_graph_cache_stats(*[ctypes.byref(t) for t in v]))
+    return tuple(t.value for t in v)
+
+
 CHAIN_AUTO, CHAIN_SEQUENTIAL, CHAIN_SEGMENTED = 0, 1, 2
 
 

@@ -1,0 +1,108 @@
+"""Batched calls replayed from captured HIP graphs equal eager calls on every
+replay, with the program's own eager work and synchronisations between
+replays, after in-place changes of the input data, and across evictions."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2305_00332_amd import ops, synth
+
+pytestmark = pytest.mark.gpu
+
+
+def _batch(seed, count, nmax):
+    rng = np.random.default_rng(seed)
+    lengths = rng.integers(1, nmax, size=count)
+    n_outs = rng.choice([3, 50, 500, 2000], size=count)
+    r_pss = rng.choice([2, 4, 8, 100], size=count)
+    x, y, offsets = synth.batch_series(lengths, seed, device="cuda")
+    segs = [(int(o), int(n), int(no), int(r)) for o, n, no, r in zip(offsets, lengths, n_outs, r_pss)]
+    return x, y, segs
+
+
+def _eager(y, segs, x):
+    # the default stream is never captured, whatever the cache setting
+    assert torch.cuda.current_stream().cuda_stream == 0
+    out, outoff = ops.minmaxlttb_batched(y, segs, x_base=x)
+    torch.cuda.synchronize()
+    return out.clone(), outoff
+
+
+@pytest.fixture(autouse=True)
+def _reset():
+    ops.set_graph_cache(0)
+    yield
+    ops.set_graph_cache(0)
+
+
+def test_replays_equal_eager_with_eager_work_between():
+    x, y, segs = _batch(3, 40, 300_000)
+    ref, outoff = _eager(y, segs, x)
+    stream = torch.cuda.Stream()
+    out = torch.empty_like(ref)
+    ws = torch.empty(ops.batched_workspace_size(segs), dtype=torch.uint8, device="cuda")
+    table = ops.segment_table(segs)
+    ops.set_graph_cache(4)
+    for i in range(6):
+        with torch.cuda.stream(stream):
+            out.fill_(-1)
+            ops.minmaxlttb_batched(y, segs, x_base=x, out=out, ws=ws, table=table)
+        stream.synchronize()
+        assert torch.equal(out, ref), f"replay {i}"
+        # unrelated eager work on the default stream between replays
+        ops.minmaxlttb(y[:10_000], 100, 4)
+        torch.cuda.synchronize()
+    entries, hits, captures = ops.graph_cache_stats()
+    assert captures == 1 and hits == 5 and entries == 1
+
+
+def test_replay_reads_current_data():
+    x, y, segs = _batch(4, 20, 100_000)
+    stream = torch.cuda.Stream()
+    ref, outoff = _eager(y, segs, x)
+    out = torch.empty_like(ref)
+    ws = torch.empty(ops.batched_workspace_size(segs), dtype=torch.uint8, device="cuda")
+    ops.set_graph_cache(2)
+    with torch.cuda.stream(stream):
+        ops.minmaxlttb_batched(y, segs, x_base=x, out=out, ws=ws)
+    stream.synchronize()
+    assert torch.equal(out, ref)
+    y.copy_(torch.flip(y, [0]))  # new data, same pointers
+    ref2, _ = _eager(y, segs, x)
+    assert not torch.equal(ref, ref2)
+    with torch.cuda.stream(stream):
+        ops.minmaxlttb_batched(y, segs, x_base=x, out=out, ws=ws)
+    stream.synchronize()
+    assert torch.equal(out, ref2)
+    assert ops.graph_cache_stats()[1] == 1  # the second call was a replay
+    # and against the oracle for a few series
+    got = out.cpu().numpy()
+    for i in (0, 5, 19):
+        o, n, no, r = segs[i]
+        want = oracle.minmaxlttb(y[o:o + n].cpu().numpy(), no, r, x[o:o + n].cpu().numpy())
+        assert np.array_equal(got[outoff[i]: outoff[i] + min(n, no)], want)
+
+
+def test_eviction_keeps_results_correct():
+    xa, ya, sa = _batch(5, 12, 200_000)
+    xb, yb, sb = _batch(6, 7, 200_000)
+    ra, _ = _eager(ya, sa, xa)
+    rb, _ = _eager(yb, sb, xb)
+    stream = torch.cuda.Stream()
+    oa, ob = torch.empty_like(ra), torch.empty_like(rb)
+    wa = torch.empty(ops.batched_workspace_size(sa), dtype=torch.uint8, device="cuda")
+    wb = torch.empty(ops.batched_workspace_size(sb), dtype=torch.uint8, device="cuda")
+    ops.set_graph_cache(1)
+    for i in range(4):
+        with torch.cuda.stream(stream):
+            oa.fill_(-1)
+            ops.minmaxlttb_batched(ya, sa, x_base=xa, out=oa, ws=wa)
+            ob.fill_(-1)
+            ops.minmaxlttb_batched(yb, sb, x_base=xb, out=ob, ws=wb)
+        stream.synchronize()
+        assert torch.equal(oa, ra) and torch.equal(ob, rb), f"round {i}"
+    entries, hits, captures = ops.graph_cache_stats()
+    assert entries == 1 and captures >= 8
