@@ -123,6 +123,10 @@ def bench_headline(args):
     torch.cuda.set_device(dev)
     _lib.load()
 
+    from paper_2305_00332_amd import autotune
+
+    tuned = autotune.apply("single")
+    log(f"tuning: {ops.get_tuning()} (cache entry: {tuned})")
     log(f"generating y: float32 random walk, n={n}, seed={args.seed}")
     y = synth.random_walk(n, args.seed, device=dev)
     torch.cuda.synchronize()
@@ -178,6 +182,7 @@ def bench_headline(args):
                                f"implicit x, resident in HBM; MinMaxLTTB n_out={n_out}, r_ps={r_ps}",
                    "n": n, "n_out": n_out, "r_ps": r_ps, "mode": "plain single-series call"},
         "kernel_avg_ms": kern,
+        "tuning": dict(zip(("unroll", "chunk", "chain", "tile"), ops.get_tuning())),
         "roofline": roofline,
         "repeat_identical": stable,
     }
@@ -261,6 +266,9 @@ def bench_batched(args):
 
     from paper_2305_00332_amd import ops, synth
 
+    from paper_2305_00332_amd import autotune
+
+    autotune.apply("batched")
     count = args.batch_series
     lengths = synth.batch_lengths(count, 1e3, 1e7, 4)
     n_outs = synth.choice([200, 500, 1000, 2000], count, 40)
@@ -350,6 +358,7 @@ def bench_batched(args):
            "points": pts, "ms": round(t_batched * 1e3, 4), "gpts_per_s": round(pts / t_batched / 1e9, 3),
            "plain_ms": round(t_plain * 1e3, 4), "plain_gpts_per_s": round(pts / t_plain / 1e9, 3),
            "speedup_vs_plain": round(t_plain / t_batched, 3), "kernel_ms": kern,
+           "tuning": dict(zip(("unroll", "chunk", "chain", "tile"), ops.get_tuning())),
            "graph_replay_ms": round(t_graph * 1e3, 4), "graph_stats": list(graph_stats),
            "small_batch_16": {"eager_ms": round(t_small_eager * 1e3, 4), "graph_ms": round(t_small_graph * 1e3, 4),
                               "points": int(sum(n for _, n, _, _ in small))},

@@ -85,8 +85,9 @@ def load(path: str = LIB_PATH):
                                               ctypes.c_size_t, _vp]
     lib.mmlttb_set_graph_cache.argtypes = [ctypes.c_int]
     lib.mmlttb_graph_cache_stats.argtypes = [ctypes.POINTER(_i64)] * 3
-    lib.mmlttb_set_tuning.argtypes = [ctypes.c_int, _i64, ctypes.c_int]
-    lib.mmlttb_get_tuning.argtypes = [ctypes.POINTER(ctypes.c_int), ctypes.POINTER(_i64), ctypes.POINTER(ctypes.c_int)]
+    lib.mmlttb_set_tuning.argtypes = [ctypes.c_int, _i64, ctypes.c_int, ctypes.c_int]
+    lib.mmlttb_get_tuning.argtypes = [ctypes.POINTER(ctypes.c_int), ctypes.POINTER(_i64), ctypes.POINTER(ctypes.c_int),
+                                      ctypes.POINTER(ctypes.c_int)]
     lib.mmlttb_profile_enable.argtypes = [ctypes.c_int]
     lib.mmlttb_profile_read.argtypes = [ctypes.c_char_p, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_i64)]
     for f in ("mmlttb_minmax", "mmlttb_lttb", "mmlttb_minmaxlttb", "mmlttb_minmaxlttb_batched",

@@ -42,6 +42,7 @@ struct Tuning {
     int unroll = 4;        // float4 loads per lane per batch in minmax_bin_reduce
     int64_t chunk = 16384; // points per minmax work item (multiple of 256 * unroll)
     int chain = kChainAuto;
+    int tile = 4096;       // batched small-bin tile points (bins of <= tile/4 points)
 };
 
 Tuning &tuning()
@@ -57,6 +58,11 @@ Tuning &tuning()
             long long c = atoll(e);
             if (c >= 256)
                 r.chunk = c;
+        }
+        if (const char *e = getenv("MMLTTB_TILE")) {
+            int t = atoi(e);
+            if (t == 2048 || t == 4096 || t == 8192)
+                r.tile = t;
         }
         if (const char *e = getenv("MMLTTB_CHAIN")) {
             int c = atoi(e);
@@ -361,9 +367,9 @@ int plan_batch(int xk, const mmlttb_segment_t *in, int64_t n_segs, BatchPlan &pl
         if (g.mode == kSegMinMax) {
             g.bins = make_split(q.n - 2, nb);
             const int64_t maxbin = g.bins.q + (g.bins.r ? 1 : 0);
-            if (maxbin <= kSmallBinMax) {
+            if (maxbin <= tn.tile / 4) {
                 int64_t G = 256;
-                while (G * maxbin > kTilePoints)
+                while (G * maxbin > tn.tile)
                     G >>= 1;
                 g.small = 1;
                 g.tile_bins = (int32_t)G;
@@ -466,7 +472,7 @@ int enqueue_batch(const BatchPlan &plan, int xk, const int64_t *x_base, const fl
         MMLTTB_LAUNCH("batch_minmax_large", s, launch_batch_large(b, tuning().unroll, s));
     }
     if (h.n_small_tiles > 0) {
-        MMLTTB_LAUNCH("batch_minmax_small", s, launch_batch_small(b, s));
+        MMLTTB_LAUNCH("batch_minmax_small", s, launch_batch_small(b, tuning().tile, s));
     }
     MMLTTB_LAUNCH("batch_compact_means", s, launch_batch_compact_means(b, s));
     MMLTTB_LAUNCH("batch_chain", s, launch_batch_chain(b, s));
@@ -513,11 +519,11 @@ std::vector<char> graph_key(int xk, const int64_t *x_base, const float *y_base, 
 {
     const Tuning &t = tuning();
     struct Head {
-        int xk, unroll, chain, pad;
+        int xk, unroll, chain, tile;
         int64_t chunk, n_segs;
         const void *x, *y, *out, *ws, *stream;
         size_t ws_bytes;
-    } head{xk, t.unroll, t.chain, 0, t.chunk, n_segs, x_base, y_base, out, ws, (const void *)s, ws_bytes};
+    } head{xk, t.unroll, t.chain, t.tile, t.chunk, n_segs, x_base, y_base, out, ws, (const void *)s, ws_bytes};
     std::vector<char> k(sizeof(head) + (size_t)n_segs * sizeof(mmlttb_segment_t));
     memcpy(k.data(), &head, sizeof(head));
     memcpy(k.data() + sizeof(head), segs, (size_t)n_segs * sizeof(mmlttb_segment_t));
@@ -828,9 +834,11 @@ int mmlttb_graph_cache_stats(int64_t *entries, int64_t *hits, int64_t *captures)
     return ok();
 }
 
-int mmlttb_set_tuning(int unroll, int64_t chunk, int chain)
+int mmlttb_set_tuning(int unroll, int64_t chunk, int chain, int tile)
 {
     Tuning &t = tuning();
+    if (tile != 0 && tile != 2048 && tile != 4096 && tile != 8192)
+        return fail(MMLTTB_EINVAL, "tile must be 2048, 4096 or 8192");
     if (unroll != 0 && unroll != 1 && unroll != 2 && unroll != 4 && unroll != 8)
         return fail(MMLTTB_EINVAL, "unroll must be 1, 2, 4 or 8");
     if (chunk != 0 && chunk < 256)
@@ -843,18 +851,21 @@ int mmlttb_set_tuning(int unroll, int64_t chunk, int chain)
         t.chunk = chunk;
     if (chain)
         t.chain = chain;
+    if (tile)
+        t.tile = tile;
     const int64_t q = 256 * (int64_t)t.unroll;
     t.chunk = ((t.chunk + q - 1) / q) * q;
     return ok();
 }
 
-int mmlttb_get_tuning(int *unroll, int64_t *chunk, int *chain)
+int mmlttb_get_tuning(int *unroll, int64_t *chunk, int *chain, int *tile)
 {
-    if (!unroll || !chunk || !chain)
+    if (!unroll || !chunk || !chain || !tile)
         return fail(MMLTTB_EINVAL, "NULL argument");
     *unroll = tuning().unroll;
     *chunk = tuning().chunk;
     *chain = tuning().chain;
+    *tile = tuning().tile;
     return ok();
 }
 

@@ -12,8 +12,8 @@
 //             (bin, chunk) item, as in the single-series stream (16-byte
 //             loads, atomic key merge)
 //   small     series with small bins: a workgroup stages a tile of whole bins
-//             (<= kTilePoints points) in LDS; a power-of-two lane group
-//             reduces each bin and stores its keys
+//             (<= tile points) in LDS; a power-of-two lane group reduces each
+//             bin and stores its keys
 //   compact_means  one workgroup per series: P, X_P, Y_P, m, then the exact
 //             next-bucket means (identity series write their output here)
 //   chain     segmented chain, walks: one wave per (series, chain segment)
@@ -90,6 +90,7 @@ __global__ __launch_bounds__(256) void k_batch_large(BatchPtrs b)
     }
 }
 
+template <int kTilePoints>
 __global__ __launch_bounds__(kTileThreads) void k_batch_small(BatchPtrs b)
 {
     __shared__ float tile[kTilePoints];
@@ -363,11 +364,22 @@ hipError_t launch_batch_large(const BatchPtrs &b, int unroll, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_batch_small(const BatchPtrs &b, hipStream_t s)
+hipError_t launch_batch_small(const BatchPtrs &b, int tile, hipStream_t s)
 {
     if (b.n_small_tiles == 0)
         return hipSuccess;
-    hipLaunchKernelGGL(k_batch_small, dim3(cap_grid(b.n_small_tiles, 0x7fffffff)), dim3(kTileThreads), 0, s, b);
+    const dim3 grid(cap_grid(b.n_small_tiles, 0x7fffffff));
+    switch (tile) {
+    case 2048:
+        hipLaunchKernelGGL(k_batch_small<2048>, grid, dim3(kTileThreads), 0, s, b);
+        break;
+    case 8192:
+        hipLaunchKernelGGL(k_batch_small<8192>, grid, dim3(kTileThreads), 0, s, b);
+        break;
+    default:
+        hipLaunchKernelGGL(k_batch_small<4096>, grid, dim3(kTileThreads), 0, s, b);
+        break;
+    }
     return hipGetLastError();
 }
 

@@ -46,12 +46,11 @@ struct SegChainArgs {
 
 enum SegMode : int32_t { kSegIdentity = 0, kSegAll = 1, kSegMinMax = 2 };
 
-// Small-bin tiles: a workgroup of kTileThreads stages up to kTilePoints
-// consecutive points (whole bins) in LDS; a power-of-two group of lanes
-// reduces each bin. Bins of at most kSmallBinMax points take this path.
+// Small-bin tiles: a workgroup of kTileThreads stages up to `tile` consecutive
+// points (whole bins; tile in {2048, 4096, 8192}, a tuning choice) in LDS; a
+// power-of-two group of lanes reduces each bin. Bins of at most tile / 4
+// points take this path.
 constexpr int kTileThreads = 256;
-constexpr int kTilePoints = 4096;
-constexpr int kSmallBinMax = 1024;
 
 // One series of a batch as planned on the host (copied to the workspace).
 struct BatchSeg {
@@ -110,7 +109,7 @@ struct BatchPtrs {
 
 hipError_t launch_batch_init(const BatchPtrs &b, hipStream_t s);
 hipError_t launch_batch_large(const BatchPtrs &b, int unroll, hipStream_t s);
-hipError_t launch_batch_small(const BatchPtrs &b, hipStream_t s);
+hipError_t launch_batch_small(const BatchPtrs &b, int tile, hipStream_t s);
 hipError_t launch_batch_compact_means(const BatchPtrs &b, hipStream_t s);
 hipError_t launch_batch_chain(const BatchPtrs &b, hipStream_t s);
 hipError_t launch_batch_link_emit(const BatchPtrs &b, hipStream_t s);

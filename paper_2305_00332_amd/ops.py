@@ -147,22 +147,23 @@ def graph_cache_stats():
 CHAIN_AUTO, CHAIN_SEQUENTIAL, CHAIN_SEGMENTED = 0, 1, 2
 
 
-def set_tuning(unroll: int = 0, chunk: int = 0, chain: int = 0):
+def set_tuning(unroll: int = 0, chunk: int = 0, chain: int = 0, tile: int = 0):
     """Execution tuning (results never depend on it): MinMax loads in flight per
-    lane, points per MinMax work item, LTTB pass form (1 sequential, 2 segmented).
-    Zero keeps the current value."""
-    _lib.check(_lib.load().mmlttb_set_tuning(unroll, chunk, chain))
+    lane, points per MinMax work item, LTTB pass form (1 sequential, 2 segmented),
+    batched small-bin tile points. Zero keeps the current value."""
+    _lib.check(_lib.load().mmlttb_set_tuning(unroll, chunk, chain, tile))
 
 
 def get_tuning():
-    """(unroll, chunk, chain)"""
+    """(unroll, chunk, chain, tile)"""
     import ctypes
 
     u = ctypes.c_int(0)
     c = ctypes.c_int64(0)
     ch = ctypes.c_int(0)
-    _lib.check(_lib.load().mmlttb_get_tuning(ctypes.byref(u), ctypes.byref(c), ctypes.byref(ch)))
-    return u.value, c.value, ch.value
+    t = ctypes.c_int(0)
+    _lib.check(_lib.load().mmlttb_get_tuning(ctypes.byref(u), ctypes.byref(c), ctypes.byref(ch), ctypes.byref(t)))
+    return u.value, c.value, ch.value, t.value
 
 
 def profile_enable(on: bool = True):

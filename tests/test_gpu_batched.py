@@ -123,3 +123,23 @@ def test_full_batch_4096_series():
         assert np.array_equal(got[outoff[i]: outoff[i] + min(n, no)], want), f"series {i} vs oracle"
     del x, y
     torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("tile,chunk,unroll", [(2048, 1024, 1), (4096, 4096, 2), (8192, 65536, 8), (4096, 16384, 4)])
+def test_tuning_does_not_change_batched_results(tile, chunk, unroll):
+    lengths, n_outs, r_pss = _random_batch(21, 50, 2_000_000)
+    x, y, offsets = synth.batch_series(lengths, 21, device="cuda")
+    segs = [(int(o), int(n), int(no), int(r)) for o, n, no, r in zip(offsets, lengths, n_outs, r_pss)]
+    ref, _ = ops.minmaxlttb_batched(y, segs, x_base=x)
+    old = ops.get_tuning()
+    try:
+        ops.set_tuning(unroll=unroll, chunk=chunk, tile=tile)
+        got, outoff = ops.minmaxlttb_batched(y, segs, x_base=x)
+    finally:
+        ops.set_tuning(*old)
+    assert torch.equal(got, ref)
+    g = got.cpu().numpy()
+    for i in (0, 17, 49):
+        o, n, no, r = segs[i]
+        want = oracle.minmaxlttb(y[o:o + n].cpu().numpy(), no, r, x[o:o + n].cpu().numpy())
+        assert np.array_equal(g[outoff[i]: outoff[i] + min(n, no)], want)
