@@ -41,15 +41,16 @@ def kernel_source_sha() -> str:
     return h.hexdigest()
 
 
-def measured_traffic(launch_points: int):
+def measured_traffic(launch_points: int, unroll: int, chunk: int):
     """HBM bytes per launch from the committed rocprofv3 counter summary, or None
-    when it is missing or was taken on another version of the kernel source."""
+    when it is missing or was taken on another kernel source, size or tuning."""
     try:
         with open(TRAFFIC_FILE) as f:
             t = json.load(f)
     except (OSError, ValueError):
         return None
-    if t.get("kernel_source_sha") != kernel_source_sha() or t.get("n") != launch_points:
+    if (t.get("kernel_source_sha") != kernel_source_sha() or t.get("n") != launch_points
+            or t.get("unroll") != unroll or t.get("chunk") != chunk):
         return None
     return t.get("hbm_bytes_per_launch")
 
@@ -161,7 +162,8 @@ def bench_headline(args):
     mm_ms = kern["minmax_bin_reduce"]
     alg_bytes = 4 * n + 16 * nb  # y read once + the bins' key pair
     achieved = alg_bytes / (mm_ms * 1e-3) / 1e9
-    traffic = measured_traffic(n)
+    tun = ops.get_tuning()
+    traffic = measured_traffic(n, tun[0], tun[1])
     roofline = {"bound": "hbm", "kernel": "minmax_bin_reduce", "achieved": round(achieved, 1),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": traffic, "algorithmic_bytes": alg_bytes, "avg_ms": mm_ms}

@@ -153,8 +153,9 @@ int mmlttb_graph_cache_stats(int64_t *entries, int64_t *hits, int64_t *captures)
 int mmlttb_set_tuning(int unroll, int64_t chunk, int chain, int tile);
 int mmlttb_get_tuning(int *unroll, int64_t *chunk, int *chain, int *tile);
 
-/* Kernel timing for measurement. When enabled, HIP events are recorded on the
- * caller's stream around every launch of the named kernels; mmlttb_profile_read
+/* Kernel timing for measurement. When enabled, timing-only HIP events (no
+ * system-scope fence) are recorded on the caller's stream around every launch
+ * of the named kernels; mmlttb_profile_read
  * synchronises those events and returns the summed milliseconds and the
  * launch count of `kernel` since the last reset. Not thread-safe; off by default. */
 int mmlttb_profile_enable(int on);

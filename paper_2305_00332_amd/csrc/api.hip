@@ -84,15 +84,31 @@ struct Pending {
 };
 bool g_prof = false;
 std::vector<Pending> g_pending;
+std::vector<hipEvent_t> g_event_pool;
 std::map<std::string, std::pair<double, int64_t>> g_totals;
+
+// Timing-only events: no system-scope fence on record, so recording them
+// neither writes back nor invalidates caches around the timed kernel.
+hipEvent_t take_event()
+{
+    if (!g_event_pool.empty()) {
+        hipEvent_t e = g_event_pool.back();
+        g_event_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess)
+        return nullptr;
+    return e;
+}
 
 template <class F>
 hipError_t timed(const char *name, hipStream_t s, F &&launch)
 {
     if (!g_prof)
         return launch();
-    hipEvent_t a = nullptr, b = nullptr;
-    if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess)
+    hipEvent_t a = take_event(), b = take_event();
+    if (!a || !b)
         return launch();
     (void)hipEventRecord(a, s);
     hipError_t e = launch();
@@ -110,8 +126,8 @@ void drain_pending()
             t.first += ms;
             t.second += 1;
         }
-        (void)hipEventDestroy(p.a);
-        (void)hipEventDestroy(p.b);
+        g_event_pool.push_back(p.a);
+        g_event_pool.push_back(p.b);
     }
     g_pending.clear();
 }
