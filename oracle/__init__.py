@@ -15,6 +15,8 @@ from .oracle import (  # noqa: F401
     lib_path,
     lttb,
     lttb_means,
+    m4,
+    everynth,
     minmax,
     minmaxlttb,
     XK_IMPLICIT,

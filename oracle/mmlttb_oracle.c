@@ -47,6 +47,19 @@
  *   R9  n <= n_out returns every index; n < 1, n_out < 3 or r_ps < 2 is an
  *       argument error. No other short-circuit: P is always computed.
  *   R10 y must be finite; the oracle refuses non-finite input.
+ *
+ * The other downsamplers of Table 1, on the same building blocks:
+ *   R11 MinMax alone is the preselection with r_ps = 1 (section 3 footnote:
+ *       MinMaxLTTB with r_ps = 1 corresponds to MinMax aggregation):
+ *       floor(n_out / 2) interior bins plus the first and last points.
+ *   R12 M4 keeps per bin the first, the last, the lowest-index minimum and
+ *       the lowest-index maximum (section 2.2.1); floor(n_out / 4)
+ *       equal-index bins over all points, part b = [floor(b n / nb),
+ *       floor((b+1) n / nb)); output sorted distinct; n <= n_out keeps
+ *       every index; n_out < 4 is an argument error.
+ *   R13 EveryNth keeps n_out evenly spaced indices floor(k n / n_out),
+ *       k = 0..n_out-1 (section 2.2.1); n <= n_out keeps every index;
+ *       n_out < 1 is an argument error.
  */
 #include <math.h>
 #include <stdint.h>
@@ -229,10 +242,10 @@ static int cmp_i64(const void *a, const void *b)
 }
 
 /* Writes the sorted distinct preselection into P (capacity 2*nb+2) and its
- * size into *m. */
+ * size into *m. r_ps = 1 gives the MinMax downsampler (R11). */
 int oracle_minmax(const float *y, int64_t n, int64_t n_out, int32_t r_ps, int64_t *P, int64_t *m)
 {
-    if (n < 1 || n_out < 3 || r_ps < 2)
+    if (n < 1 || n_out < 3 || r_ps < 1)
         return ORC_EINVAL;
     for (int64_t i = 0; i < n; i++)
         if (!is_finite_f32(y[i]))
@@ -426,6 +439,67 @@ int oracle_minmaxlttb(int xk, const int64_t *x, const float *y, int64_t n, int64
     free(ys);
     free(pos);
     return rc;
+}
+
+/* ------------------------------------------------------------------------ */
+/* M4 and EveryNth (section 2.2.1, Table 1; R12, R13).                       */
+/* ------------------------------------------------------------------------ */
+
+/* out: capacity 4 * floor(n_out / 4) (or n when n <= n_out); *count = size. */
+int oracle_m4(const float *y, int64_t n, int64_t n_out, int64_t *out, int64_t *count)
+{
+    if (n < 1 || n_out < 4)
+        return ORC_EINVAL;
+    for (int64_t i = 0; i < n; i++)
+        if (!is_finite_f32(y[i]))
+            return ORC_ENOTFINITE;
+    int64_t cnt = 0;
+    if (n <= n_out) {
+        for (int64_t i = 0; i < n; i++)
+            out[cnt++] = i;
+        *count = cnt;
+        return ORC_OK;
+    }
+    int64_t nb = n_out / 4;
+    for (int64_t b = 0; b < nb; b++) {
+        int64_t lo = floor_frac(b, n, nb);
+        int64_t hi = floor_frac(b + 1, n, nb);
+        if (lo == hi)
+            continue;
+        int64_t imin = lo, imax = lo;
+        for (int64_t i = lo + 1; i < hi; i++) {
+            if (y[i] < y[imin]) /* lowest index on ties (R12) */
+                imin = i;
+            if (y[i] > y[imax]) /* lowest index on ties (R12) */
+                imax = i;
+        }
+        out[cnt++] = lo;
+        out[cnt++] = imin;
+        out[cnt++] = imax;
+        out[cnt++] = hi - 1;
+    }
+    qsort(out, (size_t)cnt, sizeof(int64_t), cmp_i64);
+    int64_t d = 0;
+    for (int64_t i = 0; i < cnt; i++)
+        if (d == 0 || out[i] != out[d - 1])
+            out[d++] = out[i];
+    *count = d;
+    return ORC_OK;
+}
+
+/* out: capacity min(n, n_out). */
+int oracle_everynth(int64_t n, int64_t n_out, int64_t *out)
+{
+    if (n < 0 || n_out < 1)
+        return ORC_EINVAL;
+    if (n <= n_out) {
+        for (int64_t i = 0; i < n; i++)
+            out[i] = i;
+        return ORC_OK;
+    }
+    for (int64_t k = 0; k < n_out; k++)
+        out[k] = floor_frac(k, n, n_out);
+    return ORC_OK;
 }
 
 /* ------------------------------------------------------------------------ */

@@ -57,8 +57,10 @@ def _bind(path: str):
     lib.oracle_lttb_means.argtypes = [ctypes.c_int, _i64p, _f32p, ctypes.c_int64, ctypes.c_int64, _f64p, _f64p]
     lib.oracle_exact_sum_f32.argtypes = [_f32p, ctypes.c_int64, _f64p]
     lib.oracle_exact_sum_i64.argtypes = [_i64p, ctypes.c_int64, _f64p]
+    lib.oracle_m4.argtypes = [_f32p, ctypes.c_int64, ctypes.c_int64, _i64p, _i64p]
+    lib.oracle_everynth.argtypes = [ctypes.c_int64, ctypes.c_int64, _i64p]
     for f in ("oracle_minmax", "oracle_lttb", "oracle_minmaxlttb", "oracle_lttb_means",
-              "oracle_exact_sum_f32", "oracle_exact_sum_i64"):
+              "oracle_exact_sum_f32", "oracle_exact_sum_i64", "oracle_m4", "oracle_everynth"):
         getattr(lib, f).restype = ctypes.c_int
     return lib
 
@@ -94,6 +96,8 @@ def compile_variant(src_text: str, out_path: str):
     v.lttb = lambda y, n_out, x=None: lttb(y, n_out, x, _lib_override=lib)
     v.minmaxlttb = lambda y, n_out, r_ps, x=None: minmaxlttb(y, n_out, r_ps, x, _lib_override=lib)
     v.lttb_means = lambda y, n_out, x=None: lttb_means(y, n_out, x, _lib_override=lib)
+    v.m4 = lambda y, n_out: m4(y, n_out, _lib_override=lib)
+    v.everynth = lambda n, n_out: everynth(n, n_out, _lib_override=lib)
     v.exact_sum_f32 = lambda a: exact_sum_f32(a, _lib_override=lib)
     v.exact_sum_i64 = lambda a: exact_sum_i64(a, _lib_override=lib)
     return v
@@ -126,7 +130,8 @@ def _ptr(a, t):
 
 
 def minmax(y, n_out: int, r_ps: int, _lib_override=None) -> np.ndarray:
-    """Sorted distinct MinMax preselection P (readings R1-R4)."""
+    """Sorted distinct MinMax preselection P (readings R1-R4); r_ps = 1 is the
+    MinMax downsampler (R11)."""
     y = _f32(y)
     n = y.shape[0]
     nb = (n_out * r_ps) // 2
@@ -136,6 +141,27 @@ def minmax(y, n_out: int, r_ps: int, _lib_override=None) -> np.ndarray:
     if rc != 0:
         raise OracleError(rc, "minmax")
     return P[: m.value].copy()
+
+
+def m4(y, n_out: int, _lib_override=None) -> np.ndarray:
+    """M4: per bin first, last, min and max (reading R12)."""
+    y = _f32(y)
+    n = y.shape[0]
+    out = np.empty(max(4 * (n_out // 4), n if n <= n_out else 0, 1), dtype=np.int64)
+    cnt = ctypes.c_int64(0)
+    rc = (_lib_override or _load()).oracle_m4(_ptr(y, _f32p), n, n_out, out.ctypes.data_as(_i64p), ctypes.byref(cnt))
+    if rc != 0:
+        raise OracleError(rc, "m4")
+    return out[: cnt.value].copy()
+
+
+def everynth(n: int, n_out: int, _lib_override=None) -> np.ndarray:
+    """EveryNth: n_out evenly spaced indices (reading R13)."""
+    out = np.empty(max(min(n, n_out), 1), dtype=np.int64)
+    rc = (_lib_override or _load()).oracle_everynth(n, n_out, out.ctypes.data_as(_i64p))
+    if rc != 0:
+        raise OracleError(rc, "everynth")
+    return out[: min(n, n_out)].copy()
 
 
 def lttb(y, n_out: int, x=None, _lib_override=None) -> np.ndarray:

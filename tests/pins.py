@@ -137,3 +137,23 @@ def check_output_invariants(out, n: int, n_out: int):
         return
     assert out[0] == 0 and out[-1] == n - 1
     assert all(b > a for a, b in zip(out, out[1:]))
+
+
+def m4_by_numpy(y: np.ndarray, n_out: int) -> np.ndarray:
+    """M4 from numpy: per part of all points, first, last, first-occurrence argmin/argmax."""
+    n = len(y)
+    if n <= n_out:
+        return np.arange(n, dtype=np.int64)
+    sel = set()
+    for lo, hi in partition_by_inequality(n, n_out // 4):
+        if hi > lo:
+            seg = y[lo:hi]
+            sel.update({lo, hi - 1, lo + int(np.argmin(seg)), lo + int(np.argmax(seg))})
+    return np.array(sorted(sel), dtype=np.int64)
+
+
+def everynth_by_parts(n: int, n_out: int) -> np.ndarray:
+    """EveryNth as the first index of each part of an n_out-part balanced partition."""
+    if n <= n_out:
+        return np.arange(n, dtype=np.int64)
+    return np.array([lo for lo, _ in partition_by_inequality(n, n_out)], dtype=np.int64)

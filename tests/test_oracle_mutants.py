@@ -25,8 +25,13 @@ HALFWAY_CASES = [
 ]
 
 MUTANTS = {
-    "min_tie_highest": ("if (y[i] < y[imin])", "if (y[i] <= y[imin])"),
-    "max_tie_highest": ("if (y[i] > y[imax])", "if (y[i] >= y[imax])"),
+    "min_tie_highest": ("if (y[i] < y[imin]) /* strict", "if (y[i] <= y[imin]) /* strict"),
+    "max_tie_highest": ("if (y[i] > y[imax])\n                imax = i;\n        }\n        P[cnt++] = imin;",
+                        "if (y[i] >= y[imax])\n                imax = i;\n        }\n        P[cnt++] = imin;"),
+    "m4_min_tie_highest": ("if (y[i] < y[imin]) /* lowest index on ties (R12) */",
+                           "if (y[i] <= y[imin]) /* lowest index on ties (R12) */"),
+    "m4_max_tie_highest": ("if (y[i] > y[imax]) /* lowest index on ties (R12) */",
+                           "if (y[i] >= y[imax]) /* lowest index on ties (R12) */"),
     "ceil_boundaries": ("return (int64_t)(((__int128)k * (__int128)len) / (__int128)parts);",
                         "return (int64_t)(((__int128)k * (__int128)len + parts - 1) / (__int128)parts);"),
     "nb_not_halved": ("int64_t nb = (int64_t)(((__int128)n_out * r_ps) / 2); /* R1 */",
@@ -49,6 +54,9 @@ MUTANTS = {
     "subnormal_shift": ("mant = frac;\n            shift = 0;", "mant = frac;\n            shift = 1;"),
     "gather_wrong_x": ("xs[i] = (xk == XK_INT64) ? x[P[i]] : P[i];", "xs[i] = (xk == XK_INT64) ? x[i] : P[i];"),
     "no_first_point": ("    P[cnt++] = 0;\n    for (int64_t b = 0;", "    for (int64_t b = 0;"),
+    "m4_no_last": ("        out[cnt++] = hi - 1;\n", ""),
+    "m4_bins_not_quartered": ("    int64_t nb = n_out / 4;", "    int64_t nb = n_out / 2;"),
+    "everynth_ceil": ("        out[k] = floor_frac(k, n, n_out);", "        out[k] = (k * n + n_out - 1) / n_out;"),
 }
 
 
@@ -87,6 +95,14 @@ def _passes_pins(v) -> bool:
                     return False
                 if MY[k] != math.fsum(float(t) for t in y[g0:g1]) / (g1 - g0):
                     return False
+        # M4 and EveryNth vs numpy / partition starts
+        for seed in range(6):
+            gen = synth.ties_series if seed % 2 else synth.random_walk
+            y = synth.to_numpy(gen(300 + 97 * seed, seed))
+            if not np.array_equal(v.m4(y, 8 + 4 * seed), pins.m4_by_numpy(y, 8 + 4 * seed)):
+                return False
+            if not np.array_equal(v.everynth(1000 + seed, 7 + seed), pins.everynth_by_parts(1000 + seed, 7 + seed)):
+                return False
         # exact-regime LTTB vs rationals
         for seed in range(30):
             rng = np.random.default_rng(seed)
