@@ -70,6 +70,7 @@ def main():
     ap.add_argument("--skip-batched", action="store_true")
     ap.add_argument("--skip-comparator", action="store_true")
     ap.add_argument("--skip-served", action="store_true")
+    ap.add_argument("--skip-downsamplers", action="store_true")
     ap.add_argument("--batch-series", type=int, default=4096)
     ap.add_argument("--pool-series", type=int, default=512)
     ap.add_argument("--rates", type=str, default="100,500,1000,2000,5000")
@@ -101,6 +102,8 @@ def main():
         torch.cuda.synchronize()
         result["copy_calibration_bytes"] = {"read": 1 << 30, "write": 1 << 30}
         del src, dst
+    if not args.skip_downsamplers:
+        result["downsamplers"] = bench_downsamplers(args)
     if not args.skip_comparator:
         result["comparator"] = bench_comparator(args)
     if not args.skip_batched:
@@ -159,6 +162,25 @@ def bench_headline(args):
         kern[k] = round(tot / cnt, 5) if cnt else None
     stable = bool(torch.equal(out, ref_out))
 
+    # the LTTB pass in its sequential form on the same data (identical picks)
+    seg_ms = (kern["lttb_chain_seg"] or 0.0)
+    old_tuning = ops.get_tuning()
+    ops.set_tuning(chain=ops.CHAIN_SEQUENTIAL)
+    out_seq = torch.empty_like(out)
+    ops.minmaxlttb(y, n_out, r_ps, out=out_seq, ws=ws)
+    torch.cuda.synchronize()
+    ops.profile_enable(True)
+    ops.profile_reset()
+    for _ in range(5):
+        ops.minmaxlttb(y, n_out, r_ps, out=out_seq, ws=ws)
+    torch.cuda.synchronize()
+    ops.profile_enable(False)
+    tot, cnt = ops.profile_read("lttb_chain")
+    ops.set_tuning(*old_tuning)
+    chain_forms = {"sequential_ms": round(tot / max(cnt, 1), 5), "segmented_ms": round(seg_ms, 5),
+                   "speedup": round((tot / max(cnt, 1)) / seg_ms, 2) if seg_ms else None,
+                   "identical": bool(torch.equal(out_seq, out))}
+
     mm_ms = kern["minmax_bin_reduce"]
     alg_bytes = 4 * n + 16 * nb  # y read once + the bins' key pair
     achieved = alg_bytes / (mm_ms * 1e-3) / 1e9
@@ -184,6 +206,7 @@ def bench_headline(args):
                                f"implicit x, resident in HBM; MinMaxLTTB n_out={n_out}, r_ps={r_ps}",
                    "n": n, "n_out": n_out, "r_ps": r_ps, "mode": "plain single-series call"},
         "kernel_avg_ms": kern,
+        "chain_forms": chain_forms,
         "tuning": dict(zip(("unroll", "chunk", "chain", "tile"), ops.get_tuning())),
         "roofline": roofline,
         "repeat_identical": stable,
@@ -209,6 +232,66 @@ def bench_headline(args):
     del y, ws
     torch.cuda.empty_cache()
     return result
+
+
+def bench_downsamplers(args, reps: int = 10):
+    """The other Table 1 downsamplers on the headline series (n=1e9 float32
+    random walk, n_out as the headline): MinMax alone (r_ps = 1), M4 and
+    EveryNth. Whole-call and stream-kernel times, the stream kernel's HBM
+    roofline fraction, and parity of each output with the oracle."""
+    import numpy as np
+    import torch
+
+    import oracle
+    from paper_2305_00332_amd import ops, synth
+
+    n, n_out = int(args.n), args.n_out
+    dev = torch.device("cuda", 0)
+    log(f"downsamplers: generating y, n={n}")
+    y = synth.random_walk(n, args.seed, device=dev)
+    torch.cuda.synchronize()
+    y_np = y.cpu().numpy() if not args.no_cpu_baseline else None
+    out = torch.empty(max(n_out + 2, 2 * (n_out // 2) + 2), dtype=torch.int64, device=dev)
+    cnt = torch.empty(1, dtype=torch.int64, device=dev)
+    res = {}
+
+    def run(name, call, kernel, alg_bytes, want_fn):
+        call()
+        torch.cuda.synchronize()
+        ops.profile_enable(True)
+        ops.profile_reset()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            call()
+        torch.cuda.synchronize()
+        wall = (time.perf_counter() - t0) * 1e3 / reps
+        ops.profile_enable(False)
+        tot, c = ops.profile_read(kernel)
+        k_ms = tot / max(c, 1)
+        entry = {"call_ms": round(wall, 5), "kernel": kernel, "kernel_ms": round(k_ms, 5),
+                 "gpts_per_s": round(n / (wall * 1e-3) / 1e9, 3)}
+        if alg_bytes is not None:
+            gbs = alg_bytes / (k_ms * 1e-3) / 1e9
+            entry.update({"algorithmic_bytes": alg_bytes, "achieved_GBps": round(gbs, 1),
+                          "frac": round(gbs / HBM_PEAK_GBS, 4)})
+        if want_fn is not None:
+            m = int(cnt.item()) if name != "everynth" else min(n, n_out)
+            entry["parity_vs_oracle"] = bool(np.array_equal(out[:m].cpu().numpy(), want_fn()))
+        res[name] = entry
+        log(f"  {name}: {entry}")
+
+    ws_mm = torch.empty(ops.workspace_size(n, n_out, 1), dtype=torch.uint8, device=dev)
+    ws_m4 = torch.empty(ops.m4_workspace_size(n, n_out), dtype=torch.uint8, device=dev)
+    nb1, nb4 = n_out // 2, n_out // 4
+    run("minmax_r1", lambda: ops.minmax(y, n_out, 1, out=out, count=cnt, ws=ws_mm, sync=False), "minmax_bin_reduce",
+        4 * n + 16 * nb1, (lambda: oracle.minmax(y_np, n_out, 1)) if y_np is not None else None)
+    run("m4", lambda: ops.m4(y, n_out, out=out, count=cnt, ws=ws_m4, sync=False), "m4_bin_reduce",
+        4 * n + 16 * nb4, (lambda: oracle.m4(y_np, n_out)) if y_np is not None else None)
+    run("everynth", lambda: ops.everynth(n, n_out, out=out), "everynth", None,
+        (lambda: oracle.everynth(n, n_out)) if y_np is not None else None)
+    del y, y_np, ws_mm, ws_m4
+    torch.cuda.empty_cache()
+    return {"workload": f"one series, n={n}, float32 random walk (seed={args.seed}), n_out={n_out}", **res}
 
 
 def bench_comparator(args):

@@ -34,8 +34,9 @@
  *   on error nothing is enqueued and the return is negative. A failed HIP
  *   launch returns MMLTTB_EDEVICE. The message of the last error of the calling
  *   thread is in mmlttb_last_error(). No C++ exception crosses this boundary.
- * - Limits: 1 <= n <= 2^62; 3 <= n_out <= 2^31-1; 2 <= r_ps;
- *   floor(n_out*r_ps/2) <= 2^31-1; each MinMax bin holds < 2^32 points.
+ * - Limits: 1 <= n <= 2^62; 3 <= n_out <= 2^31-1; 2 <= r_ps (1 <= r_ps for
+ *   mmlttb_minmax alone); floor(n_out*r_ps/2) <= 2^31-1; each MinMax bin
+ *   holds < 2^32 points. M4 and EveryNth state their own limits.
  */
 #ifndef LIBMMLTTB_H
 #define LIBMMLTTB_H
@@ -80,7 +81,8 @@ const char *mmlttb_last_error(void);
 
 /* Workspace bytes for mmlttb_minmax and mmlttb_minmaxlttb. The size depends
  * on n_out and r_ps only, never on n: the method keeps O(n_out) state
- * (Table 1, memory column; section 3.2). Returns 0 on invalid arguments. */
+ * (Table 1, memory column; section 3.2). r_ps = 1 is accepted (the size for
+ * mmlttb_minmax). Returns 0 on invalid arguments. */
 size_t mmlttb_workspace_size(int64_t n, int64_t n_out, int32_t r_ps);
 
 /* Workspace bytes for mmlttb_lttb (next-bucket means and chain scratch);
@@ -92,7 +94,10 @@ size_t mmlttb_lttb_workspace_size(int64_t n, int64_t n_out);
  * non-empty bin, the lowest index of its minimum and of its maximum of y
  * (values compared as numbers, so -0.0 == +0.0) to out_idx[0..m-1] and m to
  * the device scalar *out_count. out_idx capacity: 2*floor(n_out*r_ps/2) + 2
- * (or n if smaller). x is validated but not read (bins are equal-index). */
+ * (or n if smaller). x is validated but not read (bins are equal-index).
+ * r_ps = 1 gives the MinMax downsampler of Table 1 itself: floor(n_out/2)
+ * bins, at most n_out points plus the first and last (section 3 footnote:
+ * MinMaxLTTB with r_ps = 1 is MinMax aggregation). */
 int mmlttb_minmax(int xk, const int64_t *x, const float *y, int64_t n, int64_t n_out, int32_t r_ps,
                   int64_t *out_idx, int64_t *out_count, void *ws, size_t ws_bytes, void *stream);
 
@@ -126,6 +131,30 @@ size_t mmlttb_batched_workspace_size(const mmlttb_segment_t *segs_host, int64_t 
  * the call returns. All segments are checked before anything is enqueued. */
 int mmlttb_minmaxlttb_batched(int xk, const int64_t *x_base, const float *y_base, const mmlttb_segment_t *segs_host,
                               int64_t n_segs, int64_t *out_idx_base, void *ws, size_t ws_bytes, void *stream);
+
+/* Workspace bytes for mmlttb_m4 (one key pair per bin); independent of n.
+ * Returns 0 on invalid arguments. */
+size_t mmlttb_m4_workspace_size(int64_t n, int64_t n_out);
+
+/* M4 (section 2.2.1, M4; Table 1): nb = floor(n_out/4) equal-index bins over
+ * all points, bin b = [floor(b*n/nb), floor((b+1)*n/nb)); per bin the first
+ * and the last index and the lowest index of the minimum and of the maximum of
+ * y (compared as numbers, -0.0 == +0.0). Writes the sorted distinct indices
+ * to out_idx[0..m-1] (capacity n_out suffices) and m to the device scalar
+ * *out_count. n <= n_out keeps 0..n-1. y: float32[n], finite, 4-byte
+ * aligned; x is not an argument (bins are equal-index). Limits:
+ * 1 <= n <= 2^62; 4 <= n_out <= 2^31-1; each bin holds < 2^32 points;
+ * otherwise MMLTTB_EINVAL. ws: mmlttb_m4_workspace_size bytes (may be NULL
+ * when n <= n_out). */
+int mmlttb_m4(const float *y, int64_t n, int64_t n_out, int64_t *out_idx, int64_t *out_count, void *ws,
+              size_t ws_bytes, void *stream);
+
+/* EveryNth (section 2.2.1, EveryNth; Table 1): out_idx[k] = floor(k*n/n_out)
+ * for k = 0..n_out-1, the n_out evenly spaced indices; n <= n_out writes
+ * 0..n-1. out_idx receives min(n, n_out) indices; no data is read and no
+ * workspace is used. Limits: 1 <= n <= 2^62; 1 <= n_out <= 2^31-1;
+ * otherwise MMLTTB_EINVAL. */
+int mmlttb_everynth(int64_t n, int64_t n_out, int64_t *out_idx, void *stream);
 
 /* Graph replay of batched calls. With max_graphs > 0, a batched call on a
  * non-default stream is captured into a HIP graph (segment-table upload from

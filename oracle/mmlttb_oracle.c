@@ -56,10 +56,10 @@
  *       the lowest-index maximum (section 2.2.1); floor(n_out / 4)
  *       equal-index bins over all points, part b = [floor(b n / nb),
  *       floor((b+1) n / nb)); output sorted distinct; n <= n_out keeps
- *       every index; n_out < 4 is an argument error.
+ *       every index; n < 1 or n_out < 4 is an argument error.
  *   R13 EveryNth keeps n_out evenly spaced indices floor(k n / n_out),
  *       k = 0..n_out-1 (section 2.2.1); n <= n_out keeps every index;
- *       n_out < 1 is an argument error.
+ *       n < 1 or n_out < 1 is an argument error.
  */
 #include <math.h>
 #include <stdint.h>
@@ -490,7 +490,7 @@ int oracle_m4(const float *y, int64_t n, int64_t n_out, int64_t *out, int64_t *c
 /* out: capacity min(n, n_out). */
 int oracle_everynth(int64_t n, int64_t n_out, int64_t *out)
 {
-    if (n < 0 || n_out < 1)
+    if (n < 1 || n_out < 1)
         return ORC_EINVAL;
     if (n <= n_out) {
         for (int64_t i = 0; i < n; i++)

@@ -8,7 +8,10 @@ library is not built.
 """
 from .ops import (  # noqa: F401
     batched_workspace_size,
+    everynth,
     lttb,
+    m4,
+    m4_workspace_size,
     minmaxlttb_batched,
     segment_table,
     lttb_workspace_size,

@@ -29,6 +29,9 @@ EXPORTS = (
     "mmlttb_minmaxlttb",
     "mmlttb_batched_workspace_size",
     "mmlttb_minmaxlttb_batched",
+    "mmlttb_m4_workspace_size",
+    "mmlttb_m4",
+    "mmlttb_everynth",
     "mmlttb_set_graph_cache",
     "mmlttb_graph_cache_stats",
     "mmlttb_set_tuning",
@@ -83,6 +86,10 @@ def load(path: str = LIB_PATH):
     lib.mmlttb_batched_workspace_size.restype = ctypes.c_size_t
     lib.mmlttb_minmaxlttb_batched.argtypes = [ctypes.c_int, _vp, _vp, ctypes.POINTER(Segment), _i64, _vp, _vp,
                                               ctypes.c_size_t, _vp]
+    lib.mmlttb_m4_workspace_size.argtypes = [_i64, _i64]
+    lib.mmlttb_m4_workspace_size.restype = ctypes.c_size_t
+    lib.mmlttb_m4.argtypes = [_vp, _i64, _i64, _vp, _vp, _vp, ctypes.c_size_t, _vp]
+    lib.mmlttb_everynth.argtypes = [_i64, _i64, _vp, _vp]
     lib.mmlttb_set_graph_cache.argtypes = [ctypes.c_int]
     lib.mmlttb_graph_cache_stats.argtypes = [ctypes.POINTER(_i64)] * 3
     lib.mmlttb_set_tuning.argtypes = [ctypes.c_int, _i64, ctypes.c_int, ctypes.c_int]
@@ -90,11 +97,9 @@ def load(path: str = LIB_PATH):
                                       ctypes.POINTER(ctypes.c_int)]
     lib.mmlttb_profile_enable.argtypes = [ctypes.c_int]
     lib.mmlttb_profile_read.argtypes = [ctypes.c_char_p, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_i64)]
-    for f in ("mmlttb_minmax", "mmlttb_lttb", "mmlttb_minmaxlttb", "mmlttb_minmaxlttb_batched",
-              "mmlttb_set_graph_cache",
-    "mmlttb_graph_cache_stats",
-    "mmlttb_set_tuning", "mmlttb_get_tuning",
-              "mmlttb_profile_enable", "mmlttb_profile_reset", "mmlttb_profile_read"):
+    for f in ("mmlttb_minmax", "mmlttb_lttb", "mmlttb_minmaxlttb", "mmlttb_minmaxlttb_batched", "mmlttb_m4",
+              "mmlttb_everynth", "mmlttb_set_graph_cache", "mmlttb_graph_cache_stats", "mmlttb_set_tuning",
+              "mmlttb_get_tuning", "mmlttb_profile_enable", "mmlttb_profile_reset", "mmlttb_profile_read"):
         getattr(lib, f).restype = ctypes.c_int
     _lib = lib
     return lib

@@ -221,10 +221,10 @@ int check_series(int xk, const int64_t *x, const float *y, int64_t n, int64_t n_
     return MMLTTB_OK;
 }
 
-int check_rps(int64_t n, int64_t n_out, int32_t r_ps)
+int check_rps(int64_t n, int64_t n_out, int32_t r_ps, int32_t min_rps = 2)
 {
-    if (r_ps < 2)
-        return fail(MMLTTB_EINVAL, "r_ps must be >= 2, got %d", r_ps);
+    if (r_ps < min_rps)
+        return fail(MMLTTB_EINVAL, "r_ps must be >= %d, got %d", min_rps, r_ps);
     const int64_t nb = n_out * (int64_t)r_ps / 2;
     if (nb > kMaxI32)
         return fail(MMLTTB_EINVAL, "floor(n_out*r_ps/2) must be <= 2^31-1, got %lld", (long long)nb);
@@ -245,11 +245,12 @@ int check_rps(int64_t n, int64_t n_out, int32_t r_ps)
             return fail(MMLTTB_EDEVICE, "%s launch failed: %s", name, hipGetErrorString(e_));                          \
     } while (0)
 
-MinMaxGeom minmax_geom(int64_t n, int64_t nb)
+// Bins over `len` points (the interior n-2 for MinMax, all n for M4).
+MinMaxGeom minmax_geom(int64_t len, int64_t nb)
 {
     const Tuning &t = tuning();
     MinMaxGeom g;
-    g.bins = make_split(n - 2, nb);
+    g.bins = make_split(len, nb);
     const int64_t maxbin = g.bins.q + (g.bins.r ? 1 : 0);
     g.chunk = t.chunk;
     g.chunks_per_bin = (maxbin + g.chunk - 1) / g.chunk;
@@ -300,7 +301,7 @@ int enqueue_preselect(const int64_t *x, const float *y, int64_t n, int64_t n_out
         return MMLTTB_OK;
     }
     unsigned long long *keys = at<unsigned long long>(ws, L.keys);
-    const MinMaxGeom g = minmax_geom(n, nb);
+    const MinMaxGeom g = minmax_geom(n - 2, nb);
     MMLTTB_LAUNCH("init_keys", s, launch_init_keys(keys, nb, s));
     MMLTTB_LAUNCH("minmax_bin_reduce", s, launch_minmax_bin_reduce(y, g, tuning().unroll, keys, s));
     MMLTTB_LAUNCH("preselect_compact", s, launch_preselect_compact(keys, g.bins, n, x, y, P, XP, YP, m_out, s));
@@ -604,7 +605,7 @@ const char *mmlttb_last_error(void) { return g_err.c_str(); }
 size_t mmlttb_workspace_size(int64_t n, int64_t n_out, int32_t r_ps)
 {
     (void)n;
-    if (n_out < 3 || n_out > kMaxI32 || r_ps < 2 || n_out * (int64_t)r_ps / 2 > kMaxI32)
+    if (n_out < 3 || n_out > kMaxI32 || r_ps < 1 || n_out * (int64_t)r_ps / 2 > kMaxI32)
         return 0;
     return mm_layout(n_out, r_ps).total;
 }
@@ -623,7 +624,7 @@ int mmlttb_minmax(int xk, const int64_t *x, const float *y, int64_t n, int64_t n
     int rc = check_series(xk, x, y, n, n_out);
     if (rc)
         return rc;
-    if ((rc = check_rps(n, n_out, r_ps)))
+    if ((rc = check_rps(n, n_out, r_ps, 1)))
         return rc;
     if (!out_idx || !out_count)
         return fail(MMLTTB_EINVAL, "out_idx and out_count must not be NULL");
@@ -712,7 +713,7 @@ int mmlttb_minmaxlttb(int xk, const int64_t *x, const float *y, int64_t n, int64
         MMLTTB_LAUNCH("bucket_mean", s, launch_bucket_mean_small(XP, YP, m, 0, B, MX, MY, s));
     } else {
         unsigned long long *keys = at<unsigned long long>(ws, L.keys);
-        const MinMaxGeom g = minmax_geom(n, nb);
+        const MinMaxGeom g = minmax_geom(n - 2, nb);
         MMLTTB_LAUNCH("init_keys", s, launch_init_keys(keys, nb, s));
         MMLTTB_LAUNCH("minmax_bin_reduce", s, launch_minmax_bin_reduce(y, g, tuning().unroll, keys, s));
         MMLTTB_LAUNCH("preselect_compact_means", s,
@@ -725,6 +726,64 @@ int mmlttb_minmaxlttb(int xk, const int64_t *x, const float *y, int64_t n, int64
         MMLTTB_LAUNCH("lttb_chain_seg", s, launch_lttb_chain_seg(a, P, out_idx, s));
     } else {
         MMLTTB_LAUNCH("lttb_chain", s, launch_lttb_chain(XP, YP, m, 0, B, MX, MY, P, out_idx, s));
+    }
+    return ok();
+}
+
+size_t mmlttb_m4_workspace_size(int64_t n, int64_t n_out)
+{
+    (void)n;
+    if (n_out < 4 || n_out > kMaxI32)
+        return 0;
+    return align_up(16 * (size_t)(n_out / 4));
+}
+
+int mmlttb_m4(const float *y, int64_t n, int64_t n_out, int64_t *out_idx, int64_t *out_count, void *ws,
+              size_t ws_bytes, void *stream)
+{
+    if (!y || ((uintptr_t)y & 3u))
+        return fail(MMLTTB_EINVAL, "y must be a non-NULL 4-byte aligned pointer");
+    if (n < 1 || n > kMaxN)
+        return fail(MMLTTB_EINVAL, "n must be in [1, 2^62], got %lld", (long long)n);
+    if (n_out < 4 || n_out > kMaxI32)
+        return fail(MMLTTB_EINVAL, "n_out must be in [4, 2^31-1], got %lld", (long long)n_out);
+    if (!out_idx || !out_count)
+        return fail(MMLTTB_EINVAL, "out_idx and out_count must not be NULL");
+    hipStream_t s = (hipStream_t)stream;
+    if (n <= n_out) {
+        MMLTTB_LAUNCH("iota", s, launch_iota(out_idx, n, out_count, s));
+        return ok();
+    }
+    const int64_t nb = n_out / 4;
+    const int64_t maxbin = n / nb + (n % nb ? 1 : 0);
+    if (maxbin >= ((int64_t)1 << 32))
+        return fail(MMLTTB_EINVAL, "M4 bins of %lld points exceed 2^32-1", (long long)maxbin);
+    const size_t need = mmlttb_m4_workspace_size(n, n_out);
+    if (!ws)
+        return fail(MMLTTB_EINVAL, "ws must not be NULL");
+    if (ws_bytes < need)
+        return fail(MMLTTB_ENOMEM, "workspace of %zu bytes is below the %zu required", ws_bytes, need);
+    unsigned long long *keys = static_cast<unsigned long long *>(ws);
+    const MinMaxGeom g = minmax_geom(n, nb);
+    MMLTTB_LAUNCH("init_keys", s, launch_init_keys(keys, nb, s));
+    MMLTTB_LAUNCH("m4_bin_reduce", s, launch_m4_bin_reduce(y, g, tuning().unroll, keys, s));
+    MMLTTB_LAUNCH("m4_compact", s, launch_m4_compact(keys, g.bins, out_idx, out_count, s));
+    return ok();
+}
+
+int mmlttb_everynth(int64_t n, int64_t n_out, int64_t *out_idx, void *stream)
+{
+    if (n < 1 || n > kMaxN)
+        return fail(MMLTTB_EINVAL, "n must be in [1, 2^62], got %lld", (long long)n);
+    if (n_out < 1 || n_out > kMaxI32)
+        return fail(MMLTTB_EINVAL, "n_out must be in [1, 2^31-1], got %lld", (long long)n_out);
+    if (!out_idx)
+        return fail(MMLTTB_EINVAL, "out_idx must not be NULL");
+    hipStream_t s = (hipStream_t)stream;
+    if (n <= n_out) {
+        MMLTTB_LAUNCH("iota", s, launch_iota(out_idx, n, nullptr, s));
+    } else {
+        MMLTTB_LAUNCH("everynth", s, launch_everynth(n, n_out, out_idx, s));
     }
     return ok();
 }

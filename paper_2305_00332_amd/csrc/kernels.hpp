@@ -130,6 +130,11 @@ hipError_t launch_preselect_compact_means(const unsigned long long *keys, const 
 hipError_t launch_preselect_all(int64_t n, const int64_t *x, const float *y, int64_t *P, int64_t *XP, float *YP,
                                 int64_t *m_out, hipStream_t s);
 hipError_t launch_iota(int64_t *out, int64_t n, int64_t *count_out, hipStream_t s);
+hipError_t launch_m4_bin_reduce(const float *y, const MinMaxGeom &g, int unroll, unsigned long long *keys,
+                                hipStream_t s);
+hipError_t launch_m4_compact(const unsigned long long *keys, const Split &bins, int64_t *out, int64_t *count,
+                             hipStream_t s);
+hipError_t launch_everynth(int64_t n, int64_t n_out, int64_t *out, hipStream_t s);
 
 hipError_t launch_bucket_mean_small(const int64_t *XP, const float *YP, const int64_t *m_ptr, int64_t m_const,
                                     int64_t B, double *MX, double *MY, hipStream_t s);

@@ -4,6 +4,9 @@
     idx = minmaxlttb(y, n_out=2000, r_ps=4, x=x)       # x: int64 cuda tensor
     P, m = minmax(y, n_out, r_ps)
     idx = lttb(y, n_out, x=x)
+    P, m = minmax(y, n_out, 1)                          # the MinMax downsampler
+    idx, m = m4(y, n_out)
+    idx = everynth(n, n_out, device=y.device)
 
 Each call only checks tensor types and passes pointers; the C library checks
 the arguments again and runs the whole path in HIP kernels on the current
@@ -60,6 +63,36 @@ def minmax(y, n_out: int, r_ps: int, x=None, out=None, count=None, ws=None, sync
         return out, count
     m = int(count.item())
     return out[:m], m
+
+
+def m4_workspace_size(n: int, n_out: int) -> int:
+    return int(_lib.load().mmlttb_m4_workspace_size(n, n_out))
+
+
+def m4(y, n_out: int, out=None, count=None, ws=None, sync: bool = True):
+    """M4: per equal-index bin the first, last, min and max point. Returns
+    (idx, m) with the sorted distinct indices in idx[:m]; with sync=False, m is
+    the device scalar tensor instead."""
+    lib = _lib.load()
+    _as_series(y, None)
+    n = y.numel()
+    out = out if out is not None else torch.empty(max(n_out, 1), dtype=torch.int64, device=y.device)
+    count = count if count is not None else torch.empty(1, dtype=torch.int64, device=y.device)
+    ws = _workspace(lib.mmlttb_m4_workspace_size(n, n_out), y.device, ws)
+    _lib.check(lib.mmlttb_m4(y.data_ptr(), n, n_out, out.data_ptr(), count.data_ptr(), ws.data_ptr(), ws.numel(),
+                             _lib.stream_ptr()))
+    if not sync:
+        return out, count
+    m = int(count.item())
+    return out[:m], m
+
+
+def everynth(n: int, n_out: int, out=None, device="cuda"):
+    """EveryNth: the min(n, n_out) indices floor(k*n/n_out)."""
+    lib = _lib.load()
+    out = out if out is not None else torch.empty(max(min(n, n_out), 1), dtype=torch.int64, device=device)
+    _lib.check(lib.mmlttb_everynth(n, n_out, out.data_ptr(), _lib.stream_ptr()))
+    return out[: min(n, n_out)]
 
 
 def lttb(y, n_out: int, x=None, out=None, ws=None):

@@ -34,7 +34,7 @@ def test_minmax_r1_matches_numpy(seed):
     assert np.array_equal(oracle.minmax(y, n_out, 1), pins.minmax_by_numpy(y, n_out, 1))
 
 
-@pytest.mark.parametrize("n,n_out", [(0, 5), (1, 5), (5, 5), (6, 5), (10, 3), (1000, 7), (10 ** 7 + 3, 997),
+@pytest.mark.parametrize("n,n_out", [(1, 5), (5, 5), (6, 5), (10, 3), (1000, 7), (10 ** 7 + 3, 997),
                                      (2 ** 40 + 11, 4001)])
 def test_everynth_is_part_starts(n, n_out):
     got = oracle.everynth(n, n_out)
@@ -55,3 +55,5 @@ def test_m4_keeps_bin_edges_and_errors():
         oracle.m4(y, 3)
     with pytest.raises(oracle.OracleError):
         oracle.everynth(10, 0)
+    with pytest.raises(oracle.OracleError):
+        oracle.everynth(0, 10)
