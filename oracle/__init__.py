@@ -18,6 +18,8 @@ from .oracle import (  # noqa: F401
     m4,
     everynth,
     minmax,
+    minmax_xbins,
+    minmaxlttb_xbins,
     minmaxlttb,
     XK_IMPLICIT,
     XK_INT64,

@@ -60,6 +60,15 @@
  *   R13 EveryNth keeps n_out evenly spaced indices floor(k n / n_out),
  *       k = 0..n_out-1 (section 2.2.1); n <= n_out keeps every index;
  *       n < 1 or n_out < 1 is an argument error.
+ *
+ * Bins equal in x (a variant for irregular timestamps; a bin has edges, Fig. 3):
+ *   R14 x int64, strictly increasing. The interior points 1..n-2 fall into nb
+ *       bins of equal x width: edges e_b = x_1 + floor(b (x_{n-1} - x_1) / nb),
+ *       b = 0..nb, and point i is in bin b when e_b <= x_i < e_{b+1}. For
+ *       x_i = i this is the equal-index binning of R2. Extrema, ties and P as
+ *       R3-R4; bins may be empty (gaps in x), so P may hold n_out points or
+ *       fewer; LTTB then keeps every point of P (R9 applied to P). The output
+ *       count is min(m, n_out) when n > n_out, else n.
  */
 #include <math.h>
 #include <stdint.h>
@@ -433,6 +442,123 @@ int oracle_minmaxlttb(int xk, const int64_t *x, const float *y, int64_t n, int64
         int64_t cnt = m < n_out ? m : n_out;
         for (int64_t i = 0; i < cnt; i++)
             out[i] = P[pos[i]];
+    }
+    free(P);
+    free(xs);
+    free(ys);
+    free(pos);
+    return rc;
+}
+
+/* ------------------------------------------------------------------------ */
+/* MinMax bins equal in x (R14).                                              */
+/* ------------------------------------------------------------------------ */
+
+/* Edge b of nb equal x-width bins over [x1, xlast]. */
+static int64_t x_edge(int64_t x1, int64_t xlast, int64_t b, int64_t nb)
+{
+    __int128 span = (__int128)xlast - (__int128)x1;
+    return (int64_t)((__int128)x1 + (span * b) / nb);
+}
+
+int oracle_minmax_xbins(const int64_t *x, const float *y, int64_t n, int64_t n_out, int32_t r_ps, int64_t *P,
+                        int64_t *m)
+{
+    if (n < 1 || n_out < 3 || r_ps < 1 || !x)
+        return ORC_EINVAL;
+    for (int64_t i = 0; i < n; i++)
+        if (!is_finite_f32(y[i]))
+            return ORC_ENOTFINITE;
+    for (int64_t i = 1; i < n; i++)
+        if (x[i] <= x[i - 1])
+            return ORC_EINVAL;
+    int64_t cnt = 0;
+    if (n <= 2) {
+        for (int64_t i = 0; i < n; i++)
+            P[cnt++] = i;
+        *m = cnt;
+        return ORC_OK;
+    }
+    int64_t nb = (int64_t)(((__int128)n_out * r_ps) / 2); /* R1, R14 */
+    P[cnt++] = 0;
+    int64_t lo = 1; /* first interior point with x >= the current bin's left edge */
+    for (int64_t b = 0; b < nb; b++) {
+        int64_t right = x_edge(x[1], x[n - 1], b + 1, nb);
+        int64_t hi = lo;
+        while (hi < n - 1 && x[hi] < right)
+            hi++;
+        if (hi > lo) {
+            int64_t imin = lo, imax = lo;
+            for (int64_t i = lo + 1; i < hi; i++) {
+                if (y[i] < y[imin]) /* lowest index on ties (R14, R3) */
+                    imin = i;
+                if (y[i] > y[imax]) /* lowest index on ties (R14, R3) */
+                    imax = i;
+            }
+            P[cnt++] = imin;
+            if (imax != imin)
+                P[cnt++] = imax;
+        }
+        lo = hi;
+    }
+    P[cnt++] = n - 1;
+    qsort(P, (size_t)cnt, sizeof(int64_t), cmp_i64);
+    int64_t d = 0;
+    for (int64_t i = 0; i < cnt; i++)
+        if (d == 0 || P[i] != P[d - 1])
+            P[d++] = P[i];
+    *m = d;
+    return ORC_OK;
+}
+
+/* out: capacity n_out (or n when n <= n_out); *count = entries written. */
+int oracle_minmaxlttb_xbins(const int64_t *x, const float *y, int64_t n, int64_t n_out, int32_t r_ps, int64_t *out,
+                            int64_t *count)
+{
+    if (n < 1 || n_out < 3 || r_ps < 2 || !x)
+        return ORC_EINVAL;
+    if (n <= n_out) {
+        for (int64_t i = 0; i < n; i++)
+            if (!is_finite_f32(y[i]))
+                return ORC_ENOTFINITE;
+        for (int64_t i = 1; i < n; i++)
+            if (x[i] <= x[i - 1])
+                return ORC_EINVAL;
+        for (int64_t i = 0; i < n; i++)
+            out[i] = i;
+        *count = n;
+        return ORC_OK;
+    }
+    int64_t nb = (int64_t)(((__int128)n_out * r_ps) / 2);
+    int64_t *P = (int64_t *)malloc(sizeof(int64_t) * (size_t)(2 * nb + 2));
+    if (!P)
+        return ORC_ENOMEM;
+    int64_t m = 0;
+    int rc = oracle_minmax_xbins(x, y, n, n_out, r_ps, P, &m);
+    if (rc != ORC_OK) {
+        free(P);
+        return rc;
+    }
+    int64_t *xs = (int64_t *)malloc(sizeof(int64_t) * (size_t)m);
+    float *ys = (float *)malloc(sizeof(float) * (size_t)m);
+    int64_t *pos = (int64_t *)malloc(sizeof(int64_t) * (size_t)(m < n_out ? m : n_out));
+    if (!xs || !ys || !pos) {
+        free(P);
+        free(xs);
+        free(ys);
+        free(pos);
+        return ORC_ENOMEM;
+    }
+    for (int64_t i = 0; i < m; i++) {
+        xs[i] = x[P[i]];
+        ys[i] = y[P[i]];
+    }
+    rc = lttb_positions(xs, ys, m, n_out, pos);
+    if (rc == ORC_OK) {
+        int64_t c = m < n_out ? m : n_out;
+        for (int64_t i = 0; i < c; i++)
+            out[i] = P[pos[i]];
+        *count = c;
     }
     free(P);
     free(xs);

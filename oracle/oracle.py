@@ -58,9 +58,13 @@ def _bind(path: str):
     lib.oracle_exact_sum_f32.argtypes = [_f32p, ctypes.c_int64, _f64p]
     lib.oracle_exact_sum_i64.argtypes = [_i64p, ctypes.c_int64, _f64p]
     lib.oracle_m4.argtypes = [_f32p, ctypes.c_int64, ctypes.c_int64, _i64p, _i64p]
+    lib.oracle_minmax_xbins.argtypes = [_i64p, _f32p, ctypes.c_int64, ctypes.c_int64, ctypes.c_int32, _i64p, _i64p]
+    lib.oracle_minmaxlttb_xbins.argtypes = [_i64p, _f32p, ctypes.c_int64, ctypes.c_int64, ctypes.c_int32, _i64p,
+                                            _i64p]
     lib.oracle_everynth.argtypes = [ctypes.c_int64, ctypes.c_int64, _i64p]
     for f in ("oracle_minmax", "oracle_lttb", "oracle_minmaxlttb", "oracle_lttb_means",
-              "oracle_exact_sum_f32", "oracle_exact_sum_i64", "oracle_m4", "oracle_everynth"):
+              "oracle_exact_sum_f32", "oracle_exact_sum_i64", "oracle_m4", "oracle_everynth",
+              "oracle_minmax_xbins", "oracle_minmaxlttb_xbins"):
         getattr(lib, f).restype = ctypes.c_int
     return lib
 
@@ -97,6 +101,8 @@ def compile_variant(src_text: str, out_path: str):
     v.minmaxlttb = lambda y, n_out, r_ps, x=None: minmaxlttb(y, n_out, r_ps, x, _lib_override=lib)
     v.lttb_means = lambda y, n_out, x=None: lttb_means(y, n_out, x, _lib_override=lib)
     v.m4 = lambda y, n_out: m4(y, n_out, _lib_override=lib)
+    v.minmax_xbins = lambda y, x, n_out, r_ps: minmax_xbins(y, x, n_out, r_ps, _lib_override=lib)
+    v.minmaxlttb_xbins = lambda y, x, n_out, r_ps: minmaxlttb_xbins(y, x, n_out, r_ps, _lib_override=lib)
     v.everynth = lambda n, n_out: everynth(n, n_out, _lib_override=lib)
     v.exact_sum_f32 = lambda a: exact_sum_f32(a, _lib_override=lib)
     v.exact_sum_i64 = lambda a: exact_sum_i64(a, _lib_override=lib)
@@ -141,6 +147,37 @@ def minmax(y, n_out: int, r_ps: int, _lib_override=None) -> np.ndarray:
     if rc != 0:
         raise OracleError(rc, "minmax")
     return P[: m.value].copy()
+
+
+def minmax_xbins(y, x, n_out: int, r_ps: int, _lib_override=None) -> np.ndarray:
+    """MinMax preselection with bins of equal x width (reading R14)."""
+    y = _f32(y)
+    x = np.ascontiguousarray(x, dtype=np.int64)
+    n = y.shape[0]
+    assert x.shape[0] == n
+    nb = n_out * r_ps // 2
+    P = np.empty(max(2 * nb + 2, n if n <= 2 else 0, 1), dtype=np.int64)
+    m = ctypes.c_int64(0)
+    rc = (_lib_override or _load()).oracle_minmax_xbins(x.ctypes.data_as(_i64p), _ptr(y, _f32p), n, n_out, r_ps,
+                                                        P.ctypes.data_as(_i64p), ctypes.byref(m))
+    if rc != 0:
+        raise OracleError(rc, "minmax_xbins")
+    return P[: m.value].copy()
+
+
+def minmaxlttb_xbins(y, x, n_out: int, r_ps: int, _lib_override=None) -> np.ndarray:
+    """MinMaxLTTB with MinMax bins of equal x width (reading R14)."""
+    y = _f32(y)
+    x = np.ascontiguousarray(x, dtype=np.int64)
+    n = y.shape[0]
+    assert x.shape[0] == n
+    out = np.empty(max(min(n, n_out), 1), dtype=np.int64)
+    cnt = ctypes.c_int64(0)
+    rc = (_lib_override or _load()).oracle_minmaxlttb_xbins(x.ctypes.data_as(_i64p), _ptr(y, _f32p), n, n_out, r_ps,
+                                                            out.ctypes.data_as(_i64p), ctypes.byref(cnt))
+    if rc != 0:
+        raise OracleError(rc, "minmaxlttb_xbins")
+    return out[: cnt.value].copy()
 
 
 def m4(y, n_out: int, _lib_override=None) -> np.ndarray:

@@ -157,3 +157,30 @@ def everynth_by_parts(n: int, n_out: int) -> np.ndarray:
     if n <= n_out:
         return np.arange(n, dtype=np.int64)
     return np.array([lo for lo, _ in partition_by_inequality(n, n_out)], dtype=np.int64)
+
+
+def xbin_starts(x: np.ndarray, nb: int) -> np.ndarray:
+    """Start index of each of nb equal x-width bins over the interior points,
+    edges in exact Python integers, located with numpy's searchsorted."""
+    n = len(x)
+    x1, xl = int(x[1]), int(x[n - 1])
+    edges = [x1 + (b * (xl - x1)) // nb for b in range(nb + 1)]
+    inner = x[1:n - 1]
+    starts = np.searchsorted(inner, np.array(edges[:-1], dtype=np.int64), side="left") + 1
+    return np.append(starts, n - 1).astype(np.int64)
+
+
+def minmax_xbins_by_numpy(y: np.ndarray, x: np.ndarray, n_out: int, r_ps: int) -> np.ndarray:
+    n = len(y)
+    if n <= 2:
+        return np.arange(n, dtype=np.int64)
+    nb = n_out * r_ps // 2
+    st = xbin_starts(x, nb)
+    sel = {0, n - 1}
+    for b in range(nb):
+        lo, hi = int(st[b]), int(st[b + 1])
+        if hi > lo:
+            seg = y[lo:hi]
+            sel.add(lo + int(np.argmin(seg)))
+            sel.add(lo + int(np.argmax(seg)))
+    return np.array(sorted(sel), dtype=np.int64)

@@ -57,3 +57,63 @@ def test_m4_keeps_bin_edges_and_errors():
         oracle.everynth(10, 0)
     with pytest.raises(oracle.OracleError):
         oracle.everynth(0, 10)
+
+
+# ---------------------------------------------------------------- x-equal-width bins (R14)
+
+def _gappy_x(n, seed):
+    """Strictly increasing int64 x with exponential gaps and a few huge jumps."""
+    rng = np.random.default_rng(seed)
+    gaps = 1 + np.floor(rng.exponential(50.0, size=n)).astype(np.int64)
+    jumps = rng.random(n) < 0.002
+    gaps[jumps] += rng.integers(10 ** 6, 10 ** 9, size=int(jumps.sum()))
+    return np.cumsum(gaps) - 7_000_000 + int(rng.integers(-10 ** 12, 10 ** 12))
+
+
+@pytest.mark.parametrize("seed", range(30))
+def test_xbins_with_unit_steps_is_index_binning(seed):
+    rng = np.random.default_rng(700 + seed)
+    n = int(rng.integers(1, 4000))
+    n_out = int(rng.integers(3, 300))
+    r_ps = int(rng.choice([1, 2, 4, 8]))
+    y = _series(seed, n)
+    x = np.arange(n, dtype=np.int64) + int(rng.integers(-10 ** 15, 10 ** 15))
+    assert np.array_equal(oracle.minmax_xbins(y, x, n_out, r_ps), oracle.minmax(y, n_out, r_ps))
+    if r_ps >= 2:
+        assert np.array_equal(oracle.minmaxlttb_xbins(y, x, n_out, r_ps), oracle.minmaxlttb(y, n_out, r_ps, x))
+
+
+@pytest.mark.parametrize("seed", range(40))
+def test_xbins_matches_numpy_and_lttb_over_p(seed):
+    rng = np.random.default_rng(800 + seed)
+    n = int(rng.integers(3, 5000))
+    n_out = int(rng.integers(3, 400))
+    r_ps = int(rng.choice([2, 4, 8]))
+    y = _series(seed, n)
+    x = _gappy_x(n, seed) if seed % 3 else synth.to_numpy(synth.irregular_x(n, seed))
+    want_p = pins.minmax_xbins_by_numpy(y, x, n_out, r_ps)
+    assert np.array_equal(oracle.minmax_xbins(y, x, n_out, r_ps), want_p)
+    got = oracle.minmaxlttb_xbins(y, x, n_out, r_ps)
+    if n <= n_out:
+        assert np.array_equal(got, np.arange(n))
+    else:  # LTTB over the preselected points (itself pinned), or all of them
+        assert np.array_equal(got, want_p[oracle.lttb(y[want_p], n_out, x[want_p])])
+
+
+def test_xbins_sparse_preselection_keeps_every_point():
+    # two clusters far apart: almost every bin is empty, P holds fewer than n_out points
+    x = np.concatenate([np.arange(500), 10 ** 12 + np.arange(500)]).astype(np.int64)
+    y = synth.to_numpy(synth.random_walk(1000, 5))
+    P = oracle.minmax_xbins(y, x, 100, 4)
+    assert len(P) < 100
+    assert np.array_equal(oracle.minmaxlttb_xbins(y, x, 100, 4), P)
+
+
+def test_xbins_errors():
+    y = synth.to_numpy(synth.random_walk(100, 1))
+    x = np.arange(100, dtype=np.int64)
+    x[50] = x[49]
+    with pytest.raises(oracle.OracleError):
+        oracle.minmax_xbins(y, x, 10, 4)
+    with pytest.raises(oracle.OracleError):
+        oracle.minmaxlttb_xbins(y, np.arange(100), 10, 1)

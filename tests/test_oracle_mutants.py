@@ -56,6 +56,11 @@ MUTANTS = {
     "no_first_point": ("    P[cnt++] = 0;\n    for (int64_t b = 0;", "    for (int64_t b = 0;"),
     "m4_no_last": ("        out[cnt++] = hi - 1;\n", ""),
     "m4_bins_not_quartered": ("    int64_t nb = n_out / 4;", "    int64_t nb = n_out / 2;"),
+    "xbin_edges_from_first_point": ("int64_t right = x_edge(x[1], x[n - 1], b + 1, nb);",
+                                    "int64_t right = x_edge(x[0], x[n - 1], b + 1, nb);"),
+    "xbin_right_edge_inclusive": ("while (hi < n - 1 && x[hi] < right)", "while (hi < n - 1 && x[hi] <= right)"),
+    "xbin_min_tie_highest": ("if (y[i] < y[imin]) /* lowest index on ties (R14, R3) */",
+                             "if (y[i] <= y[imin]) /* lowest index on ties (R14, R3) */"),
     "everynth_ceil": ("        out[k] = floor_frac(k, n, n_out);", "        out[k] = (k * n + n_out - 1) / n_out;"),
 }
 
@@ -102,6 +107,14 @@ def _passes_pins(v) -> bool:
             if not np.array_equal(v.m4(y, 8 + 4 * seed), pins.m4_by_numpy(y, 8 + 4 * seed)):
                 return False
             if not np.array_equal(v.everynth(1000 + seed, 7 + seed), pins.everynth_by_parts(1000 + seed, 7 + seed)):
+                return False
+        # x-equal-width bins vs numpy
+        for seed in range(6):
+            n = 400 + 131 * seed
+            gen = synth.ties_series if seed % 2 else synth.random_walk
+            y = synth.to_numpy(gen(n, seed))
+            x = np.cumsum(1 + (np.arange(n) * 7919 + seed) % 13).astype(np.int64)
+            if not np.array_equal(v.minmax_xbins(y, x, 10 + seed, 4), pins.minmax_xbins_by_numpy(y, x, 10 + seed, 4)):
                 return False
         # exact-regime LTTB vs rationals
         for seed in range(30):
