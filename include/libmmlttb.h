@@ -132,6 +132,31 @@ size_t mmlttb_batched_workspace_size(const mmlttb_segment_t *segs_host, int64_t 
 int mmlttb_minmaxlttb_batched(int xk, const int64_t *x_base, const float *y_base, const mmlttb_segment_t *segs_host,
                               int64_t n_segs, int64_t *out_idx_base, void *ws, size_t ws_bytes, void *stream);
 
+/* Workspace bytes for mmlttb_minmax_xbins and mmlttb_minmaxlttb_xbins;
+ * independent of n. Returns 0 on invalid arguments. */
+size_t mmlttb_xbins_workspace_size(int64_t n, int64_t n_out, int32_t r_ps);
+
+/* MinMax preselection with bins of equal x WIDTH, for irregular timestamps
+ * (a bin has edges in x, Fig. 3; section 2.2.1 MinMax). x: int64[n], strictly
+ * increasing (precondition: unsorted x gives meaningless indices, never an
+ * access out of bounds). The interior points 1..n-2 fall into
+ * nb = floor(n_out*r_ps/2) bins with edges e_b = x_1 + floor(b*(x_{n-1}-x_1)/nb):
+ * point i is in bin b when e_b <= x_i < e_{b+1}. With x_i = i this is the
+ * equal-index binning of mmlttb_minmax. Empty bins (gaps) are skipped. Output
+ * as mmlttb_minmax: sorted distinct P in out_idx[0..m-1] (capacity
+ * 2*nb + 2, or n if smaller), m in the device scalar *out_count. Limits:
+ * 1 <= n <= 2^32+1, 3 <= n_out <= 2^31-1, r_ps >= 1, nb <= 2^31-1. */
+int mmlttb_minmax_xbins(const int64_t *x, const float *y, int64_t n, int64_t n_out, int32_t r_ps, int64_t *out_idx,
+                        int64_t *out_count, void *ws, size_t ws_bytes, void *stream);
+
+/* MinMaxLTTB (section 3) with the preselection of mmlttb_minmax_xbins. LTTB
+ * then runs over P as in mmlttb_minmaxlttb; when gaps leave P with n_out
+ * points or fewer, every point of P is kept. out_idx (capacity n_out)
+ * receives min(n, n_out, m) ascending indices and *out_count (device scalar)
+ * their number. r_ps >= 2; other limits as mmlttb_minmax_xbins. */
+int mmlttb_minmaxlttb_xbins(const int64_t *x, const float *y, int64_t n, int64_t n_out, int32_t r_ps,
+                            int64_t *out_idx, int64_t *out_count, void *ws, size_t ws_bytes, void *stream);
+
 /* Workspace bytes for mmlttb_m4 (one key pair per bin); independent of n.
  * Returns 0 on invalid arguments. */
 size_t mmlttb_m4_workspace_size(int64_t n, int64_t n_out);

@@ -16,6 +16,9 @@ from .ops import (  # noqa: F401
     segment_table,
     lttb_workspace_size,
     minmax,
+    minmax_xbins,
+    minmaxlttb_xbins,
+    xbins_workspace_size,
     minmaxlttb,
     profile_enable,
     profile_read,

@@ -308,6 +308,58 @@ int enqueue_preselect(const int64_t *x, const float *y, int64_t n, int64_t n_out
     return MMLTTB_OK;
 }
 
+// ---------------------------------------------------------------- x-width bins
+
+struct XbLayout {
+    MmLayout mm;
+    size_t bounds, m_eff, total;
+};
+
+XbLayout xb_layout(int64_t n_out, int32_t r_ps)
+{
+    XbLayout L;
+    L.mm = mm_layout(n_out, r_ps);
+    const int64_t nb = n_out * (int64_t)r_ps / 2;
+    L.bounds = L.mm.total;
+    L.m_eff = align_up(L.bounds + 8 * (size_t)(nb + 1));
+    L.total = align_up(L.m_eff + 8);
+    return L;
+}
+
+int check_xbins(const int64_t *x, const float *y, int64_t n, int64_t n_out, int32_t r_ps, int32_t min_rps)
+{
+    if (!x || !y)
+        return fail(MMLTTB_EINVAL, "x and y must not be NULL");
+    if (((uintptr_t)y & 3u) || ((uintptr_t)x & 7u))
+        return fail(MMLTTB_EINVAL, "y must be 4-byte and x 8-byte aligned");
+    if (n < 1 || n - 2 >= ((int64_t)1 << 32))
+        return fail(MMLTTB_EINVAL, "n must be in [1, 2^32+1] with bins of equal x width, got %lld", (long long)n);
+    if (n_out < 3 || n_out > kMaxI32)
+        return fail(MMLTTB_EINVAL, "n_out must be in [3, 2^31-1], got %lld", (long long)n_out);
+    if (r_ps < min_rps)
+        return fail(MMLTTB_EINVAL, "r_ps must be >= %d, got %d", min_rps, r_ps);
+    if (n_out * (int64_t)r_ps / 2 > kMaxI32)
+        return fail(MMLTTB_EINVAL, "floor(n_out*r_ps/2) must be <= 2^31-1");
+    return MMLTTB_OK;
+}
+
+// Bounds, keys and the stream over the interior; n > 2.
+int enqueue_xbin_stream(const int64_t *x, const float *y, int64_t n, int64_t nb, void *ws, const XbLayout &L,
+                        hipStream_t s)
+{
+    const Tuning &t = tuning();
+    int64_t *bounds = at<int64_t>(ws, L.bounds);
+    unsigned long long *keys = at<unsigned long long>(ws, L.mm.keys);
+    const int64_t gran = 256 * (int64_t)t.unroll;
+    const int64_t avg = (n - 2 + nb - 1) / nb;
+    int64_t chunk = (avg + gran - 1) / gran * gran;
+    chunk = chunk < t.chunk ? chunk : t.chunk;
+    MMLTTB_LAUNCH("xbin_bounds", s, launch_xbin_bounds(x, n, nb, bounds, s));
+    MMLTTB_LAUNCH("init_keys", s, launch_init_keys(keys, nb, s));
+    MMLTTB_LAUNCH("xbin_reduce", s, launch_xbin_reduce(y, bounds, n, nb, chunk, t.unroll, keys, s));
+    return MMLTTB_OK;
+}
+
 // ---------------------------------------------------------------- batch plan
 
 struct BatchPlan {
@@ -727,6 +779,83 @@ int mmlttb_minmaxlttb(int xk, const int64_t *x, const float *y, int64_t n, int64
     } else {
         MMLTTB_LAUNCH("lttb_chain", s, launch_lttb_chain(XP, YP, m, 0, B, MX, MY, P, out_idx, s));
     }
+    return ok();
+}
+
+size_t mmlttb_xbins_workspace_size(int64_t n, int64_t n_out, int32_t r_ps)
+{
+    (void)n;
+    if (n_out < 3 || n_out > kMaxI32 || r_ps < 1 || n_out * (int64_t)r_ps / 2 > kMaxI32)
+        return 0;
+    return xb_layout(n_out, r_ps).total;
+}
+
+int mmlttb_minmax_xbins(const int64_t *x, const float *y, int64_t n, int64_t n_out, int32_t r_ps, int64_t *out_idx,
+                        int64_t *out_count, void *ws, size_t ws_bytes, void *stream)
+{
+    int rc = check_xbins(x, y, n, n_out, r_ps, 1);
+    if (rc)
+        return rc;
+    if (!out_idx || !out_count)
+        return fail(MMLTTB_EINVAL, "out_idx and out_count must not be NULL");
+    hipStream_t s = (hipStream_t)stream;
+    if (n <= 2) {
+        MMLTTB_LAUNCH("iota", s, launch_iota(out_idx, n, out_count, s));
+        return ok();
+    }
+    const XbLayout L = xb_layout(n_out, r_ps);
+    if (!ws)
+        return fail(MMLTTB_EINVAL, "ws must not be NULL");
+    if (ws_bytes < L.total)
+        return fail(MMLTTB_ENOMEM, "workspace of %zu bytes is below the %zu required", ws_bytes, L.total);
+    const int64_t nb = n_out * (int64_t)r_ps / 2;
+    if ((rc = enqueue_xbin_stream(x, y, n, nb, ws, L, s)))
+        return rc;
+    MMLTTB_LAUNCH("xbin_compact", s,
+                  launch_xbin_compact(at<unsigned long long>(ws, L.mm.keys), at<int64_t>(ws, L.bounds), nb, n, x, y,
+                                      out_idx, nullptr, nullptr, out_count, nullptr, 0, 0, nullptr, nullptr, s));
+    return ok();
+}
+
+int mmlttb_minmaxlttb_xbins(const int64_t *x, const float *y, int64_t n, int64_t n_out, int32_t r_ps,
+                            int64_t *out_idx, int64_t *out_count, void *ws, size_t ws_bytes, void *stream)
+{
+    int rc = check_xbins(x, y, n, n_out, r_ps, 2);
+    if (rc)
+        return rc;
+    if (!out_idx || !out_count)
+        return fail(MMLTTB_EINVAL, "out_idx and out_count must not be NULL");
+    hipStream_t s = (hipStream_t)stream;
+    if (n <= n_out) {
+        MMLTTB_LAUNCH("iota", s, launch_iota(out_idx, n, out_count, s));
+        return ok();
+    }
+    const XbLayout L = xb_layout(n_out, r_ps);
+    if (!ws)
+        return fail(MMLTTB_EINVAL, "ws must not be NULL");
+    if (ws_bytes < L.total)
+        return fail(MMLTTB_ENOMEM, "workspace of %zu bytes is below the %zu required", ws_bytes, L.total);
+    const int64_t nb = n_out * (int64_t)r_ps / 2;
+    const int64_t B = n_out - 2;
+    if ((rc = enqueue_xbin_stream(x, y, n, nb, ws, L, s)))
+        return rc;
+    int64_t *P = at<int64_t>(ws, L.mm.P), *XP = at<int64_t>(ws, L.mm.XP), *m = at<int64_t>(ws, L.mm.m);
+    int64_t *m_eff = at<int64_t>(ws, L.m_eff);
+    float *YP = at<float>(ws, L.mm.YP);
+    double *MX = at<double>(ws, L.mm.MX), *MY = at<double>(ws, L.mm.MY);
+    MMLTTB_LAUNCH("xbin_compact", s,
+                  launch_xbin_compact(at<unsigned long long>(ws, L.mm.keys), at<int64_t>(ws, L.bounds), nb, n, x, y, P,
+                                      XP, YP, m, m_eff, n_out + 1, B, MX, MY, s));
+    // the LTTB pass runs on at most max(2*nb + 2, n_out + 1) points
+    const int64_t maxb_bound = (2 * nb + B - 1) / B;
+    if (use_segmented_chain(maxb_bound)) {
+        const SegChainArgs a = seg_args(ws, L.mm.path, L.mm.finals, L.mm.start, XP, YP, m_eff, 0, B, MX, MY,
+                                        maxb_bound);
+        MMLTTB_LAUNCH("lttb_chain_seg", s, launch_lttb_chain_seg(a, P, out_idx, s));
+    } else {
+        MMLTTB_LAUNCH("lttb_chain", s, launch_lttb_chain(XP, YP, m_eff, 0, B, MX, MY, P, out_idx, s));
+    }
+    MMLTTB_LAUNCH("xbin_finish", s, launch_xbin_finish(P, m, n_out, out_idx, out_count, s));
     return ok();
 }
 

@@ -135,6 +135,14 @@ hipError_t launch_m4_bin_reduce(const float *y, const MinMaxGeom &g, int unroll,
 hipError_t launch_m4_compact(const unsigned long long *keys, const Split &bins, int64_t *out, int64_t *count,
                              hipStream_t s);
 hipError_t launch_everynth(int64_t n, int64_t n_out, int64_t *out, hipStream_t s);
+hipError_t launch_xbin_bounds(const int64_t *x, int64_t n, int64_t nb, int64_t *bounds, hipStream_t s);
+hipError_t launch_xbin_reduce(const float *y, const int64_t *bounds, int64_t n, int64_t nb, int64_t chunk,
+                              int unroll, unsigned long long *keys, hipStream_t s);
+hipError_t launch_xbin_compact(const unsigned long long *keys, const int64_t *bounds, int64_t nb, int64_t n,
+                               const int64_t *x, const float *y, int64_t *P, int64_t *XP, float *YP, int64_t *m_true,
+                               int64_t *m_eff, int64_t pad_to, int64_t B, double *MX, double *MY, hipStream_t s);
+hipError_t launch_xbin_finish(const int64_t *P, const int64_t *m_true, int64_t n_out, int64_t *out, int64_t *count,
+                              hipStream_t s);
 
 hipError_t launch_bucket_mean_small(const int64_t *XP, const float *YP, const int64_t *m_ptr, int64_t m_const,
                                     int64_t B, double *MX, double *MY, hipStream_t s);

@@ -65,6 +65,50 @@ def minmax(y, n_out: int, r_ps: int, x=None, out=None, count=None, ws=None, sync
     return out[:m], m
 
 
+def xbins_workspace_size(n: int, n_out: int, r_ps: int) -> int:
+    return int(_lib.load().mmlttb_xbins_workspace_size(n, n_out, r_ps))
+
+
+def _xbins_series(y, x):
+    if x is None:
+        raise TypeError("bins of equal x width need x (int64, strictly increasing)")
+    _as_series(y, x)
+
+
+def minmax_xbins(y, x, n_out: int, r_ps: int, out=None, count=None, ws=None, sync: bool = True):
+    """MinMax preselection with bins of equal x width. Returns (P, m) as minmax()."""
+    lib = _lib.load()
+    _xbins_series(y, x)
+    n = y.numel()
+    cap = max(2 * (n_out * r_ps // 2) + 2, min(n, 2), 1)
+    out = out if out is not None else torch.empty(cap, dtype=torch.int64, device=y.device)
+    count = count if count is not None else torch.empty(1, dtype=torch.int64, device=y.device)
+    ws = _workspace(lib.mmlttb_xbins_workspace_size(n, n_out, r_ps), y.device, ws)
+    _lib.check(lib.mmlttb_minmax_xbins(x.data_ptr(), y.data_ptr(), n, n_out, r_ps, out.data_ptr(), count.data_ptr(),
+                                       ws.data_ptr(), ws.numel(), _lib.stream_ptr()))
+    if not sync:
+        return out, count
+    m = int(count.item())
+    return out[:m], m
+
+
+def minmaxlttb_xbins(y, x, n_out: int, r_ps: int, out=None, count=None, ws=None, sync: bool = True):
+    """MinMaxLTTB with MinMax bins of equal x width. Returns the selected
+    indices (fewer than n_out when gaps leave fewer preselected points); with
+    sync=False, (out, device count) instead."""
+    lib = _lib.load()
+    _xbins_series(y, x)
+    n = y.numel()
+    out = out if out is not None else torch.empty(max(min(n, n_out), 1), dtype=torch.int64, device=y.device)
+    count = count if count is not None else torch.empty(1, dtype=torch.int64, device=y.device)
+    ws = _workspace(lib.mmlttb_xbins_workspace_size(n, n_out, r_ps), y.device, ws)
+    _lib.check(lib.mmlttb_minmaxlttb_xbins(x.data_ptr(), y.data_ptr(), n, n_out, r_ps, out.data_ptr(),
+                                           count.data_ptr(), ws.data_ptr(), ws.numel(), _lib.stream_ptr()))
+    if not sync:
+        return out, count
+    return out[: int(count.item())]
+
+
 def m4_workspace_size(n: int, n_out: int) -> int:
     return int(_lib.load().mmlttb_m4_workspace_size(n, n_out))
 

@@ -174,6 +174,29 @@ def extreme_series(n: int, seed: int, device="cpu") -> torch.Tensor:
     return v
 
 
+def bursty_x(n: int, seed: int, mean_gap: float = 1000.0, outage_frac: float = 1e-3,
+             outage_len=(1e6, 1e9), start: int = 0, device="cpu") -> torch.Tensor:
+    """Strictly increasing int64 timestamps with outages: gaps as irregular_x,
+    plus, at a fraction outage_frac of the points, a jump drawn log-uniformly
+    from outage_len (sensor downtime; leaves runs of empty x-width bins)."""
+    base = irregular_x(n, seed, mean_gap=mean_gap, start=0, device=device)
+    g = _gen(seed + 7_000_003, device)
+    out = torch.empty(n, dtype=torch.int64, device=device)
+    carry = 0
+    lo_l, hi_l = math.log(outage_len[0]), math.log(outage_len[1])
+    for lo in range(0, n, _CHUNK):
+        hi = min(n, lo + _CHUNK)
+        u = torch.rand(hi - lo, generator=g, dtype=torch.float64, device=device)
+        v = torch.rand(hi - lo, generator=g, dtype=torch.float64, device=device)
+        jump = torch.where(u < outage_frac, torch.exp(lo_l + v * (hi_l - lo_l)).floor(), torch.zeros_like(v))
+        if lo == 0:
+            jump[0] = 0
+        js = torch.cumsum(jump.to(torch.int64), 0) + carry
+        carry = int(js[-1].item())
+        out[lo:hi] = base[lo:hi] + js + int(start)
+    return out
+
+
 def epoch_x(n: int, seed: int, device="cpu") -> torch.Tensor:
     """Nanosecond epoch timestamps (~1.7e18, above 2^53, so not exact in binary64)."""
     return irregular_x(n, seed, mean_gap=1000.0, start=1_700_000_000_123_456_789, device=device)
