@@ -71,6 +71,7 @@ def main():
     ap.add_argument("--skip-comparator", action="store_true")
     ap.add_argument("--skip-served", action="store_true")
     ap.add_argument("--skip-downsamplers", action="store_true")
+    ap.add_argument("--skip-xbins", action="store_true")
     ap.add_argument("--batch-series", type=int, default=4096)
     ap.add_argument("--pool-series", type=int, default=512)
     ap.add_argument("--rates", type=str, default="100,500,1000,2000,5000")
@@ -104,6 +105,8 @@ def main():
         del src, dst
     if not args.skip_downsamplers:
         result["downsamplers"] = bench_downsamplers(args)
+    if not args.skip_xbins:
+        result["xbins"] = bench_xbins(args)
     if not args.skip_comparator:
         result["comparator"] = bench_comparator(args)
     if not args.skip_batched:
@@ -245,6 +248,9 @@ def bench_downsamplers(args, reps: int = 10):
     import oracle
     from paper_2305_00332_amd import ops, synth
 
+    from paper_2305_00332_amd import autotune
+
+    autotune.apply("single")
     n, n_out = int(args.n), args.n_out
     dev = torch.device("cuda", 0)
     log(f"downsamplers: generating y, n={n}")
@@ -292,6 +298,71 @@ def bench_downsamplers(args, reps: int = 10):
     del y, y_np, ws_mm, ws_m4
     torch.cuda.empty_cache()
     return {"workload": f"one series, n={n}, float32 random walk (seed={args.seed}), n_out={n_out}", **res}
+
+
+def bench_xbins(args, reps: int = 10):
+    """MinMaxLTTB with MinMax bins of equal x width on n=1e9 points with
+    bursty int64 timestamps (exponential gaps, mean 1000, plus outages of
+    1e6-1e9 at 0.1% of the points): call time, the stream kernel's HBM
+    roofline fraction (it reads y only: 4 B per point), the edge search, and
+    parity with the oracle."""
+    import numpy as np
+    import torch
+
+    import oracle
+    from paper_2305_00332_amd import ops, synth
+
+    from paper_2305_00332_amd import autotune
+
+    autotune.apply("single")
+    n, n_out, r_ps = int(args.n), args.n_out, args.r_ps
+    nb = n_out * r_ps // 2
+    dev = torch.device("cuda", 0)
+    log(f"xbins: generating y and bursty x, n={n}")
+    x = synth.bursty_x(n, args.seed, device=dev)
+    y = synth.random_walk(n, args.seed, device=dev)
+    torch.cuda.synchronize()
+    out = torch.empty(n_out, dtype=torch.int64, device=dev)
+    cnt = torch.empty(1, dtype=torch.int64, device=dev)
+    ws = torch.empty(ops.xbins_workspace_size(n, n_out, r_ps), dtype=torch.uint8, device=dev)
+
+    def call():
+        ops.minmaxlttb_xbins(y, x, n_out, r_ps, out=out, count=cnt, ws=ws, sync=False)
+
+    call()
+    torch.cuda.synchronize()
+    ops.profile_enable(True)
+    ops.profile_reset()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        call()
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) * 1e3 / reps
+    ops.profile_enable(False)
+    kern = {}
+    for k in ("xbin_bounds", "init_keys", "xbin_reduce", "xbin_compact", "lttb_chain_seg", "lttb_chain",
+              "xbin_finish"):
+        tot, c = ops.profile_read(k)
+        kern[k] = round(tot / c, 5) if c else None
+    alg = 4 * n + 16 * nb
+    gbs = alg / (kern["xbin_reduce"] * 1e-3) / 1e9
+    res = {"workload": f"one series, n={n}, float32 random walk, bursty int64 x (seed={args.seed}); "
+                       f"MinMaxLTTB n_out={n_out}, r_ps={r_ps}, bins of equal x width",
+           "call_ms": round(wall, 5), "gpts_per_s": round(n / (wall * 1e-3) / 1e9, 3), "kernel_avg_ms": kern,
+           "stream_roofline": {"kernel": "xbin_reduce", "algorithmic_bytes": alg, "achieved_GBps": round(gbs, 1),
+                               "frac": round(gbs / HBM_PEAK_GBS, 4)},
+           "count": int(cnt.item())}
+    if not args.no_cpu_baseline:
+        y_np, x_np = y.cpu().numpy(), x.cpu().numpy()
+        c0 = time.perf_counter()
+        want = oracle.minmaxlttb_xbins(y_np, x_np, n_out, r_ps)
+        res["oracle_s"] = round(time.perf_counter() - c0, 3)
+        res["parity_vs_oracle"] = bool(np.array_equal(out[: int(cnt.item())].cpu().numpy(), want))
+        del y_np, x_np
+    log(f"  xbins: {res}")
+    del x, y, ws
+    torch.cuda.empty_cache()
+    return res
 
 
 def bench_comparator(args):

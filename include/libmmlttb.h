@@ -199,11 +199,13 @@ int mmlttb_graph_cache_stats(int64_t *entries, int64_t *hits, int64_t *captures)
  * item (rounded up to a multiple of 256*unroll); chain = LTTB pass form:
  * 1 sequential (one wave walks every bucket in order), 2 segmented (segments
  * walked from every start point in parallel, then linked; used when buckets
- * hold at most 64 points), 0 or unset = automatic (segmented when possible);
+ * hold at most 64 points), 3 automatic (the default: segmented when possible);
  * tile = points a workgroup stages in LDS for batched series with small bins
  * (2048, 4096 or 8192; bins of at most tile/4 points take that path).
- * A value of 0 keeps the current setting. Returns MMLTTB_EINVAL for other
- * values. Process-wide; not thread-safe with concurrent calls. */
+ * A value of 0 keeps the current setting; mmlttb_get_tuning reports every
+ * field as a settable value, so passing its results back restores a saved
+ * setting. Returns MMLTTB_EINVAL for other values. Process-wide; not
+ * thread-safe with concurrent calls. */
 int mmlttb_set_tuning(int unroll, int64_t chunk, int chain, int tile);
 int mmlttb_get_tuning(int *unroll, int64_t *chunk, int *chain, int *tile);
 

@@ -36,7 +36,8 @@ int ok()
 
 // ---------------------------------------------------------------- tuning
 
-enum ChainMode { kChainAuto = 0, kChainSequential = 1, kChainSegmented = 2 };
+// Chain forms; 0 is reserved for "keep the current setting" in mmlttb_set_tuning.
+enum ChainMode { kChainSequential = 1, kChainSegmented = 2, kChainAuto = 3 };
 
 struct Tuning {
     int unroll = 4;        // float4 loads per lane per batch in minmax_bin_reduce
@@ -66,7 +67,7 @@ Tuning &tuning()
         }
         if (const char *e = getenv("MMLTTB_CHAIN")) {
             int c = atoi(e);
-            if (c >= 0 && c <= 2)
+            if (c >= 1 && c <= 3)
                 r.chain = c;
         }
         int64_t q = 256 * (int64_t)r.unroll;
@@ -1047,8 +1048,8 @@ int mmlttb_set_tuning(int unroll, int64_t chunk, int chain, int tile)
         return fail(MMLTTB_EINVAL, "unroll must be 1, 2, 4 or 8");
     if (chunk != 0 && chunk < 256)
         return fail(MMLTTB_EINVAL, "chunk must be >= 256");
-    if (chain < 0 || chain > 2)
-        return fail(MMLTTB_EINVAL, "chain must be 0 (auto), 1 (sequential) or 2 (segmented)");
+    if (chain < 0 || chain > 3)
+        return fail(MMLTTB_EINVAL, "chain must be 0 (keep), 1 (sequential), 2 (segmented) or 3 (automatic)");
     if (unroll)
         t.unroll = unroll;
     if (chunk)

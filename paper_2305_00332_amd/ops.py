@@ -221,13 +221,14 @@ def graph_cache_stats():
     return tuple(t.value for t in v)
 
 
-CHAIN_AUTO, CHAIN_SEQUENTIAL, CHAIN_SEGMENTED = 0, 1, 2
+CHAIN_SEQUENTIAL, CHAIN_SEGMENTED, CHAIN_AUTO = 1, 2, 3
 
 
 def set_tuning(unroll: int = 0, chunk: int = 0, chain: int = 0, tile: int = 0):
     """Execution tuning (results never depend on it): MinMax loads in flight per
-    lane, points per MinMax work item, LTTB pass form (1 sequential, 2 segmented),
-    batched small-bin tile points. Zero keeps the current value."""
+    lane, points per MinMax work item, LTTB pass form (1 sequential, 2 segmented,
+    3 automatic), batched small-bin tile points. Zero keeps the current value, so
+    set_tuning(*get_tuning()) restores a saved setting exactly."""
     _lib.check(_lib.load().mmlttb_set_tuning(unroll, chunk, chain, tile))
 
 

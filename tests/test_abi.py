@@ -125,3 +125,51 @@ def test_oracle_shares_no_code_with_gpu_path():
         if f.endswith((".py", ".c", ".h")):
             text = open(f).read()
             assert "paper_2305_00332_amd" not in text and "libmmlttb" not in text, f
+
+
+def test_tuning_round_trips_including_automatic_chain(lib):
+    lib.mmlttb_set_tuning.argtypes = [ctypes.c_int, ctypes.c_int64, ctypes.c_int, ctypes.c_int]
+    lib.mmlttb_get_tuning.argtypes = [ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int64),
+                                      ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]
+
+    def get():
+        u, c, ch, t = ctypes.c_int(), ctypes.c_int64(), ctypes.c_int(), ctypes.c_int()
+        assert lib.mmlttb_get_tuning(ctypes.byref(u), ctypes.byref(c), ctypes.byref(ch), ctypes.byref(t)) == 0
+        return u.value, c.value, ch.value, t.value
+
+    saved = get()
+    assert saved[2] in (1, 2, 3) and saved[0] in (1, 2, 4, 8) and saved[3] in (2048, 4096, 8192)
+    try:
+        assert lib.mmlttb_set_tuning(8, 2048, 1, 8192) == 0
+        assert get() == (8, 2048, 1, 8192)
+        assert lib.mmlttb_set_tuning(0, 0, 3, 0) == 0  # automatic again, the rest kept
+        assert get() == (8, 2048, 3, 8192)
+        assert lib.mmlttb_set_tuning(0, 0, 4, 0) == -1
+        assert lib.mmlttb_set_tuning(3, 0, 0, 0) == -1
+    finally:
+        assert lib.mmlttb_set_tuning(*saved) == 0
+    assert get() == saved
+
+
+def test_new_calls_reject_invalid_arguments_on_host(lib):
+    _setup(lib)
+    fake = ctypes.c_void_p(0x100000)
+    ws = ctypes.c_void_p(0x200000)
+    i64 = ctypes.c_int64
+    lib.mmlttb_m4.argtypes = [ctypes.c_void_p, i64, i64, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                              ctypes.c_size_t, ctypes.c_void_p]
+    lib.mmlttb_everynth.argtypes = [i64, i64, ctypes.c_void_p, ctypes.c_void_p]
+    xb = [ctypes.c_void_p, ctypes.c_void_p, i64, i64, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
+          ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]
+    lib.mmlttb_minmax_xbins.argtypes = xb
+    lib.mmlttb_minmaxlttb_xbins.argtypes = xb
+    assert lib.mmlttb_m4(fake, 100, 3, fake, fake, ws, 1 << 20, None) == -1      # n_out < 4
+    assert lib.mmlttb_m4(fake, 0, 10, fake, fake, ws, 1 << 20, None) == -1       # n < 1
+    assert lib.mmlttb_m4(fake, 10 ** 6, 1000, fake, fake, ws, 16, None) == -2    # workspace
+    assert lib.mmlttb_everynth(0, 10, fake, None) == -1
+    assert lib.mmlttb_everynth(10, 0, fake, None) == -1
+    assert lib.mmlttb_minmax_xbins(None, fake, 100, 10, 4, fake, fake, ws, 1 << 20, None) == -1   # x NULL
+    assert lib.mmlttb_minmax_xbins(fake, fake, 2 ** 32 + 2, 10, 4, fake, fake, ws, 1 << 20, None) == -1
+    assert lib.mmlttb_minmax_xbins(fake, fake, 100, 10, 0, fake, fake, ws, 1 << 20, None) == -1
+    assert lib.mmlttb_minmaxlttb_xbins(fake, fake, 100, 10, 1, fake, fake, ws, 1 << 20, None) == -1
+    assert lib.mmlttb_minmaxlttb_xbins(fake, fake, 10 ** 6, 1000, 4, fake, fake, ws, 16, None) == -2
