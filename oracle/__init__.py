@@ -18,6 +18,10 @@ from .oracle import (  # noqa: F401
     m4,
     everynth,
     minmax,
+    minmax_typed,
+    minmaxlttb_typed,
+    exact_sum_f64,
+    lttb_means_typed,
     minmax_xbins,
     minmaxlttb_xbins,
     minmaxlttb,

@@ -69,6 +69,15 @@
  *       R3-R4; bins may be empty (gaps in x), so P may hold n_out points or
  *       fewer; LTTB then keeps every point of P (R9 applied to P). The output
  *       count is min(m, n_out) when n > n_out, else n.
+ *
+ * Other value types (same definitions, other storage):
+ *   R15 y may be float32, binary64 or int32; x may be implicit, int64 or
+ *       binary64. Values compare as numbers (-0.0 == +0.0). Y = y converted
+ *       to binary64 (exact for all three). X = x for binary64 x, x rounded to
+ *       binary64 for int64 x. Next-bucket means: the exact sum of the raw
+ *       values (x as stored; y as its exact binary64 value) rounded once to
+ *       binary64, then one division by the count (R6); a sum beyond the
+ *       binary64 range rounds to an infinity. binary64 x and y must be finite.
  */
 #include <math.h>
 #include <stdint.h>
@@ -82,19 +91,32 @@
 
 #define XK_IMPLICIT 0
 #define XK_INT64 1
+#define XK_F64 2
+
+#define YK_F32 0
+#define YK_F64 1
+#define YK_I32 2
 
 /* ------------------------------------------------------------------------ */
 /* Exact sums, rounded once to binary64 (reading R6).                        */
 /* A big unsigned integer, 32-bit words, least significant word first.       */
 /* ------------------------------------------------------------------------ */
 
-#define BIG_WORDS 16 /* 512 bits: float32 sums need < 2^(277+64) */
+/* float32 sums need < 2^(277+64): 16 words; binary64 sums need
+ * < 2^(2098+64): 72 words. */
+#define BIG_WORDS_F32 16
+#define BIG_WORDS 72
 
 typedef struct {
     uint32_t w[BIG_WORDS];
+    int nw; /* words in use */
 } big_t;
 
-static void big_zero(big_t *a) { memset(a, 0, sizeof(*a)); }
+static void big_zero(big_t *a, int nw)
+{
+    memset(a, 0, sizeof(*a));
+    a->nw = nw;
+}
 
 /* a += v << shift, for v < 2^32 */
 static void big_add_u32_shifted(big_t *a, uint32_t v, int shift)
@@ -103,7 +125,7 @@ static void big_add_u32_shifted(big_t *a, uint32_t v, int shift)
     int bit = shift % 32;
     uint64_t wide = (uint64_t)v << bit; /* < 2^63 */
     uint64_t carry = 0;
-    for (int i = word; i < BIG_WORDS; i++) {
+    for (int i = word; i < a->nw; i++) {
         uint64_t add = 0;
         if (i == word)
             add = wide & 0xffffffffu;
@@ -117,7 +139,7 @@ static void big_add_u32_shifted(big_t *a, uint32_t v, int shift)
 
 static int big_cmp(const big_t *a, const big_t *b)
 {
-    for (int i = BIG_WORDS - 1; i >= 0; i--) {
+    for (int i = a->nw - 1; i >= 0; i--) {
         if (a->w[i] != b->w[i])
             return a->w[i] < b->w[i] ? -1 : 1;
     }
@@ -128,7 +150,8 @@ static int big_cmp(const big_t *a, const big_t *b)
 static void big_sub(big_t *r, const big_t *a, const big_t *b)
 {
     int64_t borrow = 0;
-    for (int i = 0; i < BIG_WORDS; i++) {
+    r->nw = a->nw;
+    for (int i = 0; i < a->nw; i++) {
         int64_t d = (int64_t)a->w[i] - (int64_t)b->w[i] - borrow;
         borrow = 0;
         if (d < 0) {
@@ -142,11 +165,13 @@ static void big_sub(big_t *r, const big_t *a, const big_t *b)
 static int big_bit(const big_t *a, int i) { return (int)((a->w[i / 32] >> (i % 32)) & 1u); }
 
 /* The binary64 nearest to (negative ? -1 : 1) * a * 2^scale_exp, ties to
- * even. The callers keep the result inside the normal binary64 range. */
+ * even. An a below 2^53 is converted exactly (with scale_exp = -1074 this
+ * covers every subnormal result); larger ones keep 53 bits with round and
+ * sticky bits, so the result is normal or overflows to an infinity. */
 static double big_round_to_double(const big_t *a, int scale_exp, int negative)
 {
     int top = -1;
-    for (int i = BIG_WORDS * 32 - 1; i >= 0; i--) {
+    for (int i = a->nw * 32 - 1; i >= 0; i--) {
         if (big_bit(a, i)) {
             top = i;
             break;
@@ -181,8 +206,8 @@ static double big_round_to_double(const big_t *a, int scale_exp, int negative)
 static double exact_sum_f32(const float *v, int64_t c)
 {
     big_t pos, neg;
-    big_zero(&pos);
-    big_zero(&neg);
+    big_zero(&pos, BIG_WORDS_F32);
+    big_zero(&neg, BIG_WORDS_F32);
     for (int64_t i = 0; i < c; i++) {
         uint32_t bits;
         memcpy(&bits, &v[i], 4);
@@ -222,10 +247,48 @@ static double exact_sum_i64(const int64_t *x, int64_t c)
     int negative = s < 0;
     unsigned __int128 mag = negative ? (unsigned __int128)(-s) : (unsigned __int128)s;
     big_t a;
-    big_zero(&a);
+    big_zero(&a, 4);
     for (int i = 0; i < 4; i++)
         a.w[i] = (uint32_t)(mag >> (32 * i));
     return big_round_to_double(&a, 0, negative);
+}
+
+/* RN(sum of v[0..c-1]) for finite binary64 values, the sum taken exactly.
+ * Every finite binary64 is an integer multiple of 2^-1074 below 2^1024; the
+ * significand (< 2^53) is added as two 32-bit pieces. A sum beyond the
+ * binary64 range rounds to an infinity, as IEEE rounding to nearest does. */
+static double exact_sum_f64(const double *v, int64_t c)
+{
+    big_t pos, neg;
+    big_zero(&pos, BIG_WORDS);
+    big_zero(&neg, BIG_WORDS);
+    for (int64_t i = 0; i < c; i++) {
+        uint64_t bits;
+        memcpy(&bits, &v[i], 8);
+        uint32_t expo = (uint32_t)((bits >> 52) & 0x7ffu);
+        uint64_t frac = bits & 0xfffffffffffffull;
+        uint64_t mant;
+        int shift;
+        if (expo == 0) { /* zero or subnormal: frac * 2^-1074 */
+            mant = frac;
+            shift = 0;
+        } else { /* normal: (2^52 + frac) * 2^(expo - 1075) */
+            mant = frac | (1ull << 52);
+            shift = (int)expo - 1;
+        }
+        big_t *dst = (bits >> 63) ? &neg : &pos;
+        big_add_u32_shifted(dst, (uint32_t)(mant & 0xffffffffu), shift);
+        big_add_u32_shifted(dst, (uint32_t)(mant >> 32), shift + 32);
+    }
+    big_t mag;
+    int negative = 0;
+    if (big_cmp(&pos, &neg) >= 0) {
+        big_sub(&mag, &pos, &neg);
+    } else {
+        big_sub(&mag, &neg, &pos);
+        negative = 1;
+    }
+    return big_round_to_double(&mag, -1074, negative);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -568,6 +631,197 @@ int oracle_minmaxlttb_xbins(const int64_t *x, const float *y, int64_t n, int64_t
 }
 
 /* ------------------------------------------------------------------------ */
+/* Other value types (R15).                                                  */
+/* ------------------------------------------------------------------------ */
+
+static double y_value(int yk, const void *y, int64_t i)
+{
+    if (yk == YK_F32)
+        return (double)((const float *)y)[i];
+    if (yk == YK_F64)
+        return ((const double *)y)[i];
+    return (double)((const int32_t *)y)[i];
+}
+
+/* y_i < y_j as numbers; every y type fits binary64 exactly, so comparing the
+ * binary64 values compares the stored ones. */
+static int y_less(int yk, const void *y, int64_t i, int64_t j) { return y_value(yk, y, i) < y_value(yk, y, j); }
+
+static int check_typed(int xk, const void *x, int yk, const void *y, int64_t n)
+{
+    if (yk != YK_F32 && yk != YK_F64 && yk != YK_I32)
+        return ORC_EINVAL;
+    if (xk == XK_IMPLICIT ? x != NULL : (xk == XK_INT64 || xk == XK_F64) ? x == NULL : 1)
+        return ORC_EINVAL;
+    for (int64_t i = 0; i < n; i++)
+        if (!isfinite(y_value(yk, y, i)))
+            return ORC_ENOTFINITE;
+    if (xk == XK_F64)
+        for (int64_t i = 0; i < n; i++)
+            if (!isfinite(((const double *)x)[i]))
+                return ORC_ENOTFINITE;
+    return ORC_OK;
+}
+
+int oracle_minmax_typed(int yk, const void *y, int64_t n, int64_t n_out, int32_t r_ps, int64_t *P, int64_t *m)
+{
+    if (n < 1 || n_out < 3 || r_ps < 1)
+        return ORC_EINVAL;
+    int rc = check_typed(XK_IMPLICIT, NULL, yk, y, n);
+    if (rc != ORC_OK)
+        return rc;
+    int64_t cnt = 0;
+    if (n <= 2) {
+        for (int64_t i = 0; i < n; i++)
+            P[cnt++] = i;
+        *m = cnt;
+        return ORC_OK;
+    }
+    int64_t nb = (int64_t)(((__int128)n_out * r_ps) / 2); /* R1, R15 */
+    int64_t L = n - 2;
+    P[cnt++] = 0;
+    for (int64_t b = 0; b < nb; b++) {
+        int64_t lo = 1 + floor_frac(b, L, nb);
+        int64_t hi = 1 + floor_frac(b + 1, L, nb);
+        if (lo == hi)
+            continue;
+        int64_t imin = lo, imax = lo;
+        for (int64_t i = lo + 1; i < hi; i++) {
+            if (y_less(yk, y, i, imin)) /* lowest index on ties (R15, R3) */
+                imin = i;
+            if (y_less(yk, y, imax, i)) /* lowest index on ties (R15, R3) */
+                imax = i;
+        }
+        P[cnt++] = imin;
+        if (imax != imin)
+            P[cnt++] = imax;
+    }
+    P[cnt++] = n - 1;
+    qsort(P, (size_t)cnt, sizeof(int64_t), cmp_i64);
+    int64_t d = 0;
+    for (int64_t i = 0; i < cnt; i++)
+        if (d == 0 || P[i] != P[d - 1])
+            P[d++] = P[i];
+    *m = d;
+    return ORC_OK;
+}
+
+/* Next-bucket means over m > n_out points (R6 with R15): exact sums of xi
+ * (int64 x) or xf (binary64 x), and of Y. */
+static void lttb_means_typed(const int64_t *xi, const double *xf, const double *Y, int64_t m, int64_t n_out,
+                             double *MX, double *MY)
+{
+    int64_t B = n_out - 2;
+    for (int64_t k = 0; k < B; k++) {
+        int64_t g0, g1;
+        if (k < B - 1) {
+            g0 = 1 + floor_frac(k + 1, m - 2, B);
+            g1 = 1 + floor_frac(k + 2, m - 2, B);
+        } else {
+            g0 = m - 1;
+            g1 = m;
+        }
+        double c = (double)(g1 - g0);
+        MX[k] = (xi ? exact_sum_i64(xi + g0, g1 - g0) : exact_sum_f64(xf + g0, g1 - g0)) / c;
+        MY[k] = exact_sum_f64(Y + g0, g1 - g0) / c;
+    }
+}
+
+/* LTTB positions over m points (R5-R8 with R15): X, Y are the binary64
+ * coordinates; the means sum xi (int64 x) or xf (binary64 x) and Y exactly. */
+static int lttb_positions_typed(const double *X, const int64_t *xi, const double *xf, const double *Y, int64_t m,
+                                int64_t n_out, int64_t *out)
+{
+    if (m <= n_out) {
+        for (int64_t i = 0; i < m; i++)
+            out[i] = i;
+        return ORC_OK;
+    }
+    int64_t B = n_out - 2;
+    double *MX = (double *)malloc(sizeof(double) * (size_t)B);
+    double *MY = (double *)malloc(sizeof(double) * (size_t)B);
+    if (!MX || !MY) {
+        free(MX);
+        free(MY);
+        return ORC_ENOMEM;
+    }
+    lttb_means_typed(xi, xf, Y, m, n_out, MX, MY);
+    int64_t a = 0;
+    out[0] = 0;
+    for (int64_t k = 0; k < B; k++) {
+        int64_t s0 = 1 + floor_frac(k, m - 2, B);
+        int64_t s1 = 1 + floor_frac(k + 1, m - 2, B);
+        double best = -1.0;
+        int64_t sel = -1;
+        for (int64_t j = s0; j < s1; j++) {
+            double area = fabs((X[a] - MX[k]) * (Y[j] - Y[a]) - (X[a] - X[j]) * (MY[k] - Y[a])); /* R7 */
+            if (area > best) { /* lowest index on ties (R8) */
+                best = area;
+                sel = j;
+            }
+        }
+        out[k + 1] = sel;
+        a = sel;
+    }
+    out[n_out - 1] = m - 1;
+    free(MX);
+    free(MY);
+    return ORC_OK;
+}
+
+int oracle_minmaxlttb_typed(int xk, const void *x, int yk, const void *y, int64_t n, int64_t n_out, int32_t r_ps,
+                            int64_t *out)
+{
+    if (n < 1 || n_out < 3 || r_ps < 2)
+        return ORC_EINVAL;
+    int rc = check_typed(xk, x, yk, y, n);
+    if (rc != ORC_OK)
+        return rc;
+    if (n <= n_out) {
+        for (int64_t i = 0; i < n; i++)
+            out[i] = i;
+        return ORC_OK;
+    }
+    int64_t nb = (int64_t)(((__int128)n_out * r_ps) / 2);
+    int64_t *P = (int64_t *)malloc(sizeof(int64_t) * (size_t)(2 * nb + 2));
+    if (!P)
+        return ORC_ENOMEM;
+    int64_t m = 0;
+    rc = oracle_minmax_typed(yk, y, n, n_out, r_ps, P, &m);
+    double *X = (double *)malloc(sizeof(double) * (size_t)m);
+    double *Y = (double *)malloc(sizeof(double) * (size_t)m);
+    int64_t *xi = (int64_t *)malloc(sizeof(int64_t) * (size_t)m);
+    double *xf = (double *)malloc(sizeof(double) * (size_t)m);
+    int64_t *pos = (int64_t *)malloc(sizeof(int64_t) * (size_t)n_out);
+    if (rc == ORC_OK && (!X || !Y || !xi || !xf || !pos))
+        rc = ORC_ENOMEM;
+    if (rc == ORC_OK) {
+        for (int64_t i = 0; i < m; i++) {
+            int64_t p = P[i];
+            if (xk == XK_F64) {
+                xf[i] = ((const double *)x)[p];
+                X[i] = xf[i];
+            } else {
+                xi[i] = (xk == XK_INT64) ? ((const int64_t *)x)[p] : p;
+                X[i] = (double)xi[i];
+            }
+            Y[i] = y_value(yk, y, p);
+        }
+        rc = lttb_positions_typed(X, xk == XK_F64 ? NULL : xi, xf, Y, m, n_out, pos);
+        if (rc == ORC_OK)
+            for (int64_t i = 0; i < n_out; i++)
+                out[i] = P[pos[i]];
+    }
+    free(P);
+    free(X);
+    free(Y);
+    free(xi);
+    free(xf);
+    free(pos);
+    return rc;
+}
+
+/* ------------------------------------------------------------------------ */
 /* M4 and EveryNth (section 2.2.1, Table 1; R12, R13).                       */
 /* ------------------------------------------------------------------------ */
 
@@ -648,6 +902,40 @@ int oracle_lttb_means(int xk, const int64_t *x, const float *y, int64_t m, int64
 int oracle_exact_sum_f32(const float *v, int64_t c, double *out)
 {
     *out = exact_sum_f32(v, c);
+    return ORC_OK;
+}
+
+/* The next-bucket means LTTB takes over m > n_out points of any value type. */
+int oracle_lttb_means_typed(int xk, const void *x, int yk, const void *y, int64_t m, int64_t n_out, double *MX,
+                            double *MY)
+{
+    if (m <= n_out || n_out < 3)
+        return ORC_EINVAL;
+    int rc = check_typed(xk, x, yk, y, m);
+    if (rc != ORC_OK)
+        return rc;
+    int64_t *xi = (int64_t *)malloc(sizeof(int64_t) * (size_t)m);
+    double *xf = (double *)malloc(sizeof(double) * (size_t)m);
+    double *Y = (double *)malloc(sizeof(double) * (size_t)m);
+    if (xi && xf && Y) {
+        for (int64_t i = 0; i < m; i++) {
+            xi[i] = (xk == XK_INT64) ? ((const int64_t *)x)[i] : i;
+            xf[i] = (xk == XK_F64) ? ((const double *)x)[i] : 0.0;
+            Y[i] = y_value(yk, y, i);
+        }
+        lttb_means_typed(xk == XK_F64 ? NULL : xi, xf, Y, m, n_out, MX, MY);
+    } else {
+        rc = ORC_ENOMEM;
+    }
+    free(xi);
+    free(xf);
+    free(Y);
+    return rc;
+}
+
+int oracle_exact_sum_f64(const double *v, int64_t c, double *out)
+{
+    *out = exact_sum_f64(v, c);
     return ORC_OK;
 }
 

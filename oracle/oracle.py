@@ -58,13 +58,21 @@ def _bind(path: str):
     lib.oracle_exact_sum_f32.argtypes = [_f32p, ctypes.c_int64, _f64p]
     lib.oracle_exact_sum_i64.argtypes = [_i64p, ctypes.c_int64, _f64p]
     lib.oracle_m4.argtypes = [_f32p, ctypes.c_int64, ctypes.c_int64, _i64p, _i64p]
+    _vp = ctypes.c_void_p
+    lib.oracle_minmax_typed.argtypes = [ctypes.c_int, _vp, ctypes.c_int64, ctypes.c_int64, ctypes.c_int32, _i64p, _i64p]
+    lib.oracle_minmaxlttb_typed.argtypes = [ctypes.c_int, _vp, ctypes.c_int, _vp, ctypes.c_int64, ctypes.c_int64,
+                                            ctypes.c_int32, _i64p]
+    lib.oracle_exact_sum_f64.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.c_int64, _f64p]
+    lib.oracle_lttb_means_typed.argtypes = [ctypes.c_int, _vp, ctypes.c_int, _vp, ctypes.c_int64, ctypes.c_int64,
+                                            _f64p, _f64p]
     lib.oracle_minmax_xbins.argtypes = [_i64p, _f32p, ctypes.c_int64, ctypes.c_int64, ctypes.c_int32, _i64p, _i64p]
     lib.oracle_minmaxlttb_xbins.argtypes = [_i64p, _f32p, ctypes.c_int64, ctypes.c_int64, ctypes.c_int32, _i64p,
                                             _i64p]
     lib.oracle_everynth.argtypes = [ctypes.c_int64, ctypes.c_int64, _i64p]
     for f in ("oracle_minmax", "oracle_lttb", "oracle_minmaxlttb", "oracle_lttb_means",
               "oracle_exact_sum_f32", "oracle_exact_sum_i64", "oracle_m4", "oracle_everynth",
-              "oracle_minmax_xbins", "oracle_minmaxlttb_xbins"):
+              "oracle_minmax_xbins", "oracle_minmaxlttb_xbins", "oracle_minmax_typed", "oracle_minmaxlttb_typed",
+              "oracle_exact_sum_f64", "oracle_lttb_means_typed"):
         getattr(lib, f).restype = ctypes.c_int
     return lib
 
@@ -101,6 +109,10 @@ def compile_variant(src_text: str, out_path: str):
     v.minmaxlttb = lambda y, n_out, r_ps, x=None: minmaxlttb(y, n_out, r_ps, x, _lib_override=lib)
     v.lttb_means = lambda y, n_out, x=None: lttb_means(y, n_out, x, _lib_override=lib)
     v.m4 = lambda y, n_out: m4(y, n_out, _lib_override=lib)
+    v.minmax_typed = lambda y, n_out, r_ps: minmax_typed(y, n_out, r_ps, _lib_override=lib)
+    v.minmaxlttb_typed = lambda y, n_out, r_ps, x=None: minmaxlttb_typed(y, n_out, r_ps, x, _lib_override=lib)
+    v.exact_sum_f64 = lambda a: exact_sum_f64(a, _lib_override=lib)
+    v.lttb_means_typed = lambda y, n_out, x=None: lttb_means_typed(y, n_out, x, _lib_override=lib)
     v.minmax_xbins = lambda y, x, n_out, r_ps: minmax_xbins(y, x, n_out, r_ps, _lib_override=lib)
     v.minmaxlttb_xbins = lambda y, x, n_out, r_ps: minmaxlttb_xbins(y, x, n_out, r_ps, _lib_override=lib)
     v.everynth = lambda n, n_out: everynth(n, n_out, _lib_override=lib)
@@ -147,6 +159,79 @@ def minmax(y, n_out: int, r_ps: int, _lib_override=None) -> np.ndarray:
     if rc != 0:
         raise OracleError(rc, "minmax")
     return P[: m.value].copy()
+
+
+_YKINDS = {np.dtype(np.float32): 0, np.dtype(np.float64): 1, np.dtype(np.int32): 2}
+_XKINDS = {np.dtype(np.int64): 1, np.dtype(np.float64): 2}
+
+
+def _typed_y(y):
+    y = np.ascontiguousarray(y)
+    if y.dtype not in _YKINDS:
+        raise TypeError("y must be float32, float64 or int32")
+    return y, _YKINDS[y.dtype]
+
+
+def minmax_typed(y, n_out: int, r_ps: int, _lib_override=None) -> np.ndarray:
+    """MinMax preselection for float32, float64 or int32 y (reading R15)."""
+    y, yk = _typed_y(y)
+    n = y.shape[0]
+    nb = n_out * r_ps // 2
+    P = np.empty(max(2 * nb + 2, n if n <= 2 else 0, 1), dtype=np.int64)
+    m = ctypes.c_int64(0)
+    rc = (_lib_override or _load()).oracle_minmax_typed(yk, y.ctypes.data, n, n_out, r_ps, P.ctypes.data_as(_i64p),
+                                                        ctypes.byref(m))
+    if rc != 0:
+        raise OracleError(rc, "minmax_typed")
+    return P[: m.value].copy()
+
+
+def minmaxlttb_typed(y, n_out: int, r_ps: int, x=None, _lib_override=None) -> np.ndarray:
+    """MinMaxLTTB for float32, float64 or int32 y and implicit, int64 or
+    float64 x (reading R15)."""
+    y, yk = _typed_y(y)
+    n = y.shape[0]
+    xk, xp = 0, None
+    if x is not None:
+        x = np.ascontiguousarray(x)
+        if x.dtype not in _XKINDS or x.shape[0] != n:
+            raise TypeError("x must be int64 or float64, as long as y")
+        xk, xp = _XKINDS[x.dtype], x.ctypes.data
+    out = np.empty(max(min(n, n_out), 1), dtype=np.int64)
+    rc = (_lib_override or _load()).oracle_minmaxlttb_typed(xk, xp, yk, y.ctypes.data, n, n_out, r_ps,
+                                                            out.ctypes.data_as(_i64p))
+    if rc != 0:
+        raise OracleError(rc, "minmaxlttb_typed")
+    return out[: min(n, n_out)].copy()
+
+
+def lttb_means_typed(y, n_out: int, x=None, _lib_override=None):
+    """(MX, MY): LTTB's next-bucket means over all m = len(y) points, any value type (R6, R15)."""
+    y, yk = _typed_y(y)
+    m = y.shape[0]
+    xk, xp = 0, None
+    if x is not None:
+        x = np.ascontiguousarray(x)
+        if x.dtype not in _XKINDS or x.shape[0] != m:
+            raise TypeError("x must be int64 or float64, as long as y")
+        xk, xp = _XKINDS[x.dtype], x.ctypes.data
+    B = max(n_out - 2, 1)
+    MX = np.empty(B, dtype=np.float64)
+    MY = np.empty(B, dtype=np.float64)
+    rc = (_lib_override or _load()).oracle_lttb_means_typed(xk, xp, yk, y.ctypes.data, m, n_out,
+                                                            MX.ctypes.data_as(_f64p), MY.ctypes.data_as(_f64p))
+    if rc != 0:
+        raise OracleError(rc, "lttb_means_typed")
+    return MX, MY
+
+
+def exact_sum_f64(a, _lib_override=None) -> float:
+    """RN(exact sum) of binary64 values (reading R15)."""
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    r = ctypes.c_double(0.0)
+    (_lib_override or _load()).oracle_exact_sum_f64(a.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), a.shape[0],
+                                                    ctypes.byref(r))
+    return r.value
 
 
 def minmax_xbins(y, x, n_out: int, r_ps: int, _lib_override=None) -> np.ndarray:

@@ -17,6 +17,9 @@ a resident pool queried by sub-range):
   batch_lengths      log-uniform integer lengths
   edge cases         ties, signed zeros, subnormals, extreme magnitudes,
                      epoch-nanosecond timestamps
+  other types        float64 random walk, int32 counts (int_series), float64
+                     timestamps in seconds (float_x), bursty int64 timestamps
+                     with outages (bursty_x)
 """
 from __future__ import annotations
 
@@ -34,10 +37,12 @@ def _gen(seed: int, device) -> torch.Generator:
     return g
 
 
-def random_walk(n: int, seed: int, sigma: float = 1.0, device="cpu", start: float = 0.0) -> torch.Tensor:
-    """float32 random walk with Gaussian increments (accumulated in float64)."""
+def random_walk(n: int, seed: int, sigma: float = 1.0, device="cpu", start: float = 0.0,
+                dtype=torch.float32) -> torch.Tensor:
+    """Random walk with Gaussian increments (accumulated in float64), stored
+    as dtype (float32 or float64)."""
     g = _gen(seed, device)
-    out = torch.empty(n, dtype=torch.float32, device=device)
+    out = torch.empty(n, dtype=dtype, device=device)
     carry = torch.tensor(start, dtype=torch.float64, device=device)
     for lo in range(0, n, _CHUNK):
         hi = min(n, lo + _CHUNK)
@@ -46,8 +51,34 @@ def random_walk(n: int, seed: int, sigma: float = 1.0, device="cpu", start: floa
             inc.mul_(sigma)
         walk = torch.cumsum(inc, 0).add_(carry)
         carry = walk[-1].clone()
-        out[lo:hi] = walk.to(torch.float32)
+        out[lo:hi] = walk.to(dtype)
         del inc, walk
+    return out
+
+
+def int_series(n: int, seed: int, device="cpu", scale: float = 1e6) -> torch.Tensor:
+    """int32 sensor counts: a float64 random walk of step sigma scale/1e3,
+    rounded and clipped to the int32 range (long flat runs of equal values
+    when scale is small)."""
+    w = random_walk(n, seed, sigma=scale / 1e3, device=device, dtype=torch.float64)
+    return torch.clamp(torch.round(w), -2 ** 31, 2 ** 31 - 1).to(torch.int32)
+
+
+def float_x(n: int, seed: int, device="cpu", start: float = 1.7e9) -> torch.Tensor:
+    """Strictly increasing float64 timestamps in seconds: start + cumulative
+    gaps 1e-6 * (1 + Exp(999.5)), not integers."""
+    g = _gen(seed + 11_000_003, device)
+    out = torch.empty(n, dtype=torch.float64, device=device)
+    carry = float(start)
+    for lo in range(0, n, _CHUNK):
+        hi = min(n, lo + _CHUNK)
+        u = torch.rand(hi - lo, generator=g, dtype=torch.float64, device=device)
+        gaps = (1.0 - torch.log1p(-u) * 999.5) * 1e-6
+        if lo == 0:
+            gaps[0] = 0.0
+        xs = torch.cumsum(gaps, 0) + carry
+        carry = float(xs[-1].item())
+        out[lo:hi] = xs
     return out
 
 

@@ -102,8 +102,8 @@ def check_lttb_near_optimal(xs_int, ys, out, n_out: int, rel=2.0 ** -44):
     if m <= n_out:
         assert list(out) == list(range(m))
         return
-    X = [Fraction(int(v)) for v in xs_int]
-    Y = [Fraction(float(v)) for v in ys]
+    X = [Fraction(int(v)) if isinstance(v, (int, np.integer)) else Fraction(float(v)) for v in xs_int]
+    Y = [Fraction(int(v)) if isinstance(v, (int, np.integer)) else Fraction(float(v)) for v in ys]
     B = n_out - 2
     buckets = lttb_buckets(m, n_out)
     assert out[0] == 0 and out[-1] == m - 1
@@ -184,3 +184,17 @@ def minmax_xbins_by_numpy(y: np.ndarray, x: np.ndarray, n_out: int, r_ps: int) -
             sel.add(lo + int(np.argmin(seg)))
             sel.add(lo + int(np.argmax(seg)))
     return np.array(sorted(sel), dtype=np.int64)
+
+
+def means_by_fsum(v: np.ndarray, n_out: int) -> np.ndarray:
+    """LTTB next-bucket means over all points from math.fsum (a correctly
+    rounded sum) divided by the count; last interior bucket: the last point."""
+    import math
+
+    m = len(v)
+    bk = lttb_buckets(m, n_out)
+    out = []
+    for k in range(n_out - 2):
+        g0, g1 = bk[k + 1] if k < n_out - 3 else (m - 1, m)
+        out.append(math.fsum(float(t) for t in v[g0:g1]) / (g1 - g0))
+    return np.array(out, dtype=np.float64)

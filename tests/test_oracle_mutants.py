@@ -42,18 +42,27 @@ MUTANTS = {
                         "fabs((Xa - MX[k]) * (Yj - Ya) + (Xa - Xj) * (MY[k] - Ya))"),
     "area_transposed": ("fabs((Xa - MX[k]) * (Yj - Ya) - (Xa - Xj) * (MY[k] - Ya))",
                         "fabs((Xa - MY[k]) * (Yj - Ya) - (Xa - Xj) * (MX[k] - Ya))"),
-    "area_tie_highest": ("if (area > best) {", "if (area >= best) {"),
+    "area_tie_highest": ("if (area > best) { /* strict", "if (area >= best) { /* strict"),
+    "typed_area_tie_highest": ("if (area > best) { /* lowest index on ties (R8) */",
+                               "if (area >= best) { /* lowest index on ties (R8) */"),
     "mean_of_current_bucket": ("g0 = 1 + floor_frac(k + 1, m - 2, B);\n            g1 = 1 + floor_frac(k + 2, m - 2, B);",
-                               "g0 = 1 + floor_frac(k, m - 2, B);\n            g1 = 1 + floor_frac(k + 1, m - 2, B);"),
-    "last_mean_two_points": ("g0 = m - 1;\n            g1 = m;", "g0 = m - 2;\n            g1 = m;"),
-    "mean_count_off_by_one": ("double c = (double)(g1 - g0);", "double c = (double)(g1 - g0 + 1);"),
-    "chain_not_updated": ("out[k + 1] = sel;\n        a = sel;", "out[k + 1] = sel;\n        a = 0;"),
+                               "g0 = 1 + floor_frac(k, m - 2, B);\n            g1 = 1 + floor_frac(k + 1, m - 2, B);", 0, 2),
+    "typed_mean_of_current_bucket": ("g0 = 1 + floor_frac(k + 1, m - 2, B);\n            g1 = 1 + floor_frac(k + 2, m - 2, B);",
+                               "g0 = 1 + floor_frac(k, m - 2, B);\n            g1 = 1 + floor_frac(k + 1, m - 2, B);", 1, 2),
+    "last_mean_two_points": ("g0 = m - 1;\n            g1 = m;", "g0 = m - 2;\n            g1 = m;", 0, 2),
+    "typed_last_mean_two_points": ("g0 = m - 1;\n            g1 = m;", "g0 = m - 2;\n            g1 = m;", 1, 2),
+    "mean_count_off_by_one": ("double c = (double)(g1 - g0);", "double c = (double)(g1 - g0 + 1);", 0, 2),
+    "typed_mean_count_off_by_one": ("double c = (double)(g1 - g0);", "double c = (double)(g1 - g0 + 1);", 1, 2),
+    "chain_not_updated": ("out[k + 1] = sel;\n        a = sel;", "out[k + 1] = sel;\n        a = 0;", 0, 2),
+    "typed_chain_not_updated": ("out[k + 1] = sel;\n        a = sel;", "out[k + 1] = sel;\n        a = 0;", 1, 2),
     "round_half_up": ("if (round_bit && (sticky || (mant & 1u)))", "if (round_bit)"),
     "sum_in_double": ("MY[k] = exact_sum_f32(ys + g0, g1 - g0) / c;",
                       "{ double s_ = 0; for (int64_t q = g0; q < g1; q++) s_ += (double)ys[q]; MY[k] = s_ / c; }"),
-    "subnormal_shift": ("mant = frac;\n            shift = 0;", "mant = frac;\n            shift = 1;"),
+    "subnormal_shift": ("mant = frac;\n            shift = 0;", "mant = frac;\n            shift = 1;", 0, 2),
+    "f64_subnormal_shift": ("mant = frac;\n            shift = 0;", "mant = frac;\n            shift = 1;", 1, 2),
     "gather_wrong_x": ("xs[i] = (xk == XK_INT64) ? x[P[i]] : P[i];", "xs[i] = (xk == XK_INT64) ? x[i] : P[i];"),
-    "no_first_point": ("    P[cnt++] = 0;\n    for (int64_t b = 0;", "    for (int64_t b = 0;"),
+    "no_first_point": ("    P[cnt++] = 0;\n    for (int64_t b = 0;", "    for (int64_t b = 0;", 0, 2),
+    "typed_no_first_point": ("    P[cnt++] = 0;\n    for (int64_t b = 0;", "    for (int64_t b = 0;", 1, 2),
     "m4_no_last": ("        out[cnt++] = hi - 1;\n", ""),
     "m4_bins_not_quartered": ("    int64_t nb = n_out / 4;", "    int64_t nb = n_out / 2;"),
     "xbin_edges_from_first_point": ("int64_t right = x_edge(x[1], x[n - 1], b + 1, nb);",
@@ -61,6 +70,12 @@ MUTANTS = {
     "xbin_right_edge_inclusive": ("while (hi < n - 1 && x[hi] < right)", "while (hi < n - 1 && x[hi] <= right)"),
     "xbin_min_tie_highest": ("if (y[i] < y[imin]) /* lowest index on ties (R14, R3) */",
                              "if (y[i] <= y[imin]) /* lowest index on ties (R14, R3) */"),
+    "typed_min_tie_highest": ("if (y_less(yk, y, i, imin)) /* lowest index on ties (R15, R3) */",
+                              "if (!y_less(yk, y, imin, i)) /* lowest index on ties (R15, R3) */"),
+    "typed_sum_f64_in_double": ("MY[k] = exact_sum_f64(Y + g0, g1 - g0) / c;",
+                                "MY[k] = 0.0;\n        for (int64_t q = g0; q < g1; q++)\n            MY[k] += Y[q];\n        MY[k] /= c;"),
+    "f64_sum_high_part_dropped": ("        big_add_u32_shifted(dst, (uint32_t)(mant >> 32), shift + 32);\n", ""),
+    "typed_i32_as_float": ("    return (double)((const int32_t *)y)[i];", "    return (double)(float)((const int32_t *)y)[i];"),
     "everynth_ceil": ("        out[k] = floor_frac(k, n, n_out);", "        out[k] = (k * n + n_out - 1) / n_out;"),
 }
 
@@ -116,6 +131,35 @@ def _passes_pins(v) -> bool:
             x = np.cumsum(1 + (np.arange(n) * 7919 + seed) % 13).astype(np.int64)
             if not np.array_equal(v.minmax_xbins(y, x, 10 + seed, 4), pins.minmax_xbins_by_numpy(y, x, 10 + seed, 4)):
                 return False
+        # other value types: exact binary64 sums, numpy MinMax, float32 reduction, cancellation means
+        import math as _m
+        for seed in range(6):
+            rng = np.random.default_rng(seed)
+            vals = rng.standard_normal(50 + seed) * 10.0 ** rng.integers(-30, 30, size=50 + seed)
+            if v.exact_sum_f64(vals) != _m.fsum(vals):
+                return False
+            subs = rng.standard_normal(40) * 5e-324 * 2.0 ** rng.integers(0, 70, size=40)
+            if v.exact_sum_f64(subs) != _m.fsum(subs):
+                return False
+            yi = (rng.integers(-2 ** 31, 2 ** 31 - 1, size=400 + 17 * seed)).astype(np.int32)
+            if not np.array_equal(v.minmax_typed(yi, 20, 2), pins.minmax_by_numpy(yi, 20, 2)):
+                return False
+            yt = synth.to_numpy(synth.ties_series(300 + 29 * seed, seed)).astype(np.float64)
+            if not np.array_equal(v.minmax_typed(yt, 20, 4), pins.minmax_by_numpy(yt, 20, 4)):
+                return False
+            y32 = synth.to_numpy(synth.random_walk(500 + 31 * seed, seed))
+            if not np.array_equal(v.minmaxlttb_typed(y32.astype(np.float64), 17, 4), v.minmaxlttb(y32, 17, 4)):
+                return False
+            # means that cancel: values 1e17 +- small, where a running binary64 sum loses the small parts
+            ph = np.arange(400) % 3  # +1e17, a small value (lost by a running sum), -1e17
+            yc = np.where(ph == 0, 1e17, np.where(ph == 2, -1e17, rng.standard_normal(400)))
+            xc = np.cumsum(rng.random(400) + 0.5) + 1e15
+            MX, MY = v.lttb_means_typed(yc, 13, xc)
+            if not (np.array_equal(MX, pins.means_by_fsum(xc, 13)) and np.array_equal(MY, pins.means_by_fsum(yc, 13))):
+                return False
+            yi = synth.to_numpy(synth.int_series(300, seed, scale=1e9))
+            if not np.array_equal(v.lttb_means_typed(yi, 11)[1], pins.means_by_fsum(yi.astype(np.float64), 11)):
+                return False
         # exact-regime LTTB vs rationals
         for seed in range(30):
             rng = np.random.default_rng(seed)
@@ -129,6 +173,13 @@ def _passes_pins(v) -> bool:
             xs = np.arange(m) if x is None else x
             want = pins.lttb_exact([int(t) for t in xs], [int(t) for t in y], B + 2)
             if list(v.lttb(y, B + 2, x)) != want:
+                return False
+            # the typed path with every point preselected (nb >= m - 2), binary64 and int32 y
+            r_big = 2 * m
+            xf = None if x is None else x.astype(np.float64)
+            if list(v.minmaxlttb_typed(y.astype(np.float64), B + 2, r_big, xf)) != want:
+                return False
+            if list(v.minmaxlttb_typed(y.astype(np.int32), B + 2, r_big, x)) != want:
                 return False
         # MinMaxLTTB invariants + near-optimality over P
         for seed in range(8):
@@ -174,10 +225,19 @@ def test_unmodified_oracle_passes(tmp_path):
     assert _run_isolated(oracle.source_text(), str(tmp_path / "unmodified.so"))
 
 
+def _plant(src: str, spec) -> str:
+    """(old, new) replaces the one occurrence of old; (old, new, k, count)
+    replaces occurrence k of old, which must occur exactly count times."""
+    old, new = spec[0], spec[1]
+    k, count = (spec[2], spec[3]) if len(spec) > 2 else (0, 1)
+    assert src.count(old) == count, f"mutation site {old!r} found {src.count(old)} times, expected {count}"
+    at = -1
+    for _ in range(k + 1):
+        at = src.index(old, at + 1)
+    return src[:at] + new + src[at + len(old):]
+
+
 @pytest.mark.parametrize("name", sorted(MUTANTS))
 def test_planted_mistake_is_caught(name, tmp_path):
-    old, new = MUTANTS[name]
-    src = oracle.source_text()
-    assert src.count(old) == 1, f"mutation site for {name} not found exactly once"
-    assert not _run_isolated(src.replace(old, new), str(tmp_path / f"mut_{name}.so")), \
-        f"pins did not catch the planted mistake {name}"
+    src = _plant(oracle.source_text(), MUTANTS[name])
+    assert not _run_isolated(src, str(tmp_path / f"mut_{name}.so")), f"pins did not catch the planted mistake {name}"
