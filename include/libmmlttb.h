@@ -58,8 +58,15 @@ typedef enum {
 
 typedef enum {
     MMLTTB_X_IMPLICIT = 0, /* x_i = i, x == NULL */
-    MMLTTB_X_INT64 = 1     /* x is int64[n] */
+    MMLTTB_X_INT64 = 1,    /* x is int64[n] */
+    MMLTTB_X_F64 = 2       /* x is binary64[n] (the *_typed calls only) */
 } mmlttb_xkind_t;
+
+typedef enum {
+    MMLTTB_Y_F32 = 0, /* y is float32[n] */
+    MMLTTB_Y_F64 = 1, /* y is binary64[n] */
+    MMLTTB_Y_I32 = 2  /* y is int32[n] */
+} mmlttb_ykind_t;
 
 /* One series of a batch (segment). offset: first element of the series in
  * x_base/y_base; n, n_out, r_ps: as for mmlttb_minmaxlttb; out_offset: first
@@ -131,6 +138,30 @@ size_t mmlttb_batched_workspace_size(const mmlttb_segment_t *segs_host, int64_t 
  * the call returns. All segments are checked before anything is enqueued. */
 int mmlttb_minmaxlttb_batched(int xk, const int64_t *x_base, const float *y_base, const mmlttb_segment_t *segs_host,
                               int64_t n_segs, int64_t *out_idx_base, void *ws, size_t ws_bytes, void *stream);
+
+/* Workspace bytes for mmlttb_minmax_typed and mmlttb_minmaxlttb_typed;
+ * independent of n. Returns 0 on invalid arguments. */
+size_t mmlttb_typed_workspace_size(int64_t n, int64_t n_out, int32_t r_ps);
+
+/* MinMax preselection (as mmlttb_minmax, section 2.2.1 MinMax and section 3
+ * step (i)) for y of kind yk: float32, binary64 or int32, aligned to its value
+ * size. Values compare as numbers (-0.0 == +0.0 for the floating types); y
+ * finite (precondition). Same bins, ties, output and capacity as
+ * mmlttb_minmax; r_ps >= 1. */
+int mmlttb_minmax_typed(int yk, const void *y, int64_t n, int64_t n_out, int32_t r_ps, int64_t *out_idx,
+                        int64_t *out_count, void *ws, size_t ws_bytes, void *stream);
+
+/* MinMaxLTTB (section 3) for y of kind yk (float32, binary64, int32) and x of
+ * kind xk (implicit, int64 or binary64; binary64 x finite and strictly
+ * increasing, preconditions). Preselection as mmlttb_minmax_typed; LTTB over
+ * P on Y = y as binary64 (exact) and X = x (binary64 x) or x rounded to
+ * binary64 (int64 x); next-bucket means are the exact sums of the stored x
+ * and of Y, each rounded once to binary64, divided by the count (a sum beyond
+ * the binary64 range rounds to an infinity); areas and ties as mmlttb_lttb.
+ * out_idx receives exactly min(n, n_out) indices. float32 y with implicit or
+ * int64 x gives the indices of mmlttb_minmaxlttb (which is faster). */
+int mmlttb_minmaxlttb_typed(int xk, const void *x, int yk, const void *y, int64_t n, int64_t n_out, int32_t r_ps,
+                            int64_t *out_idx, void *ws, size_t ws_bytes, void *stream);
 
 /* Workspace bytes for mmlttb_minmax_xbins and mmlttb_minmaxlttb_xbins;
  * independent of n. Returns 0 on invalid arguments. */

@@ -78,6 +78,9 @@
  *       values (x as stored; y as its exact binary64 value) rounded once to
  *       binary64, then one division by the count (R6); a sum beyond the
  *       binary64 range rounds to an infinity. binary64 x and y must be finite.
+ *       An area that is not a number (possible only when such a sum
+ *       overflowed) never wins; a bucket with no numeric area keeps its first
+ *       point.
  */
 #include <math.h>
 #include <stdint.h>
@@ -752,7 +755,7 @@ static int lttb_positions_typed(const double *X, const int64_t *xi, const double
         int64_t s0 = 1 + floor_frac(k, m - 2, B);
         int64_t s1 = 1 + floor_frac(k + 1, m - 2, B);
         double best = -1.0;
-        int64_t sel = -1;
+        int64_t sel = s0; /* kept when no area is a number (R15) */
         for (int64_t j = s0; j < s1; j++) {
             double area = fabs((X[a] - MX[k]) * (Y[j] - Y[a]) - (X[a] - X[j]) * (MY[k] - Y[a])); /* R7 */
             if (area > best) { /* lowest index on ties (R8) */

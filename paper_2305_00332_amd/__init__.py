@@ -16,6 +16,9 @@ from .ops import (  # noqa: F401
     segment_table,
     lttb_workspace_size,
     minmax,
+    minmax_typed,
+    minmaxlttb_typed,
+    typed_workspace_size,
     minmax_xbins,
     minmaxlttb_xbins,
     xbins_workspace_size,

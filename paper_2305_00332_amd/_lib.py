@@ -16,7 +16,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libmmlttb.so")
 
 OK, EINVAL, ENOMEM, EDEVICE, ENOTSUP = 0, -1, -2, -3, -4
-X_IMPLICIT, X_INT64 = 0, 1
+X_IMPLICIT, X_INT64, X_F64 = 0, 1, 2
+Y_F32, Y_F64, Y_I32 = 0, 1, 2
 
 # names declared in include/libmmlttb.h
 EXPORTS = (
@@ -29,6 +30,9 @@ EXPORTS = (
     "mmlttb_minmaxlttb",
     "mmlttb_batched_workspace_size",
     "mmlttb_minmaxlttb_batched",
+    "mmlttb_typed_workspace_size",
+    "mmlttb_minmax_typed",
+    "mmlttb_minmaxlttb_typed",
     "mmlttb_xbins_workspace_size",
     "mmlttb_minmax_xbins",
     "mmlttb_minmaxlttb_xbins",
@@ -89,6 +93,11 @@ def load(path: str = LIB_PATH):
     lib.mmlttb_batched_workspace_size.restype = ctypes.c_size_t
     lib.mmlttb_minmaxlttb_batched.argtypes = [ctypes.c_int, _vp, _vp, ctypes.POINTER(Segment), _i64, _vp, _vp,
                                               ctypes.c_size_t, _vp]
+    lib.mmlttb_typed_workspace_size.argtypes = [_i64, _i64, _i32]
+    lib.mmlttb_typed_workspace_size.restype = ctypes.c_size_t
+    lib.mmlttb_minmax_typed.argtypes = [ctypes.c_int, _vp, _i64, _i64, _i32, _vp, _vp, _vp, ctypes.c_size_t, _vp]
+    lib.mmlttb_minmaxlttb_typed.argtypes = [ctypes.c_int, _vp, ctypes.c_int, _vp, _i64, _i64, _i32, _vp, _vp,
+                                            ctypes.c_size_t, _vp]
     lib.mmlttb_xbins_workspace_size.argtypes = [_i64, _i64, _i32]
     lib.mmlttb_xbins_workspace_size.restype = ctypes.c_size_t
     lib.mmlttb_minmax_xbins.argtypes = [_vp, _vp, _i64, _i64, _i32, _vp, _vp, _vp, ctypes.c_size_t, _vp]
@@ -105,7 +114,7 @@ def load(path: str = LIB_PATH):
     lib.mmlttb_profile_enable.argtypes = [ctypes.c_int]
     lib.mmlttb_profile_read.argtypes = [ctypes.c_char_p, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_i64)]
     for f in ("mmlttb_minmax", "mmlttb_lttb", "mmlttb_minmaxlttb", "mmlttb_minmaxlttb_batched", "mmlttb_m4",
-              "mmlttb_minmax_xbins", "mmlttb_minmaxlttb_xbins",
+              "mmlttb_minmax_xbins", "mmlttb_minmaxlttb_xbins", "mmlttb_minmax_typed", "mmlttb_minmaxlttb_typed",
               "mmlttb_everynth", "mmlttb_set_graph_cache", "mmlttb_graph_cache_stats", "mmlttb_set_tuning",
               "mmlttb_get_tuning", "mmlttb_profile_enable", "mmlttb_profile_reset", "mmlttb_profile_read"):
         getattr(lib, f).restype = ctypes.c_int

@@ -267,11 +267,12 @@ bool use_segmented_chain(int64_t maxb_bound)
     return mode != kChainSequential && maxb_bound <= kSegStarts;
 }
 
-SegChainArgs seg_args(void *ws, size_t path, size_t finals, size_t start, const int64_t *XP,
-                      const float *YP, const int64_t *m_ptr, int64_t m_const, int64_t B, const double *MX,
-                      const double *MY, int64_t maxb_bound)
+template <class XT, class YT>
+SegChainArgsT<XT, YT> seg_args(void *ws, size_t path, size_t finals, size_t start, const XT *XP, const YT *YP,
+                               const int64_t *m_ptr, int64_t m_const, int64_t B, const double *MX, const double *MY,
+                               int64_t maxb_bound)
 {
-    SegChainArgs a;
+    SegChainArgsT<XT, YT> a;
     a.XP = XP;
     a.YP = YP;
     a.m_ptr = m_ptr;
@@ -358,6 +359,100 @@ int enqueue_xbin_stream(const int64_t *x, const float *y, int64_t n, int64_t nb,
     MMLTTB_LAUNCH("xbin_bounds", s, launch_xbin_bounds(x, n, nb, bounds, s));
     MMLTTB_LAUNCH("init_keys", s, launch_init_keys(keys, nb, s));
     MMLTTB_LAUNCH("xbin_reduce", s, launch_xbin_reduce(y, bounds, n, nb, chunk, t.unroll, keys, s));
+    return MMLTTB_OK;
+}
+
+// ---------------------------------------------------------------- other value types
+
+struct TyLayout {
+    size_t part, pairs, m, P, XD, YD, MX, MY, path, finals, start, total;
+    int64_t items_cap;
+};
+
+// MinMax partials: at most max(nb, 2^16) work items, so the size depends on
+// n_out and r_ps only.
+TyLayout ty_layout(int64_t n_out, int32_t r_ps)
+{
+    const int64_t nb = n_out * (int64_t)r_ps / 2;
+    const int64_t cap = 2 * nb + 2;
+    const int64_t B = n_out - 2;
+    TyLayout L;
+    L.items_cap = nb > 65536 ? nb : 65536;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t o = off;
+        off = align_up(off + bytes);
+        return o;
+    };
+    L.part = take(sizeof(TypedPartial) * (size_t)L.items_cap);
+    L.pairs = take(16 * (size_t)nb);
+    L.m = take(8);
+    L.P = take(8 * (size_t)cap);
+    L.XD = take(8 * (size_t)cap);
+    L.YD = take(8 * (size_t)cap);
+    L.MX = take(8 * (size_t)B);
+    L.MY = take(8 * (size_t)B);
+    L.path = take(seg_path_bytes(B));
+    L.finals = take(seg_finals_bytes(B));
+    L.start = take((size_t)seg_count(B));
+    L.total = off;
+    return L;
+}
+
+MinMaxGeom typed_geom(int64_t n, int64_t nb, int64_t items_cap, int yk)
+{
+    const Tuning &t = tuning();
+    MinMaxGeom g;
+    g.bins = make_split(n - 2, nb);
+    const int64_t maxbin = g.bins.q + (g.bins.r ? 1 : 0);
+    const int64_t gran = (yk == kYF64 ? 128 : 256) * (int64_t)t.unroll; // points per batch of loads
+    const int64_t cap = items_cap / nb > 1 ? items_cap / nb : 1;
+    int64_t cpb = (maxbin + t.chunk - 1) / t.chunk;
+    cpb = cpb < 1 ? 1 : (cpb > cap ? cap : cpb);
+    int64_t chunk = (maxbin + cpb - 1) / cpb;
+    chunk = (chunk + gran - 1) / gran * gran;
+    g.chunk = chunk;
+    g.chunks_per_bin = (maxbin + chunk - 1) / chunk;
+    g.n_items = nb * g.chunks_per_bin;
+    return g;
+}
+
+int check_typed(int xk, const void *x, int yk, const void *y, int64_t n, int64_t n_out, int32_t r_ps,
+                int32_t min_rps)
+{
+    if (xk != MMLTTB_X_IMPLICIT && xk != MMLTTB_X_INT64 && xk != MMLTTB_X_F64)
+        return fail(MMLTTB_EINVAL, "xk must be MMLTTB_X_IMPLICIT, MMLTTB_X_INT64 or MMLTTB_X_F64, got %d", xk);
+    if ((xk == MMLTTB_X_IMPLICIT) != (x == nullptr))
+        return fail(MMLTTB_EINVAL, "x must be NULL exactly when xk is MMLTTB_X_IMPLICIT");
+    if (yk != MMLTTB_Y_F32 && yk != MMLTTB_Y_F64 && yk != MMLTTB_Y_I32)
+        return fail(MMLTTB_EINVAL, "yk must be MMLTTB_Y_F32, MMLTTB_Y_F64 or MMLTTB_Y_I32, got %d", yk);
+    const uintptr_t ysz = yk == MMLTTB_Y_F64 ? 8 : 4;
+    if (!y || ((uintptr_t)y & (ysz - 1)) || ((uintptr_t)x & 7u))
+        return fail(MMLTTB_EINVAL, "y must be non-NULL and aligned to its value size, x 8-byte aligned");
+    if (n < 1 || n > kMaxN)
+        return fail(MMLTTB_EINVAL, "n must be in [1, 2^62], got %lld", (long long)n);
+    if (n_out < 3 || n_out > kMaxI32)
+        return fail(MMLTTB_EINVAL, "n_out must be in [3, 2^31-1], got %lld", (long long)n_out);
+    if (r_ps < min_rps)
+        return fail(MMLTTB_EINVAL, "r_ps must be >= %d, got %d", min_rps, r_ps);
+    if (n_out * (int64_t)r_ps / 2 > kMaxI32)
+        return fail(MMLTTB_EINVAL, "floor(n_out*r_ps/2) must be <= 2^31-1");
+    return MMLTTB_OK;
+}
+
+// P (with binary64 X_P, Y_P when XD != NULL) and m; n > 2.
+int enqueue_typed_preselect(int xk, const void *x, int yk, const void *y, int64_t n, int64_t nb, void *ws,
+                            const TyLayout &L, int64_t *P, double *XD, double *YD, int64_t *m, hipStream_t s)
+{
+    const MinMaxGeom g = typed_geom(n, nb, L.items_cap, yk);
+    const bool all = nb >= n - 2; // every bin holds at most one point
+    int64_t *pairs = at<int64_t>(ws, L.pairs);
+    if (!all) {
+        TypedPartial *part = at<TypedPartial>(ws, L.part);
+        MMLTTB_LAUNCH("typed_bin_reduce", s, launch_typed_bin_reduce(yk, y, g, tuning().unroll, part, s));
+        MMLTTB_LAUNCH("typed_bin_merge", s, launch_typed_bin_merge(part, nb, g.chunks_per_bin, pairs, s));
+    }
+    MMLTTB_LAUNCH("typed_compact", s, launch_typed_compact(xk, yk, pairs, g.bins, n, x, y, P, XD, YD, m, all, s));
     return MMLTTB_OK;
 }
 
@@ -779,6 +874,76 @@ int mmlttb_minmaxlttb(int xk, const int64_t *x, const float *y, int64_t n, int64
         MMLTTB_LAUNCH("lttb_chain_seg", s, launch_lttb_chain_seg(a, P, out_idx, s));
     } else {
         MMLTTB_LAUNCH("lttb_chain", s, launch_lttb_chain(XP, YP, m, 0, B, MX, MY, P, out_idx, s));
+    }
+    return ok();
+}
+
+size_t mmlttb_typed_workspace_size(int64_t n, int64_t n_out, int32_t r_ps)
+{
+    (void)n;
+    if (n_out < 3 || n_out > kMaxI32 || r_ps < 1 || n_out * (int64_t)r_ps / 2 > kMaxI32)
+        return 0;
+    return ty_layout(n_out, r_ps).total;
+}
+
+int mmlttb_minmax_typed(int yk, const void *y, int64_t n, int64_t n_out, int32_t r_ps, int64_t *out_idx,
+                        int64_t *out_count, void *ws, size_t ws_bytes, void *stream)
+{
+    int rc = check_typed(MMLTTB_X_IMPLICIT, nullptr, yk, y, n, n_out, r_ps, 1);
+    if (rc)
+        return rc;
+    if (!out_idx || !out_count)
+        return fail(MMLTTB_EINVAL, "out_idx and out_count must not be NULL");
+    hipStream_t s = (hipStream_t)stream;
+    if (n <= 2) {
+        MMLTTB_LAUNCH("iota", s, launch_iota(out_idx, n, out_count, s));
+        return ok();
+    }
+    const TyLayout L = ty_layout(n_out, r_ps);
+    if (!ws)
+        return fail(MMLTTB_EINVAL, "ws must not be NULL");
+    if (ws_bytes < L.total)
+        return fail(MMLTTB_ENOMEM, "workspace of %zu bytes is below the %zu required", ws_bytes, L.total);
+    const int64_t nb = n_out * (int64_t)r_ps / 2;
+    rc = enqueue_typed_preselect(MMLTTB_X_IMPLICIT, nullptr, yk, y, n, nb, ws, L, out_idx, nullptr, nullptr,
+                                 out_count, s);
+    return rc ? rc : ok();
+}
+
+int mmlttb_minmaxlttb_typed(int xk, const void *x, int yk, const void *y, int64_t n, int64_t n_out, int32_t r_ps,
+                            int64_t *out_idx, void *ws, size_t ws_bytes, void *stream)
+{
+    int rc = check_typed(xk, x, yk, y, n, n_out, r_ps, 2);
+    if (rc)
+        return rc;
+    if (!out_idx)
+        return fail(MMLTTB_EINVAL, "out_idx must not be NULL");
+    hipStream_t s = (hipStream_t)stream;
+    if (n <= n_out) {
+        MMLTTB_LAUNCH("iota", s, launch_iota(out_idx, n, nullptr, s));
+        return ok();
+    }
+    const TyLayout L = ty_layout(n_out, r_ps);
+    if (!ws)
+        return fail(MMLTTB_EINVAL, "ws must not be NULL");
+    if (ws_bytes < L.total)
+        return fail(MMLTTB_ENOMEM, "workspace of %zu bytes is below the %zu required", ws_bytes, L.total);
+    const int64_t nb = n_out * (int64_t)r_ps / 2;
+    const int64_t B = n_out - 2;
+    int64_t *P = at<int64_t>(ws, L.P), *m = at<int64_t>(ws, L.m);
+    double *XD = at<double>(ws, L.XD), *YD = at<double>(ws, L.YD);
+    double *MX = at<double>(ws, L.MX), *MY = at<double>(ws, L.MY);
+    if ((rc = enqueue_typed_preselect(xk, x, yk, y, n, nb, ws, L, P, XD, YD, m, s)))
+        return rc;
+    MMLTTB_LAUNCH("typed_bucket_means", s, launch_typed_bucket_means(xk, P, x, YD, m, B, MX, MY, s));
+    const int64_t maxb_bound = (2 * nb + B - 1) / B;
+    if (use_segmented_chain(maxb_bound)) {
+        const SegChainArgsD a = seg_args(ws, L.path, L.finals, L.start, (const double *)XD, (const double *)YD, m, 0,
+                                         B, MX, MY, maxb_bound);
+        MMLTTB_LAUNCH("lttb_chain_seg", s, launch_lttb_chain_seg(a, P, out_idx, s));
+    } else {
+        MMLTTB_LAUNCH("lttb_chain", s, launch_lttb_chain((const double *)XD, (const double *)YD, m, 0, B, MX, MY, P,
+                                                         out_idx, s));
     }
     return ok();
 }

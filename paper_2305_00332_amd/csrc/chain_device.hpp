@@ -51,7 +51,8 @@ __device__ inline void bucket_mean_one(const int64_t *__restrict__ XP, const flo
 // last one in finals[s*kSegStarts + l]. Every walk evaluates the same binary64
 // area on the same operands as the sequential pass, so the walk from the true
 // start repeats the sequential picks exactly.
-__device__ inline void seg_walk(const int64_t *__restrict__ XP, const float *__restrict__ YP, const Split &bk,
+template <class XT, class YT>
+__device__ inline void seg_walk(const XT *__restrict__ XP, const YT *__restrict__ YP, const Split &bk,
                                 const double *__restrict__ MX, const double *__restrict__ MY, int64_t s,
                                 int stage_cap, double *lds, uint8_t *__restrict__ path,
                                 uint8_t *__restrict__ finals)
@@ -87,7 +88,9 @@ __device__ inline void seg_walk(const int64_t *__restrict__ XP, const float *__r
         const int64_t s0 = 1 + w.lo, s1 = 1 + w.next_lo(bk);
         w.advance(bk);
         const double mx = smx[k - k0], my = smy[k - k0];
-        double best = -1.0, bx = ax, by = ay;
+        // the bucket's first point stands unless an area beats -1 (areas are
+        // >= 0, or NaN when binary64 means overflow: NaN never wins)
+        double best = -1.0, bx = sx[s0 - p0], by = sy[s0 - p0];
         bo = 0;
         for (int64_t j = s0; j < s1; ++j) {
             const double xj = sx[j - p0], yj = sy[j - p0];

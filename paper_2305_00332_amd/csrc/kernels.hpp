@@ -28,9 +28,10 @@ constexpr int kSegLen = 32;
 constexpr int kSegStarts = 64;
 constexpr int kChaseWindow = 512;
 
-struct SegChainArgs {
-    const int64_t *XP;     // raw x of the points (NULL: x = position)
-    const float *YP;       // y of the points
+template <class XT, class YT>
+struct SegChainArgsT {
+    const XT *XP;          // x of the points (NULL: x = position)
+    const YT *YP;          // y of the points
     const int64_t *m_ptr;  // device point count (NULL: m_const)
     int64_t m_const;
     int64_t B;             // interior buckets
@@ -41,6 +42,10 @@ struct SegChainArgs {
     int64_t S;             // segments
     int stage_cap;         // LDS points per segment (kSegLen * bucket-size bound)
 };
+// Points as stored by the float32 path (raw int64 x, float32 y) and by the
+// typed path (binary64 coordinates).
+using SegChainArgs = SegChainArgsT<int64_t, float>;
+using SegChainArgsD = SegChainArgsT<double, double>;
 
 // ---------------------------------------------------------------- batched
 
@@ -135,6 +140,22 @@ hipError_t launch_m4_bin_reduce(const float *y, const MinMaxGeom &g, int unroll,
 hipError_t launch_m4_compact(const unsigned long long *keys, const Split &bins, int64_t *out, int64_t *count,
                              hipStream_t s);
 hipError_t launch_everynth(int64_t n, int64_t n_out, int64_t *out, hipStream_t s);
+// Value types of the typed path (y) and the per-work-item MinMax partial.
+enum { kYF32 = 0, kYF64 = 1, kYI32 = 2 };
+struct TypedPartial {
+    uint64_t kmin;
+    int64_t imin;
+    uint64_t kmax;
+    int64_t imax;
+};
+hipError_t launch_typed_bin_reduce(int yk, const void *y, const MinMaxGeom &g, int unroll, TypedPartial *part,
+                                   hipStream_t s);
+hipError_t launch_typed_bin_merge(const TypedPartial *part, int64_t nb, int64_t cpb, int64_t *pairs, hipStream_t s);
+hipError_t launch_typed_compact(int xk, int yk, const int64_t *pairs, const Split &bins, int64_t n, const void *x,
+                                const void *y, int64_t *P, double *XD, double *YD, int64_t *m_out, bool all,
+                                hipStream_t s);
+hipError_t launch_typed_bucket_means(int xk, const int64_t *P, const void *x, const double *YD, const int64_t *m_ptr,
+                                     int64_t B, double *MX, double *MY, hipStream_t s);
 hipError_t launch_xbin_bounds(const int64_t *x, int64_t n, int64_t nb, int64_t *bounds, hipStream_t s);
 hipError_t launch_xbin_reduce(const float *y, const int64_t *bounds, int64_t n, int64_t nb, int64_t chunk,
                               int unroll, unsigned long long *keys, hipStream_t s);
@@ -151,6 +172,9 @@ hipError_t launch_bucket_mean_wide(const int64_t *X, const float *Y, int64_t m, 
 hipError_t launch_lttb_chain(const int64_t *XP, const float *YP, const int64_t *m_ptr, int64_t m_const, int64_t B,
                              const double *MX, const double *MY, const int64_t *Pmap, int64_t *out, hipStream_t s);
 hipError_t launch_lttb_chain_seg(const SegChainArgs &a, const int64_t *Pmap, int64_t *out, hipStream_t s);
+hipError_t launch_lttb_chain_seg(const SegChainArgsD &a, const int64_t *Pmap, int64_t *out, hipStream_t s);
+hipError_t launch_lttb_chain(const double *XP, const double *YP, const int64_t *m_ptr, int64_t m_const, int64_t B,
+                             const double *MX, const double *MY, const int64_t *Pmap, int64_t *out, hipStream_t s);
 hipError_t launch_lttb_chain_wide(const int64_t *X, const float *Y, int64_t m, int64_t B, const double *MX,
                                   const double *MY, int64_t *out, hipStream_t s);
 

@@ -132,7 +132,8 @@ __global__ __launch_bounds__(256) void k_bucket_mean_wide(const int64_t *__restr
 // readlane. Buckets wider than the window fall back to direct global reads.
 // Positions are written to out[] during the walk and mapped through Pmap
 // (when given) once the walk is over.
-__global__ __launch_bounds__(256) void k_lttb_chain(const int64_t *__restrict__ XP, const float *__restrict__ YP,
+template <class XT, class YT>
+__global__ __launch_bounds__(256) void k_lttb_chain(const XT *__restrict__ XP, const YT *__restrict__ YP,
                                                     const int64_t *__restrict__ m_ptr, int64_t m_const, int64_t B,
                                                     const double *__restrict__ MX, const double *__restrict__ MY,
                                                     const int64_t *__restrict__ Pmap, int64_t *__restrict__ out)
@@ -175,8 +176,11 @@ __global__ __launch_bounds__(256) void k_lttb_chain(const int64_t *__restrict__ 
             double xj, yj;
             fetch(s0 + off, xj, yj);
             double ar = lttb_area2(ax, ay, xj, yj, mx, my);
-            if (ar > best) {
-                best = ar;
+            // a lane's first candidate stands until an area beats -1, so a
+            // bucket whose areas are all NaN (overflowing binary64 means)
+            // still yields its first point
+            if (ar > best || bj == INT64_MAX) {
+                best = ar > best ? ar : best;
                 bj = s0 + off;
                 bx = xj;
                 by = yj;
@@ -256,7 +260,8 @@ __global__ __launch_bounds__(256) void k_lttb_chain(const int64_t *__restrict__ 
 // possible start point (seg_walk); k_lttb_chain_link_emit (one workgroup)
 // then follows the true start from point 0 through the segments (seg_link)
 // and writes every pick, mapped through Pmap when given.
-__global__ __launch_bounds__(kSegStarts) void k_lttb_chain_seg(SegChainArgs a)
+template <class Args>
+__global__ __launch_bounds__(kSegStarts) void k_lttb_chain_seg(Args a)
 {
     extern __shared__ double lds[];
     const int64_t m = a.m_ptr ? *a.m_ptr : a.m_const;
@@ -264,7 +269,8 @@ __global__ __launch_bounds__(kSegStarts) void k_lttb_chain_seg(SegChainArgs a)
     seg_walk(a.XP, a.YP, bk, a.MX, a.MY, (int64_t)blockIdx.x, a.stage_cap, lds, a.path, a.finals);
 }
 
-__global__ __launch_bounds__(1024) void k_lttb_chain_link_emit(SegChainArgs a, const int64_t *__restrict__ Pmap,
+template <class Args>
+__global__ __launch_bounds__(1024) void k_lttb_chain_link_emit(Args a, const int64_t *__restrict__ Pmap,
                                                                int64_t *__restrict__ out)
 {
     __shared__ uint8_t F[kChaseWindow * kSegStarts];
@@ -395,23 +401,43 @@ hipError_t launch_bucket_mean_wide(const int64_t *X, const float *Y, int64_t m, 
     return hipGetLastError();
 }
 
-hipError_t launch_lttb_chain_seg(const SegChainArgs &a, const int64_t *Pmap, int64_t *out, hipStream_t s)
+template <class Args>
+static hipError_t launch_chain_seg_impl(const Args &a, const int64_t *Pmap, int64_t *out, hipStream_t s)
 {
     if (a.S > 0x7fffffff)
         return hipErrorInvalidConfiguration;
     const size_t lds = (size_t)(2 * a.stage_cap + 2 * kSegLen) * sizeof(double); // points and means of a segment
-    hipLaunchKernelGGL(k_lttb_chain_seg, dim3((unsigned)a.S), dim3(kSegStarts), lds, s, a);
+    hipLaunchKernelGGL(k_lttb_chain_seg<Args>, dim3((unsigned)a.S), dim3(kSegStarts), lds, s, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess)
         return e;
-    hipLaunchKernelGGL(k_lttb_chain_link_emit, dim3(1), dim3(1024), 0, s, a, Pmap, out);
+    hipLaunchKernelGGL(k_lttb_chain_link_emit<Args>, dim3(1), dim3(1024), 0, s, a, Pmap, out);
     return hipGetLastError();
+}
+
+hipError_t launch_lttb_chain_seg(const SegChainArgs &a, const int64_t *Pmap, int64_t *out, hipStream_t s)
+{
+    return launch_chain_seg_impl(a, Pmap, out, s);
+}
+
+hipError_t launch_lttb_chain_seg(const SegChainArgsD &a, const int64_t *Pmap, int64_t *out, hipStream_t s)
+{
+    return launch_chain_seg_impl(a, Pmap, out, s);
 }
 
 hipError_t launch_lttb_chain(const int64_t *XP, const float *YP, const int64_t *m_ptr, int64_t m_const, int64_t B,
                              const double *MX, const double *MY, const int64_t *Pmap, int64_t *out, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_lttb_chain, dim3(1), dim3(256), 0, s, XP, YP, m_ptr, m_const, B, MX, MY, Pmap, out);
+    auto kern = k_lttb_chain<int64_t, float>;
+    hipLaunchKernelGGL(kern, dim3(1), dim3(256), 0, s, XP, YP, m_ptr, m_const, B, MX, MY, Pmap, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_lttb_chain(const double *XP, const double *YP, const int64_t *m_ptr, int64_t m_const, int64_t B,
+                             const double *MX, const double *MY, const int64_t *Pmap, int64_t *out, hipStream_t s)
+{
+    auto kern = k_lttb_chain<double, double>;
+    hipLaunchKernelGGL(kern, dim3(1), dim3(256), 0, s, XP, YP, m_ptr, m_const, B, MX, MY, Pmap, out);
     return hipGetLastError();
 }
 

@@ -65,6 +65,57 @@ def minmax(y, n_out: int, r_ps: int, x=None, out=None, count=None, ws=None, sync
     return out[:m], m
 
 
+_YKIND = {torch.float32: _lib.Y_F32, torch.float64: _lib.Y_F64, torch.int32: _lib.Y_I32}
+_XKIND = {torch.int64: _lib.X_INT64, torch.float64: _lib.X_F64}
+
+
+def _typed_series(y, x):
+    if not isinstance(y, torch.Tensor) or not y.is_cuda or y.dtype not in _YKIND:
+        raise TypeError("y must be a float32, float64 or int32 CUDA (HIP) tensor")
+    if y.dim() != 1 or not y.is_contiguous():
+        raise ValueError("y must be 1-D and contiguous")
+    if x is None:
+        return _lib.X_IMPLICIT, _YKIND[y.dtype]
+    if not isinstance(x, torch.Tensor) or x.dtype not in _XKIND or x.device != y.device:
+        raise TypeError("x must be an int64 or float64 tensor on y's device")
+    if x.dim() != 1 or not x.is_contiguous() or x.numel() != y.numel():
+        raise ValueError("x must be 1-D, contiguous and as long as y")
+    return _XKIND[x.dtype], _YKIND[y.dtype]
+
+
+def typed_workspace_size(n: int, n_out: int, r_ps: int) -> int:
+    return int(_lib.load().mmlttb_typed_workspace_size(n, n_out, r_ps))
+
+
+def minmax_typed(y, n_out: int, r_ps: int, out=None, count=None, ws=None, sync: bool = True):
+    """MinMax preselection for float32, float64 or int32 y. Returns (P, m) as minmax()."""
+    lib = _lib.load()
+    _, yk = _typed_series(y, None)
+    n = y.numel()
+    cap = max(2 * (n_out * r_ps // 2) + 2, min(n, 2), 1)
+    out = out if out is not None else torch.empty(cap, dtype=torch.int64, device=y.device)
+    count = count if count is not None else torch.empty(1, dtype=torch.int64, device=y.device)
+    ws = _workspace(lib.mmlttb_typed_workspace_size(n, n_out, r_ps), y.device, ws)
+    _lib.check(lib.mmlttb_minmax_typed(yk, y.data_ptr(), n, n_out, r_ps, out.data_ptr(), count.data_ptr(),
+                                       ws.data_ptr(), ws.numel(), _lib.stream_ptr()))
+    if not sync:
+        return out, count
+    m = int(count.item())
+    return out[:m], m
+
+
+def minmaxlttb_typed(y, n_out: int, r_ps: int, x=None, out=None, ws=None):
+    """MinMaxLTTB for float32, float64 or int32 y and implicit, int64 or float64 x."""
+    lib = _lib.load()
+    xk, yk = _typed_series(y, x)
+    n = y.numel()
+    out = out if out is not None else torch.empty(max(min(n, n_out), 1), dtype=torch.int64, device=y.device)
+    ws = _workspace(lib.mmlttb_typed_workspace_size(n, n_out, r_ps), y.device, ws)
+    _lib.check(lib.mmlttb_minmaxlttb_typed(xk, _lib.ptr(x), yk, y.data_ptr(), n, n_out, r_ps, out.data_ptr(),
+                                           ws.data_ptr(), ws.numel(), _lib.stream_ptr()))
+    return out[: min(n, n_out)]
+
+
 def xbins_workspace_size(n: int, n_out: int, r_ps: int) -> int:
     return int(_lib.load().mmlttb_xbins_workspace_size(n, n_out, r_ps))
 
