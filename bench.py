@@ -72,6 +72,7 @@ def main():
     ap.add_argument("--skip-served", action="store_true")
     ap.add_argument("--skip-downsamplers", action="store_true")
     ap.add_argument("--skip-xbins", action="store_true")
+    ap.add_argument("--skip-typed", action="store_true")
     ap.add_argument("--batch-series", type=int, default=4096)
     ap.add_argument("--pool-series", type=int, default=512)
     ap.add_argument("--rates", type=str, default="100,500,1000,2000,5000")
@@ -107,6 +108,8 @@ def main():
         result["downsamplers"] = bench_downsamplers(args)
     if not args.skip_xbins:
         result["xbins"] = bench_xbins(args)
+    if not args.skip_typed:
+        result["typed"] = bench_typed(args)
     if not args.skip_comparator:
         result["comparator"] = bench_comparator(args)
     if not args.skip_batched:
@@ -362,6 +365,73 @@ def bench_xbins(args, reps: int = 10):
     log(f"  xbins: {res}")
     del x, y, ws
     torch.cuda.empty_cache()
+    return res
+
+
+def bench_typed(args, reps: int = 10):
+    """MinMaxLTTB on other value types at the headline size (n=1e9, n_out and
+    r_ps as the headline): float64 y with float64 timestamps, and int32 y with
+    implicit x. Call and stream-kernel times, the stream's HBM roofline
+    fraction (it reads y once: 8 or 4 B per point), parity with the oracle."""
+    import numpy as np
+    import torch
+
+    import oracle
+    from paper_2305_00332_amd import autotune, ops, synth
+
+    n, n_out, r_ps = int(args.n), args.n_out, args.r_ps
+    dev = torch.device("cuda", 0)
+    res = {}
+    for name, make_y, make_x, ybytes in [
+        ("f64_y_f64_x", lambda: synth.random_walk(n, args.seed, device=dev, dtype=torch.float64),
+         lambda: synth.float_x(n, args.seed, device=dev), 8),
+        ("i32_y", lambda: synth.int_series(n, args.seed, device=dev), lambda: None, 4),
+    ]:
+        tuned = autotune.apply("typed_f64" if ybytes == 8 else "typed_i32") or autotune.apply("single")
+        log(f"typed: {name}, n={n}, tuning {ops.get_tuning()} (cache entry: {tuned})")
+        y, x = make_y(), make_x()
+        torch.cuda.synchronize()
+        out = torch.empty(n_out, dtype=torch.int64, device=dev)
+        ws = torch.empty(ops.typed_workspace_size(n, n_out, r_ps), dtype=torch.uint8, device=dev)
+
+        def call():
+            ops.minmaxlttb_typed(y, n_out, r_ps, x=x, out=out, ws=ws)
+
+        call()
+        torch.cuda.synchronize()
+        ops.profile_enable(True)
+        ops.profile_reset()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            call()
+        torch.cuda.synchronize()
+        wall = (time.perf_counter() - t0) * 1e3 / reps
+        ops.profile_enable(False)
+        kern = {}
+        for k in ("typed_bin_reduce", "typed_bin_merge", "typed_compact", "typed_bucket_means", "lttb_chain_seg",
+                  "lttb_chain"):
+            tot, c = ops.profile_read(k)
+            kern[k] = round(tot / c, 5) if c else None
+        alg = ybytes * n
+        gbs = alg / (kern["typed_bin_reduce"] * 1e-3) / 1e9
+        entry = {"call_ms": round(wall, 5), "gpts_per_s": round(n / (wall * 1e-3) / 1e9, 3), "kernel_avg_ms": kern,
+                 "tuning": dict(zip(("unroll", "chunk", "chain", "tile"), ops.get_tuning())),
+                 "stream_roofline": {"kernel": "typed_bin_reduce", "algorithmic_bytes": alg,
+                                     "achieved_GBps": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4)}}
+        if not args.no_cpu_baseline:
+            y_np = y.cpu().numpy()
+            x_np = None if x is None else x.cpu().numpy()
+            c0 = time.perf_counter()
+            want = oracle.minmaxlttb_typed(y_np, n_out, r_ps, x_np)
+            entry["oracle_s"] = round(time.perf_counter() - c0, 3)
+            entry["parity_vs_oracle"] = bool(np.array_equal(out.cpu().numpy(), want))
+            del y_np, x_np
+        log(f"  {name}: {entry}")
+        res[name] = entry
+        del y, x, ws
+        torch.cuda.empty_cache()
+    res["workload"] = (f"one series, n={n}: float64 random walk with float64 second timestamps, and int32 counts "
+                       f"with implicit x (seed={args.seed}); MinMaxLTTB n_out={n_out}, r_ps={r_ps}")
     return res
 
 

@@ -8,10 +8,11 @@ Parameters (none changes any result; see mmlttb_set_tuning):
           (bins per workgroup = tile / bin size, a power of two <= 256)
 
 tune_single() sweeps unroll x chunk on one resident series, timing the stream
-kernel with the library's HIP events; tune_batched() sweeps tile x chunk x
-unroll on a batch, timing whole batched calls. Results are cached as JSON,
-keyed by GPU architecture, HIP runtime and library version and the workload
-class ("single", "batched"); apply(kind) sets the cached choice.
+kernel with the library's HIP events; tune_typed() does the same for the
+stream of the other value types (classes "typed_f64", "typed_i32");
+tune_batched() sweeps tile x chunk x unroll on a batch, timing whole batched
+calls. Results are cached as JSON, keyed by GPU architecture, HIP runtime and
+library version and the workload class; apply(kind) sets the cached choice.
 
     python -m paper_2305_00332_amd.autotune --out tune_cache.json
 """
@@ -83,7 +84,7 @@ def _median_ms(fn, reps: int) -> float:
     return statistics.median(times)
 
 
-def tune_single(y, n_out: int, r_ps: int, unrolls=(2, 4, 8), chunks=(8192, 16384, 32768, 65536, 131072, 262144), reps=5,
+def tune_single(y, n_out: int, r_ps: int, unrolls=(2, 4, 8), chunks=(16384, 65536, 262144, 1 << 20, 1 << 22), reps=5,
                 log=None):
     """Sweep the stream kernel's parameters on one resident series."""
     import torch
@@ -118,6 +119,42 @@ def tune_single(y, n_out: int, r_ps: int, unrolls=(2, 4, 8), chunks=(8192, 16384
             "workload": {"n": int(y.numel()), "n_out": n_out, "r_ps": r_ps}, "sweep": results}
 
 
+def tune_typed(y, n_out: int, r_ps: int, unrolls=(1, 2, 4, 8), chunks=(65536, 262144, 1 << 20), reps=5, log=None):
+    """Sweep the typed stream kernel's parameters on one resident series
+    (float64 or int32 y, implicit x)."""
+    import torch
+
+    from . import ops
+
+    old = ops.get_tuning()
+    out = torch.empty(n_out, dtype=torch.int64, device=y.device)
+    ws = torch.empty(ops.typed_workspace_size(y.numel(), n_out, r_ps), dtype=torch.uint8, device=y.device)
+    results = []
+    try:
+        for u, c in itertools.product(unrolls, chunks):
+            ops.set_tuning(unroll=u, chunk=c)
+            ops.minmaxlttb_typed(y, n_out, r_ps, out=out, ws=ws)
+            torch.cuda.synchronize()
+            ops.profile_enable(True)
+            ops.profile_reset()
+            for _ in range(reps):
+                ops.minmaxlttb_typed(y, n_out, r_ps, out=out, ws=ws)
+            torch.cuda.synchronize()
+            ops.profile_enable(False)
+            tot, cnt = ops.profile_read("typed_bin_reduce")
+            ms = tot / max(cnt, 1)
+            results.append({"unroll": u, "chunk": ops.get_tuning()[1], "kernel_ms": round(ms, 5)})
+            if log:
+                log(f"  unroll={u} chunk={c}: {ms:.4f} ms")
+    finally:
+        ops.profile_enable(False)
+        ops.set_tuning(*old)
+    best = min(results, key=lambda r: r["kernel_ms"])
+    return {"best": {"unroll": best["unroll"], "chunk": best["chunk"]}, "metric": "typed_bin_reduce kernel ms",
+            "workload": {"n": int(y.numel()), "dtype": str(y.dtype), "n_out": n_out, "r_ps": r_ps},
+            "sweep": results}
+
+
 def tune_batched(y, segs, x=None, tiles=(2048, 4096, 8192), chunks=(16384, 65536, 262144), unrolls=(2, 4, 8), reps=3,
                  log=None):
     """Sweep the batched stream parameters on one batch (whole-call time)."""
@@ -150,7 +187,10 @@ def main():
     ap.add_argument("--out", default=CACHE)
     ap.add_argument("--n", type=float, default=1e9)
     ap.add_argument("--batch-series", type=int, default=4096)
+    ap.add_argument("--only", default="single,typed_f64,typed_i32,batched",
+                    help="comma-separated workload classes to tune")
     args = ap.parse_args()
+    only = set(args.only.split(","))
 
     import torch
 
@@ -162,12 +202,25 @@ def main():
     _lib.load()
     log(f"device {device_key()}")
     n = int(args.n)
-    log(f"single: {n} points")
-    y = synth.random_walk(n, 3, device="cuda")
-    torch.cuda.synchronize()
-    save_entry("single", tune_single(y, 1000, 4, log=log), args.out)
-    del y
-    torch.cuda.empty_cache()
+    if "single" in only:
+        log(f"single: {n} points")
+        y = synth.random_walk(n, 3, device="cuda")
+        torch.cuda.synchronize()
+        save_entry("single", tune_single(y, 1000, 4, log=log), args.out)
+        del y
+        torch.cuda.empty_cache()
+    for kind, make in (("typed_f64", lambda: synth.random_walk(n, 3, device="cuda", dtype=torch.float64)),
+                       ("typed_i32", lambda: synth.int_series(n, 3, device="cuda"))):
+        if kind in only:
+            log(f"{kind}: {n} points")
+            y = make()
+            torch.cuda.synchronize()
+            save_entry(kind, tune_typed(y, 1000, 4, log=log), args.out)
+            del y
+            torch.cuda.empty_cache()
+    if "batched" not in only:
+        print(json.dumps(load_cache(args.out).get(device_key(), {}), indent=1))
+        return
     lengths = synth.batch_lengths(args.batch_series, 1e3, 1e7, 4)
     n_outs = synth.choice([200, 500, 1000, 2000], args.batch_series, 40)
     log(f"batched: {args.batch_series} series, {int(lengths.sum())} points")

@@ -246,6 +246,22 @@ int check_rps(int64_t n, int64_t n_out, int32_t r_ps, int32_t min_rps = 2)
             return fail(MMLTTB_EDEVICE, "%s launch failed: %s", name, hipGetErrorString(e_));                          \
     } while (0)
 
+// Work items (one wave each) a stream launch should have to keep every CU
+// busy: 8 waves per CU of the 256 on MI355X. Fewer, longer items leave CUs
+// idle; many more add per-item reductions and merges.
+constexpr int64_t kFillItems = 2048;
+
+// Chunks per bin: enough for items of at most `chunk` points, and about
+// kFillItems items in all (rounded to the nearest whole count per bin).
+int64_t chunks_per_bin(int64_t maxbin, int64_t nb, int64_t chunk)
+{
+    int64_t cpb = (maxbin + chunk - 1) / chunk;
+    const int64_t fill = (kFillItems + nb / 2) / nb;
+    cpb = cpb > fill ? cpb : fill;
+    cpb = cpb < maxbin ? cpb : maxbin;
+    return cpb < 1 ? 1 : cpb;
+}
+
 // Bins over `len` points (the interior n-2 for MinMax, all n for M4).
 MinMaxGeom minmax_geom(int64_t len, int64_t nb)
 {
@@ -253,10 +269,10 @@ MinMaxGeom minmax_geom(int64_t len, int64_t nb)
     MinMaxGeom g;
     g.bins = make_split(len, nb);
     const int64_t maxbin = g.bins.q + (g.bins.r ? 1 : 0);
-    g.chunk = t.chunk;
+    const int64_t gran = 256 * (int64_t)t.unroll; // points per batch of loads
+    const int64_t cpb = chunks_per_bin(maxbin, nb, t.chunk);
+    g.chunk = ((maxbin + cpb - 1) / cpb + gran - 1) / gran * gran;
     g.chunks_per_bin = (maxbin + g.chunk - 1) / g.chunk;
-    if (g.chunks_per_bin < 1)
-        g.chunks_per_bin = 1;
     g.n_items = nb * g.chunks_per_bin;
     return g;
 }
@@ -354,8 +370,8 @@ int enqueue_xbin_stream(const int64_t *x, const float *y, int64_t n, int64_t nb,
     unsigned long long *keys = at<unsigned long long>(ws, L.mm.keys);
     const int64_t gran = 256 * (int64_t)t.unroll;
     const int64_t avg = (n - 2 + nb - 1) / nb;
-    int64_t chunk = (avg + gran - 1) / gran * gran;
-    chunk = chunk < t.chunk ? chunk : t.chunk;
+    const int64_t cpb = chunks_per_bin(avg, nb, t.chunk);
+    const int64_t chunk = ((avg + cpb - 1) / cpb + gran - 1) / gran * gran;
     MMLTTB_LAUNCH("xbin_bounds", s, launch_xbin_bounds(x, n, nb, bounds, s));
     MMLTTB_LAUNCH("init_keys", s, launch_init_keys(keys, nb, s));
     MMLTTB_LAUNCH("xbin_reduce", s, launch_xbin_reduce(y, bounds, n, nb, chunk, t.unroll, keys, s));
@@ -407,8 +423,8 @@ MinMaxGeom typed_geom(int64_t n, int64_t nb, int64_t items_cap, int yk)
     const int64_t maxbin = g.bins.q + (g.bins.r ? 1 : 0);
     const int64_t gran = (yk == kYF64 ? 128 : 256) * (int64_t)t.unroll; // points per batch of loads
     const int64_t cap = items_cap / nb > 1 ? items_cap / nb : 1;
-    int64_t cpb = (maxbin + t.chunk - 1) / t.chunk;
-    cpb = cpb < 1 ? 1 : (cpb > cap ? cap : cpb);
+    int64_t cpb = chunks_per_bin(maxbin, nb, t.chunk);
+    cpb = cpb > cap ? cap : cpb;
     int64_t chunk = (maxbin + cpb - 1) / cpb;
     chunk = (chunk + gran - 1) / gran * gran;
     g.chunk = chunk;

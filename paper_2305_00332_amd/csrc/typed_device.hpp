@@ -1,11 +1,11 @@
 // Device pieces of the path for other value types: float64 and int32 y,
 // float64 x (float32 y takes it only together with float64 x).
 //
-// Values are compared through order keys (unsigned integers ordered like the
-// numbers, -0.0 and +0.0 on one key), so one reduction serves every type;
-// 64-bit keys do not leave room for an index next to them, so the MinMax
-// stream writes one (key, index) partial per work item and a second kernel
-// merges each bin's partials.
+// The stream compares values as numbers and hands each work item's extremes
+// on as order keys (unsigned integers ordered like the numbers, -0.0 and +0.0
+// on one key). 64-bit keys leave no room for an index next to them, so the
+// MinMax stream writes one (key, index) partial per work item and a second
+// kernel merges each bin's partials.
 #pragma once
 
 #include "device_common.hpp"
@@ -26,6 +26,10 @@ struct ValueTraits<float> {
     __device__ static Key key(float v) { return f32_order_key(v); }
     __device__ static float at(const Vec &v, int i) { return i == 0 ? v.x : i == 1 ? v.y : i == 2 ? v.z : v.w; }
     __device__ static double widen(float v) { return (double)v; }
+    __device__ static float lo_id() { return __int_as_float(0x7f800000); }   // +inf
+    __device__ static float hi_id() { return -__int_as_float(0x7f800000); }  // -inf
+    __device__ static float vmin(float a, float b) { return fminf(a, b); }
+    __device__ static float vmax(float a, float b) { return fmaxf(a, b); }
 };
 
 template <>
@@ -36,6 +40,10 @@ struct ValueTraits<int32_t> {
     __device__ static Key key(int32_t v) { return (uint32_t)v ^ 0x80000000u; }
     __device__ static int32_t at(const Vec &v, int i) { return i == 0 ? v.x : i == 1 ? v.y : i == 2 ? v.z : v.w; }
     __device__ static double widen(int32_t v) { return (double)v; }
+    __device__ static int32_t lo_id() { return INT32_MAX; }
+    __device__ static int32_t hi_id() { return INT32_MIN; }
+    __device__ static int32_t vmin(int32_t a, int32_t b) { return a < b ? a : b; }
+    __device__ static int32_t vmax(int32_t a, int32_t b) { return a > b ? a : b; }
 };
 
 template <>
@@ -51,6 +59,10 @@ struct ValueTraits<double> {
     }
     __device__ static double at(const Vec &v, int i) { return i == 0 ? v.x : v.y; }
     __device__ static double widen(double v) { return v; }
+    __device__ static double lo_id() { return __longlong_as_double(0x7ff0000000000000ll); }  // +inf
+    __device__ static double hi_id() { return -__longlong_as_double(0x7ff0000000000000ll); } // -inf
+    __device__ static double vmin(double a, double b) { return fmin(a, b); }
+    __device__ static double vmax(double a, double b) { return fmax(a, b); }
 };
 
 template <class K>
@@ -75,21 +87,20 @@ __device__ inline K wave_max_key(K v)
     return v;
 }
 
-// Reduce y[lo, hi) (hi > lo) with one full wave: the smallest and largest
-// order keys and the lowest index holding each (uniform across the wave).
-// Same scheme as the float32 stream: 16-byte nontemporal loads in batches of
-// U per lane, the batch where each lane first reached its extreme, a wave
-// reduction of the keys, then a re-read of only the winning batch.
+// Reduce y[lo, hi) (hi > lo) with one full wave: the order keys of the
+// smallest and largest values and the lowest index holding each (uniform
+// across the wave). Same scheme as the float32 stream: values are compared
+// as numbers (finite inputs; -0.0 == +0.0), 16-byte nontemporal loads in
+// batches of U per lane, the batch where each lane first reached its extreme,
+// a wave reduction, then a re-read of only the winning batch.
 template <class T, int U>
 __device__ inline void wave_reduce_keys(const T *__restrict__ y, int64_t lo, int64_t hi, int lane,
                                         typename ValueTraits<T>::Key &o_kmin, int64_t &o_imin,
                                         typename ValueTraits<T>::Key &o_kmax, int64_t &o_imax)
 {
     using Tr = ValueTraits<T>;
-    using K = typename Tr::Key;
     using V = typename Tr::Vec;
     constexpr int W = Tr::kLanes;
-    const K kHi = (K)~(K)0;
     // head: values before the first 16-byte boundary; tail: after the last
     // full vector; fewer than W each, handled by lanes 0.. and 8..
     const uint64_t addr = (uint64_t)(uintptr_t)(y + lo);
@@ -100,33 +111,56 @@ __device__ inline void wave_reduce_keys(const T *__restrict__ y, int64_t lo, int
     const int64_t body_end = body + nvec * W;
     const V *__restrict__ vv = reinterpret_cast<const V *>(y + body);
 
-    K smin = kHi, smax = 0;
+    T smin = Tr::lo_id(), smax = Tr::hi_id();
     int64_t sidx = INT64_MAX;
     if (lane < head) {
         sidx = lo + lane;
     } else if (lane >= 8 && lane < 8 + (hi - body_end)) {
         sidx = body_end + (lane - 8);
     }
-    if (sidx != INT64_MAX) {
-        smin = smax = Tr::key(y[sidx]);
-    }
+    if (sidx != INT64_MAX)
+        smin = smax = y[sidx];
 
     constexpr int64_t kPerBatch = (int64_t)kWave * U; // vectors per batch
-    const int64_t nbatch = (nvec + kPerBatch - 1) / kPerBatch;
-    K mn = kHi, mx = 0;
+    const int64_t nfull = nvec / kPerBatch;
+    T mn = Tr::lo_id(), mx = Tr::hi_id();
     int64_t bmn = -1, bmx = -1;
-    for (int64_t t = 0; t < nbatch; ++t) {
-        K a = kHi, b = 0;
+    for (int64_t t = 0; t < nfull; ++t) {
+        V d[U];
+        const V *p = vv + t * kPerBatch + lane;
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            d[u] = __builtin_nontemporal_load(p + u * kWave);
+        T a = Tr::at(d[0], 0), b = a;
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+#pragma unroll
+            for (int i = (u == 0 ? 1 : 0); i < W; ++i) {
+                a = Tr::vmin(a, Tr::at(d[u], i));
+                b = Tr::vmax(b, Tr::at(d[u], i));
+            }
+        }
+        if (a < mn) {
+            mn = a;
+            bmn = t;
+        }
+        if (b > mx) {
+            mx = b;
+            bmx = t;
+        }
+    }
+    if (nfull * kPerBatch < nvec) { // last, partial batch
+        const int64_t t = nfull;
+        T a = Tr::lo_id(), b = Tr::hi_id();
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int64_t q = t * kPerBatch + u * kWave + lane;
             if (q < nvec) {
-                const V d = __builtin_nontemporal_load(vv + q);
+                const V d = vv[q];
 #pragma unroll
                 for (int i = 0; i < W; ++i) {
-                    const K k = Tr::key(Tr::at(d, i));
-                    a = k < a ? k : a;
-                    b = k > b ? k : b;
+                    a = Tr::vmin(a, Tr::at(d, i));
+                    b = Tr::vmax(b, Tr::at(d, i));
                 }
             }
         }
@@ -139,9 +173,15 @@ __device__ inline void wave_reduce_keys(const T *__restrict__ y, int64_t lo, int
             bmx = t;
         }
     }
-    const K wmin = wave_min_key<K>(mn < smin ? mn : smin);
-    const K wmax = wave_max_key<K>(mx > smax ? mx : smax);
+    T wmin = Tr::vmin(mn, smin), wmax = Tr::vmax(mx, smax);
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        wmin = Tr::vmin(wmin, __shfl_xor(wmin, off));
+        wmax = Tr::vmax(wmax, __shfl_xor(wmax, off));
+    }
 
+    // lowest index holding each extreme: the lane's scalar value, and the
+    // first match inside the lane's winning batch
     int64_t cmin = (sidx != INT64_MAX && smin == wmin) ? sidx : INT64_MAX;
     int64_t cmax = (sidx != INT64_MAX && smax == wmax) ? sidx : INT64_MAX;
     if (bmn >= 0 && mn == wmin) {
@@ -152,7 +192,7 @@ __device__ inline void wave_reduce_keys(const T *__restrict__ y, int64_t lo, int
                 const V d = vv[q];
 #pragma unroll
                 for (int i = W - 1; i >= 0; --i)
-                    if (Tr::key(Tr::at(d, i)) == wmin)
+                    if (Tr::at(d, i) == wmin)
                         cmin = (body + W * q + i) < cmin ? body + W * q + i : cmin;
             }
         }
@@ -165,13 +205,13 @@ __device__ inline void wave_reduce_keys(const T *__restrict__ y, int64_t lo, int
                 const V d = vv[q];
 #pragma unroll
                 for (int i = W - 1; i >= 0; --i)
-                    if (Tr::key(Tr::at(d, i)) == wmax)
+                    if (Tr::at(d, i) == wmax)
                         cmax = (body + W * q + i) < cmax ? body + W * q + i : cmax;
             }
         }
     }
-    o_kmin = wmin;
-    o_kmax = wmax;
+    o_kmin = Tr::key(wmin);
+    o_kmax = Tr::key(wmax);
     o_imin = wave_min_i64(cmin);
     o_imax = wave_min_i64(cmax);
 }
