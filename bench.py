@@ -33,6 +33,20 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+def host_cpu_model() -> str:
+    """CPU model name and logical core count of the host the oracle ran on."""
+    name = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    name = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return f"{name} ({os.cpu_count()} logical cores visible)"
+
+
 def kernel_source_sha() -> str:
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
@@ -231,6 +245,7 @@ def bench_headline(args):
             times.append(time.perf_counter() - c0)
         t = float(np.median(times))
         result["cpu_baseline"] = {"value": round(n / t / 1e9, 4), "unit": "Gpts/s", "cores": 1, "kind": "oracle",
+                                  "host_cpu": host_cpu_model(),
                                   "sample": f"the full workload (n={n}) run {len(times)} times single-threaded, "
                                             f"median {t:.3f} s"}
         result["parity_vs_oracle"] = bool(np.array_equal(out.cpu().numpy(), want))
@@ -482,6 +497,14 @@ def bench_comparator(args):
             "parity_vs_oracle": bool(np.array_equal(out_m.cpu().numpy(), want_m))}
     del x, y, y_np, x_np
     torch.cuda.empty_cache()
+    res["paper_context"] = {
+        "serial_speedup_vs_lttb": "about 10x (an order of magnitude)",
+        "parallel_speedup_vs_lttb": "30x",
+        "source": "section 3.2: CPU implementations (a C LTTB, tsdownsample's MinMaxLTTB); hardware, core "
+                  "count, N, n_out and r_ps are not stated",
+        "here": "cpu_speedup_vs_cpu_lttb compares the two single-thread oracle runs; gpu_speedup_vs_gpu_lttb "
+                "the two GPU paths",
+    }
     return res
 
 
