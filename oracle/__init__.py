@@ -18,6 +18,9 @@ from .oracle import (  # noqa: F401
     m4,
     everynth,
     minmax,
+    minmax_simplify,
+    simplify_points,
+    SIMPLIFIERS,
     minmax_typed,
     minmaxlttb_typed,
     exact_sum_f64,

@@ -81,6 +81,29 @@
  *       An area that is not a number (possible only when such a sum
  *       overflowed) never wins; a bucket with no numeric area keeps its first
  *       point.
+ *
+ * MinMax preselection in front of other line simplifiers (section 4 names
+ * Visvalingam-Whyatt, Douglas-Peucker and Longest-Line-Bucket as future work
+ * without defining them; these are their standard forms, run on P exactly as
+ * LTTB is, X and Y binary64 as in R7). m > n_out points in, n_out out; m <=
+ * n_out keeps every point.
+ *   R16 VW: while more than n_out points remain, remove the interior point
+ *       whose doubled triangle area with its current neighbours a < j < b,
+ *       |(Xa - Xb)(Yj - Ya) - (Xa - Xj)(Yb - Ya)|, is smallest (lowest index
+ *       on ties), then recompute the areas of its two neighbours.
+ *   R17 DP with a point budget: start from {first, last}; the farthest point
+ *       of a segment a < j < b of consecutive kept points maximises
+ *       |(Xb - Xa)(Yj - Ya) - (Xj - Xa)(Yb - Ya)| (lowest index on ties) and
+ *       its key is c * c / ((Xb - Xa)^2 + (Yb - Ya)^2) for that value c, the
+ *       squared distance to the chord, in this operation order (a key that
+ *       is not a number, from a chord of zero length, counts as -1); while
+ *       fewer than n_out points are kept, keep the farthest point of the
+ *       segment with the largest key (the lowest such point on ties).
+ *   R18 LLB: LTTB's buckets (R5); one point per bucket, first and last
+ *       fixed, maximising the total length of the polyline, sum of
+ *       sqrt((Xj - Xi)^2 + (Yj - Yi)^2) taken bucket by bucket in order; by
+ *       dynamic programming over the buckets, each point keeping the lowest
+ *       index among the predecessors that give the largest total (strict >).
  */
 #include <math.h>
 #include <stdint.h>
@@ -822,6 +845,222 @@ int oracle_minmaxlttb_typed(int xk, const void *x, int yk, const void *y, int64_
     free(xf);
     free(pos);
     return rc;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Other simplifiers on the preselected points (R16-R18).                    */
+/* X, Y: binary64 coordinates of m points; out: n_out positions (m > n_out). */
+/* ------------------------------------------------------------------------ */
+
+static double vw_area(const double *X, const double *Y, int64_t a, int64_t j, int64_t b)
+{
+    return fabs((X[a] - X[b]) * (Y[j] - Y[a]) - (X[a] - X[j]) * (Y[b] - Y[a])); /* R16 */
+}
+
+static int vw_positions(const double *X, const double *Y, int64_t m, int64_t n_out, int64_t *out)
+{
+    int64_t *prev = (int64_t *)malloc(sizeof(int64_t) * (size_t)m);
+    int64_t *next = (int64_t *)malloc(sizeof(int64_t) * (size_t)m);
+    double *area = (double *)malloc(sizeof(double) * (size_t)m);
+    char *alive = (char *)malloc((size_t)m);
+    if (!prev || !next || !area || !alive) {
+        free(prev);
+        free(next);
+        free(area);
+        free(alive);
+        return ORC_ENOMEM;
+    }
+    for (int64_t i = 0; i < m; i++) {
+        prev[i] = i - 1;
+        next[i] = i + 1;
+        alive[i] = 1;
+    }
+    for (int64_t i = 1; i < m - 1; i++)
+        area[i] = vw_area(X, Y, i - 1, i, i + 1);
+    /* plain scan for the smallest area each time: slow and obviously right */
+    for (int64_t left = m; left > n_out; left--) {
+        int64_t sel = -1;
+        for (int64_t i = 1; i < m - 1; i++)
+            if (alive[i] && (sel < 0 || area[i] < area[sel])) /* lowest index on ties (R16) */
+                sel = i;
+        alive[sel] = 0;
+        int64_t a = prev[sel], b = next[sel];
+        next[a] = b;
+        prev[b] = a;
+        if (a > 0)
+            area[a] = vw_area(X, Y, prev[a], a, b);
+        if (b < m - 1)
+            area[b] = vw_area(X, Y, a, b, next[b]);
+    }
+    int64_t c = 0;
+    for (int64_t i = 0; i < m; i++)
+        if (alive[i])
+            out[c++] = i;
+    free(prev);
+    free(next);
+    free(area);
+    free(alive);
+    return ORC_OK;
+}
+
+/* Farthest interior point of segment (a, b) and its key (R17); -1 if none. */
+static int64_t dp_farthest(const double *X, const double *Y, int64_t a, int64_t b, double *key)
+{
+    int64_t sel = -1;
+    double best = -1.0;
+    for (int64_t j = a + 1; j < b; j++) {
+        double c = fabs((X[b] - X[a]) * (Y[j] - Y[a]) - (X[j] - X[a]) * (Y[b] - Y[a]));
+        if (c > best) { /* lowest index on ties (R17) */
+            best = c;
+            sel = j;
+        }
+    }
+    if (sel >= 0) {
+        double dx = X[b] - X[a], dy = Y[b] - Y[a];
+        *key = best * best / (dx * dx + dy * dy);
+        if (isnan(*key))
+            *key = -1.0; /* R17 */
+    }
+    return sel;
+}
+
+static int dp_positions(const double *X, const double *Y, int64_t m, int64_t n_out, int64_t *out)
+{
+    char *kept = (char *)calloc((size_t)m, 1);
+    if (!kept)
+        return ORC_ENOMEM;
+    kept[0] = kept[m - 1] = 1;
+    /* plain rescan of every segment each time */
+    for (int64_t count = 2; count < n_out; count++) {
+        int64_t best_j = -1;
+        double best_key = -2.0; /* below every key */
+        int64_t a = 0;
+        for (int64_t b = 1; b < m; b++) {
+            if (!kept[b])
+                continue;
+            double key;
+            int64_t j = dp_farthest(X, Y, a, b, &key);
+            if (j >= 0 && key > best_key) { /* segments in index order: the lowest point wins ties */
+                best_key = key;
+                best_j = j;
+            }
+            a = b;
+        }
+        kept[best_j] = 1;
+    }
+    int64_t c = 0;
+    for (int64_t i = 0; i < m; i++)
+        if (kept[i])
+            out[c++] = i;
+    free(kept);
+    return ORC_OK;
+}
+
+static int llb_positions(const double *X, const double *Y, int64_t m, int64_t n_out, int64_t *out)
+{
+    int64_t B = n_out - 2;
+    double *L = (double *)malloc(sizeof(double) * (size_t)m);
+    int64_t *pred = (int64_t *)malloc(sizeof(int64_t) * (size_t)m);
+    if (!L || !pred) {
+        free(L);
+        free(pred);
+        return ORC_ENOMEM;
+    }
+    L[0] = 0.0;
+    int64_t p0 = 0, p1 = 1; /* the previous bucket: point 0 alone */
+    for (int64_t k = 0; k <= B; k++) {
+        int64_t s0, s1;
+        if (k < B) {
+            s0 = 1 + floor_frac(k, m - 2, B); /* R5 */
+            s1 = 1 + floor_frac(k + 1, m - 2, B);
+        } else {
+            s0 = m - 1;
+            s1 = m;
+        }
+        for (int64_t j = s0; j < s1; j++) {
+            double best = -1.0;
+            int64_t bi = p0;
+            for (int64_t i = p0; i < p1; i++) {
+                double dx = X[j] - X[i], dy = Y[j] - Y[i];
+                double t = L[i] + sqrt(dx * dx + dy * dy); /* R18 */
+                if (t > best) { /* lowest index on ties */
+                    best = t;
+                    bi = i;
+                }
+            }
+            L[j] = best;
+            pred[j] = bi;
+        }
+        p0 = s0;
+        p1 = s1;
+    }
+    int64_t j = m - 1;
+    for (int64_t k = n_out - 1; k >= 0; k--) {
+        out[k] = j;
+        j = k > 0 ? pred[j] : 0;
+    }
+    free(L);
+    free(pred);
+    return ORC_OK;
+}
+
+/* MinMax preselection (R1-R4) then VW, DP or LLB on P (alg 1, 2, 3). */
+int oracle_minmax_simplify(int alg, int xk, const int64_t *x, const float *y, int64_t n, int64_t n_out, int32_t r_ps,
+                           int64_t *out)
+{
+    if (alg < 1 || alg > 3 || n < 1 || n_out < 3 || r_ps < 2 || check_x(xk, x) != ORC_OK)
+        return ORC_EINVAL;
+    if (n <= n_out) {
+        for (int64_t i = 0; i < n; i++)
+            if (!is_finite_f32(y[i]))
+                return ORC_ENOTFINITE;
+        for (int64_t i = 0; i < n; i++)
+            out[i] = i;
+        return ORC_OK;
+    }
+    int64_t nb = (int64_t)(((__int128)n_out * r_ps) / 2);
+    int64_t *P = (int64_t *)malloc(sizeof(int64_t) * (size_t)(2 * nb + 2));
+    if (!P)
+        return ORC_ENOMEM;
+    int64_t m = 0;
+    int rc = oracle_minmax(y, n, n_out, r_ps, P, &m);
+    double *X = (double *)malloc(sizeof(double) * (size_t)(m > 0 ? m : 1));
+    double *Y = (double *)malloc(sizeof(double) * (size_t)(m > 0 ? m : 1));
+    int64_t *pos = (int64_t *)malloc(sizeof(int64_t) * (size_t)n_out);
+    if (rc == ORC_OK && (!X || !Y || !pos))
+        rc = ORC_ENOMEM;
+    if (rc == ORC_OK) {
+        for (int64_t i = 0; i < m; i++) {
+            X[i] = (double)((xk == XK_INT64) ? x[P[i]] : P[i]);
+            Y[i] = (double)y[P[i]];
+        }
+        if (alg == 1)
+            rc = vw_positions(X, Y, m, n_out, pos);
+        else if (alg == 2)
+            rc = dp_positions(X, Y, m, n_out, pos);
+        else
+            rc = llb_positions(X, Y, m, n_out, pos);
+        if (rc == ORC_OK)
+            for (int64_t i = 0; i < n_out; i++)
+                out[i] = P[pos[i]];
+    }
+    free(P);
+    free(X);
+    free(Y);
+    free(pos);
+    return rc;
+}
+
+/* The simplifier alone over m > n_out given points (test hook). */
+int oracle_simplify_points(int alg, const double *X, const double *Y, int64_t m, int64_t n_out, int64_t *out)
+{
+    if (alg < 1 || alg > 3 || n_out < 3 || m <= n_out)
+        return ORC_EINVAL;
+    if (alg == 1)
+        return vw_positions(X, Y, m, n_out, out);
+    if (alg == 2)
+        return dp_positions(X, Y, m, n_out, out);
+    return llb_positions(X, Y, m, n_out, out);
 }
 
 /* ------------------------------------------------------------------------ */

@@ -63,6 +63,9 @@ def _bind(path: str):
     lib.oracle_minmaxlttb_typed.argtypes = [ctypes.c_int, _vp, ctypes.c_int, _vp, ctypes.c_int64, ctypes.c_int64,
                                             ctypes.c_int32, _i64p]
     lib.oracle_exact_sum_f64.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.c_int64, _f64p]
+    lib.oracle_minmax_simplify.argtypes = [ctypes.c_int, ctypes.c_int, _i64p, _f32p, ctypes.c_int64, ctypes.c_int64,
+                                           ctypes.c_int32, _i64p]
+    lib.oracle_simplify_points.argtypes = [ctypes.c_int, _f64p, _f64p, ctypes.c_int64, ctypes.c_int64, _i64p]
     lib.oracle_lttb_means_typed.argtypes = [ctypes.c_int, _vp, ctypes.c_int, _vp, ctypes.c_int64, ctypes.c_int64,
                                             _f64p, _f64p]
     lib.oracle_minmax_xbins.argtypes = [_i64p, _f32p, ctypes.c_int64, ctypes.c_int64, ctypes.c_int32, _i64p, _i64p]
@@ -72,7 +75,8 @@ def _bind(path: str):
     for f in ("oracle_minmax", "oracle_lttb", "oracle_minmaxlttb", "oracle_lttb_means",
               "oracle_exact_sum_f32", "oracle_exact_sum_i64", "oracle_m4", "oracle_everynth",
               "oracle_minmax_xbins", "oracle_minmaxlttb_xbins", "oracle_minmax_typed", "oracle_minmaxlttb_typed",
-              "oracle_exact_sum_f64", "oracle_lttb_means_typed"):
+              "oracle_exact_sum_f64", "oracle_lttb_means_typed", "oracle_minmax_simplify",
+              "oracle_simplify_points"):
         getattr(lib, f).restype = ctypes.c_int
     return lib
 
@@ -112,6 +116,8 @@ def compile_variant(src_text: str, out_path: str):
     v.minmax_typed = lambda y, n_out, r_ps: minmax_typed(y, n_out, r_ps, _lib_override=lib)
     v.minmaxlttb_typed = lambda y, n_out, r_ps, x=None: minmaxlttb_typed(y, n_out, r_ps, x, _lib_override=lib)
     v.exact_sum_f64 = lambda a: exact_sum_f64(a, _lib_override=lib)
+    v.minmax_simplify = lambda alg, y, n_out, r_ps, x=None: minmax_simplify(alg, y, n_out, r_ps, x, _lib_override=lib)
+    v.simplify_points = lambda alg, X, Y, n_out: simplify_points(alg, X, Y, n_out, _lib_override=lib)
     v.lttb_means_typed = lambda y, n_out, x=None: lttb_means_typed(y, n_out, x, _lib_override=lib)
     v.minmax_xbins = lambda y, x, n_out, r_ps: minmax_xbins(y, x, n_out, r_ps, _lib_override=lib)
     v.minmaxlttb_xbins = lambda y, x, n_out, r_ps: minmaxlttb_xbins(y, x, n_out, r_ps, _lib_override=lib)
@@ -223,6 +229,43 @@ def lttb_means_typed(y, n_out: int, x=None, _lib_override=None):
     if rc != 0:
         raise OracleError(rc, "lttb_means_typed")
     return MX, MY
+
+
+SIMPLIFIERS = {"vw": 1, "dp": 2, "llb": 3}
+
+
+def _alg(alg):
+    a = SIMPLIFIERS.get(alg, alg)
+    if a not in (1, 2, 3):
+        raise ValueError(f"unknown simplifier {alg!r}")
+    return a
+
+
+def minmax_simplify(alg, y, n_out: int, r_ps: int, x=None, _lib_override=None) -> np.ndarray:
+    """MinMax preselection, then Visvalingam-Whyatt ("vw"), Douglas-Peucker
+    ("dp") or Longest-Line-Bucket ("llb") on the preselected points (R16-R18)."""
+    y = _f32(y)
+    n = y.shape[0]
+    xk, xarr, xp = _x(x)
+    assert xarr is None or xarr.shape[0] == n
+    out = np.empty(max(min(n, n_out), 1), dtype=np.int64)
+    rc = (_lib_override or _load()).oracle_minmax_simplify(_alg(alg), xk, xp, _ptr(y, _f32p), n, n_out, r_ps,
+                                                           out.ctypes.data_as(_i64p))
+    if rc != 0:
+        raise OracleError(rc, "minmax_simplify")
+    return out[: min(n, n_out)].copy()
+
+
+def simplify_points(alg, X, Y, n_out: int, _lib_override=None) -> np.ndarray:
+    """The simplifier alone over m > n_out binary64 points (positions)."""
+    X = np.ascontiguousarray(X, dtype=np.float64)
+    Y = np.ascontiguousarray(Y, dtype=np.float64)
+    out = np.empty(n_out, dtype=np.int64)
+    rc = (_lib_override or _load()).oracle_simplify_points(_alg(alg), X.ctypes.data_as(_f64p), Y.ctypes.data_as(_f64p),
+                                                           X.shape[0], n_out, out.ctypes.data_as(_i64p))
+    if rc != 0:
+        raise OracleError(rc, "simplify_points")
+    return out
 
 
 def exact_sum_f64(a, _lib_override=None) -> float:

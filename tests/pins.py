@@ -198,3 +198,68 @@ def means_by_fsum(v: np.ndarray, n_out: int) -> np.ndarray:
         g0, g1 = bk[k + 1] if k < n_out - 3 else (m - 1, m)
         out.append(math.fsum(float(t) for t in v[g0:g1]) / (g1 - g0))
     return np.array(out, dtype=np.float64)
+
+
+def vw_exact(xs, ys, n_out: int):
+    """Visvalingam-Whyatt with exact rational areas: the remaining points kept
+    as a list, the smallest doubled area removed (lowest index on ties)."""
+    X = [Fraction(v) for v in xs]
+    Y = [Fraction(v) for v in ys]
+    keep = list(range(len(X)))
+
+    def area(a, j, b):
+        return abs((X[a] - X[b]) * (Y[j] - Y[a]) - (X[a] - X[j]) * (Y[b] - Y[a]))
+
+    while len(keep) > n_out:
+        best = None
+        for t in range(1, len(keep) - 1):
+            A = area(keep[t - 1], keep[t], keep[t + 1])
+            if best is None or A < best[0]:
+                best = (A, t)
+        keep.pop(best[1])
+    return keep
+
+
+def dp_exact(xs, ys, n_out: int):
+    """Douglas-Peucker with a point budget, exact rational squared distances:
+    split the segment whose farthest point is farthest from its chord."""
+    X = [Fraction(v) for v in xs]
+    Y = [Fraction(v) for v in ys]
+    kept = [0, len(X) - 1]
+    while len(kept) < n_out:
+        best = None
+        for a, b in zip(kept, kept[1:]):
+            cand = None
+            for j in range(a + 1, b):
+                c = abs((X[b] - X[a]) * (Y[j] - Y[a]) - (X[j] - X[a]) * (Y[b] - Y[a]))
+                if cand is None or c > cand[0]:
+                    cand = (c, j)
+            if cand is None:
+                continue
+            key = cand[0] ** 2 / ((X[b] - X[a]) ** 2 + (Y[b] - Y[a]) ** 2)
+            if best is None or key > best[0]:
+                best = (key, cand[1])
+        kept = sorted(kept + [best[1]])
+    return kept
+
+
+def llb_brute(X, Y, n_out: int, digits: int = 60):
+    """Every path through the LTTB buckets (one point each, first and last
+    fixed) with its length summed in `digits`-digit decimal arithmetic.
+    Returns [(length, path), ...] sorted by decreasing length."""
+    import itertools
+    from decimal import Decimal, getcontext
+
+    getcontext().prec = digits
+    m = len(X)
+    buckets = [[0]] + [list(range(lo, hi)) for lo, hi in lttb_buckets(m, n_out)] + [[m - 1]]
+    D = [(Decimal(float(x)), Decimal(float(y))) for x, y in zip(X, Y)]
+    out = []
+    for path in itertools.product(*buckets):
+        t = Decimal(0)
+        for i, j in zip(path, path[1:]):
+            dx, dy = D[j][0] - D[i][0], D[j][1] - D[i][1]
+            t += (dx * dx + dy * dy).sqrt()
+        out.append((t, list(path)))
+    out.sort(key=lambda r: r[0], reverse=True)
+    return out

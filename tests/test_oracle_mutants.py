@@ -76,6 +76,14 @@ MUTANTS = {
                                 "MY[k] = 0.0;\n        for (int64_t q = g0; q < g1; q++)\n            MY[k] += Y[q];\n        MY[k] /= c;"),
     "f64_sum_high_part_dropped": ("        big_add_u32_shifted(dst, (uint32_t)(mant >> 32), shift + 32);\n", ""),
     "typed_i32_as_float": ("    return (double)((const int32_t *)y)[i];", "    return (double)(float)((const int32_t *)y)[i];"),
+    "vw_tie_highest": ("if (alive[i] && (sel < 0 || area[i] < area[sel]))", "if (alive[i] && (sel < 0 || area[i] <= area[sel]))"),
+    "vw_neighbour_not_updated": ("        if (b < m - 1)\n            area[b] = vw_area(X, Y, a, b, next[b]);\n", ""),
+    "vw_area_wrong_vertex": ("return fabs((X[a] - X[b]) * (Y[j] - Y[a]) - (X[a] - X[j]) * (Y[b] - Y[a])); /* R16 */",
+                             "return fabs((X[a] - X[b]) * (Y[j] - Y[a]) - (X[a] - X[j]) * (Y[j] - Y[a])); /* R16 */"),
+    "dp_key_not_normalised": ("*key = best * best / (dx * dx + dy * dy);", "*key = best * best;"),
+    "dp_farthest_tie_highest": ("if (c > best) { /* lowest index on ties (R17) */", "if (c >= best) { /* lowest index on ties (R17) */"),
+    "llb_squared_length": ("double t = L[i] + sqrt(dx * dx + dy * dy); /* R18 */", "double t = L[i] + (dx * dx + dy * dy); /* R18 */"),
+    "llb_no_accumulation": ("double t = L[i] + sqrt(dx * dx + dy * dy); /* R18 */", "double t = sqrt(dx * dx + dy * dy); /* R18 */"),
     "everynth_ceil": ("        out[k] = floor_frac(k, n, n_out);", "        out[k] = (k * n + n_out - 1) / n_out;"),
 }
 
@@ -160,6 +168,32 @@ def _passes_pins(v) -> bool:
             yi = synth.to_numpy(synth.int_series(300, seed, scale=1e9))
             if not np.array_equal(v.lttb_means_typed(yi, 11)[1], pins.means_by_fsum(yi.astype(np.float64), 11)):
                 return False
+        # other simplifiers: collinear closed forms, exact-rational VW / DP, LLB brute force
+        Xc = np.arange(50, dtype=np.float64)
+        if list(v.simplify_points("vw", Xc, 3.0 * Xc - 7.0, 10)) != [0] + list(range(41, 50)):
+            return False
+        if list(v.simplify_points("dp", Xc, 3.0 * Xc - 7.0, 10)) != list(range(9)) + [49]:
+            return False
+        for seed in range(12):
+            rng = np.random.default_rng(300 + seed)
+            m = int(rng.integers(6, 40))
+            X = np.cumsum(rng.integers(1, 9, size=m)).astype(np.float64)
+            Y = rng.integers(-40, 41, size=m).astype(np.float64)
+            if seed % 3 == 0:
+                Y = np.round(Y / 8)
+            k = int(rng.integers(3, m))
+            if list(v.simplify_points("vw", X, Y, k)) != pins.vw_exact(X.tolist(), Y.tolist(), k):
+                return False
+            if list(v.simplify_points("dp", X, Y, k)) != pins.dp_exact(X.tolist(), Y.tolist(), k):
+                return False
+            k = 3 + seed % 3
+            mm = k + 1 + seed % (2 * (k - 2))
+            Xl = np.cumsum(rng.random(mm) + 0.1)
+            Yl = rng.standard_normal(mm) * 3
+            paths = pins.llb_brute(Xl, Yl, k)
+            if len(paths) > 1 and float(paths[0][0] - paths[1][0]) > 1e-9 * 100:
+                if list(v.simplify_points("llb", Xl, Yl, k)) != paths[0][1]:
+                    return False
         # exact-regime LTTB vs rationals
         for seed in range(30):
             rng = np.random.default_rng(seed)
