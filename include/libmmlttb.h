@@ -139,6 +139,42 @@ size_t mmlttb_batched_workspace_size(const mmlttb_segment_t *segs_host, int64_t 
 int mmlttb_minmaxlttb_batched(int xk, const int64_t *x_base, const float *y_base, const mmlttb_segment_t *segs_host,
                               int64_t n_segs, int64_t *out_idx_base, void *ws, size_t ws_bytes, void *stream);
 
+/* Line simplifiers that can follow the MinMax preselection in place of LTTB
+ * (section 4 names them as future work, without definitions). */
+typedef enum {
+    MMLTTB_SIMPLIFY_VW = 1, /* Visvalingam-Whyatt */
+    MMLTTB_SIMPLIFY_DP = 2, /* Douglas-Peucker with a point budget */
+    MMLTTB_SIMPLIFY_LLB = 3 /* Longest-Line-Bucket */
+} mmlttb_simplify_t;
+
+/* Workspace bytes for mmlttb_minmax_simplify; independent of n. Returns 0 on
+ * invalid arguments. */
+size_t mmlttb_simplify_workspace_size(int64_t n, int64_t n_out, int32_t r_ps);
+
+/* MinMax preselection (as mmlttb_minmaxlttb, r_ps >= 2), then, in place of
+ * LTTB, another simplifier on the m preselected points with X = x (or the
+ * index) rounded to binary64 and Y = y widened to binary64:
+ *  VW:  while more than n_out points remain, remove the interior point whose
+ *       doubled triangle area with its current neighbours a < j < b,
+ *       |(Xa-Xb)*(Yj-Ya) - (Xa-Xj)*(Yb-Ya)|, is smallest (lowest index on
+ *       ties), then recompute its neighbours' areas.
+ *  DP:  start from the first and last point; a segment's farthest point
+ *       maximises c = |(Xb-Xa)*(Yj-Ya) - (Xj-Xa)*(Yb-Ya)| (lowest index on
+ *       ties) and its key is c*c / ((Xb-Xa)^2 + (Yb-Ya)^2), one rounding per
+ *       operation (NaN, from a zero-length chord, counts as -1); while fewer
+ *       than n_out points are kept, keep the farthest point of the segment
+ *       with the largest key (lowest point on ties).
+ *  LLB: LTTB's buckets; one point per bucket, first and last fixed,
+ *       maximising the polyline's total length, sum of
+ *       sqrt((Xj-Xi)^2 + (Yj-Yi)^2) accumulated bucket by bucket; each point
+ *       keeps the lowest-index predecessor giving the largest total.
+ * out_idx receives exactly min(n, n_out) ascending series indices; n <= n_out
+ * returns 0..n-1. Extra limit: 2*floor(n_out*r_ps/2) + 2 <= 2^31-1. One
+ * wave runs the simplifier; its per-point state (32 bytes per point) lives in
+ * LDS when it fits, else in the workspace. */
+int mmlttb_minmax_simplify(int alg, int xk, const int64_t *x, const float *y, int64_t n, int64_t n_out, int32_t r_ps,
+                           int64_t *out_idx, void *ws, size_t ws_bytes, void *stream);
+
 /* Workspace bytes for mmlttb_minmax_typed and mmlttb_minmaxlttb_typed;
  * independent of n. Returns 0 on invalid arguments. */
 size_t mmlttb_typed_workspace_size(int64_t n, int64_t n_out, int32_t r_ps);

@@ -16,6 +16,8 @@ from .ops import (  # noqa: F401
     segment_table,
     lttb_workspace_size,
     minmax,
+    minmax_simplify,
+    simplify_workspace_size,
     minmax_typed,
     minmaxlttb_typed,
     typed_workspace_size,

@@ -30,6 +30,8 @@ EXPORTS = (
     "mmlttb_minmaxlttb",
     "mmlttb_batched_workspace_size",
     "mmlttb_minmaxlttb_batched",
+    "mmlttb_simplify_workspace_size",
+    "mmlttb_minmax_simplify",
     "mmlttb_typed_workspace_size",
     "mmlttb_minmax_typed",
     "mmlttb_minmaxlttb_typed",
@@ -93,6 +95,10 @@ def load(path: str = LIB_PATH):
     lib.mmlttb_batched_workspace_size.restype = ctypes.c_size_t
     lib.mmlttb_minmaxlttb_batched.argtypes = [ctypes.c_int, _vp, _vp, ctypes.POINTER(Segment), _i64, _vp, _vp,
                                               ctypes.c_size_t, _vp]
+    lib.mmlttb_simplify_workspace_size.argtypes = [_i64, _i64, _i32]
+    lib.mmlttb_simplify_workspace_size.restype = ctypes.c_size_t
+    lib.mmlttb_minmax_simplify.argtypes = [ctypes.c_int, ctypes.c_int, _vp, _vp, _i64, _i64, _i32, _vp, _vp,
+                                           ctypes.c_size_t, _vp]
     lib.mmlttb_typed_workspace_size.argtypes = [_i64, _i64, _i32]
     lib.mmlttb_typed_workspace_size.restype = ctypes.c_size_t
     lib.mmlttb_minmax_typed.argtypes = [ctypes.c_int, _vp, _i64, _i64, _i32, _vp, _vp, _vp, ctypes.c_size_t, _vp]
@@ -115,6 +121,7 @@ def load(path: str = LIB_PATH):
     lib.mmlttb_profile_read.argtypes = [ctypes.c_char_p, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_i64)]
     for f in ("mmlttb_minmax", "mmlttb_lttb", "mmlttb_minmaxlttb", "mmlttb_minmaxlttb_batched", "mmlttb_m4",
               "mmlttb_minmax_xbins", "mmlttb_minmaxlttb_xbins", "mmlttb_minmax_typed", "mmlttb_minmaxlttb_typed",
+              "mmlttb_minmax_simplify",
               "mmlttb_everynth", "mmlttb_set_graph_cache", "mmlttb_graph_cache_stats", "mmlttb_set_tuning",
               "mmlttb_get_tuning", "mmlttb_profile_enable", "mmlttb_profile_reset", "mmlttb_profile_read"):
         getattr(lib, f).restype = ctypes.c_int

@@ -894,6 +894,74 @@ int mmlttb_minmaxlttb(int xk, const int64_t *x, const float *y, int64_t n, int64
     return ok();
 }
 
+size_t mmlttb_simplify_workspace_size(int64_t n, int64_t n_out, int32_t r_ps)
+{
+    (void)n;
+    if (n_out < 3 || n_out > kMaxI32 || r_ps < 2 || n_out * (int64_t)r_ps / 2 > kMaxI32)
+        return 0;
+    const int64_t cap = 2 * (n_out * (int64_t)r_ps / 2) + 2;
+    return mm_layout(n_out, r_ps).total + align_up((size_t)simplify_scratch_bytes(cap));
+}
+
+int mmlttb_minmax_simplify(int alg, int xk, const int64_t *x, const float *y, int64_t n, int64_t n_out, int32_t r_ps,
+                           int64_t *out_idx, void *ws, size_t ws_bytes, void *stream)
+{
+    if (alg != MMLTTB_SIMPLIFY_VW && alg != MMLTTB_SIMPLIFY_DP && alg != MMLTTB_SIMPLIFY_LLB)
+        return fail(MMLTTB_EINVAL, "alg must be MMLTTB_SIMPLIFY_VW, _DP or _LLB, got %d", alg);
+    int rc = check_series(xk, x, y, n, n_out);
+    if (rc)
+        return rc;
+    if ((rc = check_rps(n, n_out, r_ps)))
+        return rc;
+    const int64_t nb = n_out * (int64_t)r_ps / 2;
+    const int64_t cap = 2 * nb + 2;
+    if (cap > kMaxI32)
+        return fail(MMLTTB_EINVAL, "2*floor(n_out*r_ps/2)+2 must be <= 2^31-1 for the simplifiers");
+    if (!out_idx)
+        return fail(MMLTTB_EINVAL, "out_idx must not be NULL");
+    hipStream_t s = (hipStream_t)stream;
+    if (n <= n_out) {
+        MMLTTB_LAUNCH("iota", s, launch_iota(out_idx, n, nullptr, s));
+        return ok();
+    }
+    const MmLayout L = mm_layout(n_out, r_ps);
+    const size_t need = mmlttb_simplify_workspace_size(n, n_out, r_ps);
+    if (!ws)
+        return fail(MMLTTB_EINVAL, "ws must not be NULL");
+    if (ws_bytes < need)
+        return fail(MMLTTB_ENOMEM, "workspace of %zu bytes is below the %zu required", ws_bytes, need);
+    int64_t *P = at<int64_t>(ws, L.P), *XP = at<int64_t>(ws, L.XP), *m = at<int64_t>(ws, L.m);
+    float *YP = at<float>(ws, L.YP);
+    if ((rc = enqueue_preselect(x, y, n, n_out, r_ps, ws, L, P, XP, YP, m, s)))
+        return rc;
+    // per-point state in LDS when it fits the device's per-workgroup limit
+    const int64_t bytes = simplify_scratch_bytes(cap);
+    int dev = 0, lds_max = 0, lds_optin = 0;
+    if (hipGetDevice(&dev) == hipSuccess) {
+        if (hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+            lds_max = 0;
+        if (hipDeviceGetAttribute(&lds_optin, hipDeviceAttributeSharedMemPerBlockOptin, dev) != hipSuccess)
+            lds_optin = 0;
+        lds_max = lds_optin > lds_max ? lds_optin : lds_max;
+    }
+    bool in_lds = bytes <= (int64_t)lds_max;
+    if (in_lds && bytes > 65536 && simplify_allow_lds((size_t)bytes) != hipSuccess)
+        in_lds = false;
+    SimplifyArgs a;
+    a.XP = XP;
+    a.YP = YP;
+    a.m_ptr = m;
+    a.Pmap = P;
+    a.out = out_idx;
+    a.n_out = n_out;
+    a.cap = cap;
+    a.scratch = static_cast<unsigned char *>(ws) + L.total;
+    a.in_lds = in_lds ? 1 : 0;
+    static const char *names[] = {"", "simplify_vw", "simplify_dp", "simplify_llb"};
+    MMLTTB_LAUNCH(names[alg], s, launch_simplify(alg, a, s));
+    return ok();
+}
+
 size_t mmlttb_typed_workspace_size(int64_t n, int64_t n_out, int32_t r_ps)
 {
     (void)n;

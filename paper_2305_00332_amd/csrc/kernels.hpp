@@ -140,6 +140,23 @@ hipError_t launch_m4_bin_reduce(const float *y, const MinMaxGeom &g, int unroll,
 hipError_t launch_m4_compact(const unsigned long long *keys, const Split &bins, int64_t *out, int64_t *count,
                              hipStream_t s);
 hipError_t launch_everynth(int64_t n, int64_t n_out, int64_t *out, hipStream_t s);
+// Other simplifiers on the preselected points (1 VW, 2 DP, 3 LLB). Per-point
+// state lives in LDS (in_lds) or at `scratch` in the workspace.
+struct SimplifyArgs {
+    const int64_t *XP;    // raw x (or the index) of the m points
+    const float *YP;      // y of the points
+    const int64_t *m_ptr; // device point count
+    const int64_t *Pmap;  // series index of each point
+    int64_t *out;         // n_out series indices
+    int64_t n_out;
+    int64_t cap;          // bound on m the state is sized for
+    unsigned char *scratch;
+    int in_lds;
+};
+int64_t simplify_scratch_bytes(int64_t cap);
+hipError_t launch_simplify(int alg, const SimplifyArgs &a, hipStream_t s);
+hipError_t simplify_allow_lds(size_t bytes);
+
 // Value types of the typed path (y) and the per-work-item MinMax partial.
 enum { kYF32 = 0, kYF64 = 1, kYI32 = 2 };
 struct TypedPartial {

@@ -83,6 +83,27 @@ def _typed_series(y, x):
     return _XKIND[x.dtype], _YKIND[y.dtype]
 
 
+SIMPLIFIERS = {"vw": 1, "dp": 2, "llb": 3}
+
+
+def simplify_workspace_size(n: int, n_out: int, r_ps: int) -> int:
+    return int(_lib.load().mmlttb_simplify_workspace_size(n, n_out, r_ps))
+
+
+def minmax_simplify(alg: str, y, n_out: int, r_ps: int, x=None, out=None, ws=None):
+    """MinMax preselection, then Visvalingam-Whyatt ("vw"), Douglas-Peucker
+    ("dp") or Longest-Line-Bucket ("llb") on the preselected points."""
+    lib = _lib.load()
+    xk = _as_series(y, x)
+    n = y.numel()
+    code = SIMPLIFIERS.get(alg, alg)
+    out = out if out is not None else torch.empty(max(min(n, n_out), 1), dtype=torch.int64, device=y.device)
+    ws = _workspace(lib.mmlttb_simplify_workspace_size(n, n_out, r_ps), y.device, ws)
+    _lib.check(lib.mmlttb_minmax_simplify(code, xk, _lib.ptr(x), y.data_ptr(), n, n_out, r_ps, out.data_ptr(),
+                                          ws.data_ptr(), ws.numel(), _lib.stream_ptr()))
+    return out[: min(n, n_out)]
+
+
 def typed_workspace_size(n: int, n_out: int, r_ps: int) -> int:
     return int(_lib.load().mmlttb_typed_workspace_size(n, n_out, r_ps))
 
