@@ -87,6 +87,7 @@ def main():
     ap.add_argument("--skip-downsamplers", action="store_true")
     ap.add_argument("--skip-xbins", action="store_true")
     ap.add_argument("--skip-typed", action="store_true")
+    ap.add_argument("--skip-simplifiers", action="store_true")
     ap.add_argument("--batch-series", type=int, default=4096)
     ap.add_argument("--pool-series", type=int, default=512)
     ap.add_argument("--rates", type=str, default="100,500,1000,2000,5000")
@@ -124,6 +125,8 @@ def main():
         result["xbins"] = bench_xbins(args)
     if not args.skip_typed:
         result["typed"] = bench_typed(args)
+    if not args.skip_simplifiers:
+        result["simplifiers"] = bench_simplifiers(args)
     if not args.skip_comparator:
         result["comparator"] = bench_comparator(args)
     if not args.skip_batched:
@@ -447,6 +450,55 @@ def bench_typed(args, reps: int = 10):
         torch.cuda.empty_cache()
     res["workload"] = (f"one series, n={n}: float64 random walk with float64 second timestamps, and int32 counts "
                        f"with implicit x (seed={args.seed}); MinMaxLTTB n_out={n_out}, r_ps={r_ps}")
+    return res
+
+
+def bench_simplifiers(args, reps: int = 10):
+    """MinMax preselection followed by Visvalingam-Whyatt, Douglas-Peucker or
+    Longest-Line-Bucket instead of LTTB, on the headline series (n=1e9,
+    n_out and r_ps as the headline): call time, the simplifier kernel's time
+    (one wave on the preselected points), parity with the oracle."""
+    import numpy as np
+    import torch
+
+    import oracle
+    from paper_2305_00332_amd import autotune, ops, synth
+
+    autotune.apply("single")
+    n, n_out, r_ps = int(args.n), args.n_out, args.r_ps
+    dev = torch.device("cuda", 0)
+    log(f"simplifiers: generating y, n={n}")
+    y = synth.random_walk(n, args.seed, device=dev)
+    torch.cuda.synchronize()
+    y_np = None if args.no_cpu_baseline else y.cpu().numpy()
+    out = torch.empty(n_out, dtype=torch.int64, device=dev)
+    ws = torch.empty(ops.simplify_workspace_size(n, n_out, r_ps), dtype=torch.uint8, device=dev)
+    res = {"workload": f"one series, n={n}, float32 random walk (seed={args.seed}), implicit x; n_out={n_out}, "
+                       f"r_ps={r_ps} ({2 * (n_out * r_ps // 2) + 2} preselected points)"}
+    for alg in ("vw", "dp", "llb"):
+        ops.minmax_simplify(alg, y, n_out, r_ps, out=out, ws=ws)
+        torch.cuda.synchronize()
+        ops.profile_enable(True)
+        ops.profile_reset()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            ops.minmax_simplify(alg, y, n_out, r_ps, out=out, ws=ws)
+        torch.cuda.synchronize()
+        wall = (time.perf_counter() - t0) * 1e3 / reps
+        ops.profile_enable(False)
+        tot, c = ops.profile_read(f"simplify_{alg}")
+        mm, cm = ops.profile_read("minmax_bin_reduce")
+        entry = {"call_ms": round(wall, 5), "gpts_per_s": round(n / (wall * 1e-3) / 1e9, 3),
+                 "simplify_kernel_ms": round(tot / max(c, 1), 5), "stream_kernel_ms": round(mm / max(cm, 1), 5)}
+        if y_np is not None:
+            c0 = time.perf_counter()
+            want = oracle.minmax_simplify(alg, y_np, n_out, r_ps)
+            entry["oracle_s"] = round(time.perf_counter() - c0, 3)
+            entry["parity_vs_oracle"] = bool(np.array_equal(out.cpu().numpy(), want))
+        log(f"  {alg}: {entry}")
+        res[alg] = entry
+    del y, y_np, ws
+    torch.cuda.empty_cache()
     return res
 
 

@@ -955,6 +955,7 @@ int mmlttb_minmax_simplify(int alg, int xk, const int64_t *x, const float *y, in
     a.out = out_idx;
     a.n_out = n_out;
     a.cap = cap;
+    a.cap_bucket = (cap - 2 + (n_out - 2) - 1) / (n_out - 2); // ceil((m - 2) / B) for any m <= cap
     a.scratch = static_cast<unsigned char *>(ws) + L.total;
     a.in_lds = in_lds ? 1 : 0;
     static const char *names[] = {"", "simplify_vw", "simplify_dp", "simplify_llb"};

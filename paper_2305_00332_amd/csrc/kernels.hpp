@@ -150,6 +150,7 @@ struct SimplifyArgs {
     int64_t *out;         // n_out series indices
     int64_t n_out;
     int64_t cap;          // bound on m the state is sized for
+    int64_t cap_bucket;   // bound on the points of one LTTB bucket (LLB)
     unsigned char *scratch;
     int in_lds;
 };

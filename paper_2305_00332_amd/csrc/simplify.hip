@@ -22,27 +22,58 @@ struct TNode {
     int64_t i;
 };
 
-// Levels l = 1..T above m leaves; level T holds at most 64 nodes.
+// One DPP step of a lexicographic (key, index) minimum.
+template <int CTRL>
+__device__ inline void argmin_step(uint64_t &k, int32_t &i)
+{
+    const uint32_t lo = (uint32_t)dpp_i32<CTRL>((int)(uint32_t)k);
+    const uint32_t hi = (uint32_t)dpp_i32<CTRL>((int)(uint32_t)(k >> 32));
+    const int32_t oi = dpp_i32<CTRL>(i);
+    const uint64_t ok = ((uint64_t)hi << 32) | lo;
+    if (ok < k || (ok == k && oi < i)) {
+        k = ok;
+        i = oi;
+    }
+}
+
+// Levels l = 1..T above m leaves; level T holds at most 64 nodes. Every
+// loop over levels is unrolled to kMaxLevels so the level arrays stay in
+// registers (a runtime index would put them in private memory).
+constexpr int kMaxLevels = 6; // 64^6 leaves
 struct Tree {
     TNode *node;
-    int64_t off[8], cnt[8];
+    int64_t off[kMaxLevels + 1], cnt[kMaxLevels + 1];
     int T;
+    int64_t top_off, top_cnt; // level T (the leaves when T = 0)
 };
 
 __host__ __device__ inline int64_t tree_nodes(int64_t m, Tree *t)
 {
     int64_t c = m, total = 0;
     int T = 0;
-    if (t)
+    if (t) {
         t->cnt[0] = m;
-    while (c > 64) {
-        c = (c + 63) / 64;
-        ++T;
+        t->off[0] = 0;
+        t->top_off = 0;
+        t->top_cnt = m;
+    }
+#pragma unroll
+    for (int l = 1; l <= kMaxLevels; ++l) {
+        const bool more = c > 64;
+        const int64_t cn = more ? (c + 63) / 64 : c;
         if (t) {
-            t->off[T] = total;
-            t->cnt[T] = c;
+            t->off[l] = total;
+            t->cnt[l] = cn;
+            if (more) {
+                t->top_off = total;
+                t->top_cnt = cn;
+            }
         }
-        total += c;
+        if (more) {
+            total += cn;
+            T = l;
+        }
+        c = cn;
     }
     if (t)
         t->T = T;
@@ -77,16 +108,28 @@ __device__ inline SimplifyState carve_state(unsigned char *base, int64_t cap, in
     return s;
 }
 
-__device__ inline void wave_argmin(uint64_t k, int64_t i, uint64_t &ko, int64_t &io)
+// Smallest key over the wave, lowest index on ties; every lane active. DPP
+// within rows of 16 lanes, then the four row results through readlane.
+__device__ inline void wave_argmin(uint64_t k, int64_t i64, uint64_t &ko, int64_t &io)
 {
-    uint64_t km = k;
+    int32_t i = i64 > INT32_MAX ? INT32_MAX : (int32_t)i64;
+    argmin_step<0xB1>(k, i);
+    argmin_step<0x4E>(k, i);
+    argmin_step<0x141>(k, i);
+    argmin_step<0x140>(k, i);
+    uint64_t bk = (uint64_t)readlane_i64((int64_t)k, 0);
+    int32_t bi = __builtin_amdgcn_readlane(i, 0);
 #pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) {
-        const uint64_t o = __shfl_xor(km, off);
-        km = o < km ? o : km;
+    for (int r = 16; r < kWave; r += 16) {
+        const uint64_t rk = (uint64_t)readlane_i64((int64_t)k, r);
+        const int32_t ri = __builtin_amdgcn_readlane(i, r);
+        if (rk < bk || (rk == bk && ri < bi)) {
+            bk = rk;
+            bi = ri;
+        }
     }
-    io = wave_min_i64(k == km ? i : INT64_MAX);
-    ko = km;
+    ko = bk;
+    io = bi == INT32_MAX ? INT64_MAX : bi;
 }
 
 // Node (l, g) from its 64 children.
@@ -115,19 +158,24 @@ __device__ inline void tree_node(Tree &t, int l, int64_t g, LeafKey lk, int lane
 template <class LeafKey>
 __device__ inline void tree_build(Tree &t, LeafKey lk, int lane)
 {
-    for (int l = 1; l <= t.T; ++l)
+#pragma unroll
+    for (int l = 1; l <= kMaxLevels; ++l) {
+        if (l > t.T)
+            break;
         for (int64_t g = 0; g < t.cnt[l]; ++g)
             tree_node(t, l, g, lk, lane);
+    }
 }
 
 // The path from `leaf` to the top after its key (or a sibling's) changed.
 template <class LeafKey>
 __device__ inline void tree_fix(Tree &t, int64_t leaf, LeafKey lk, int lane)
 {
-    int64_t g = leaf;
-    for (int l = 1; l <= t.T; ++l) {
-        g >>= 6;
-        tree_node(t, l, g, lk, lane);
+#pragma unroll
+    for (int l = 1; l <= kMaxLevels; ++l) {
+        if (l > t.T)
+            break;
+        tree_node(t, l, leaf >> (6 * l), lk, lane);
     }
 }
 
@@ -137,12 +185,12 @@ __device__ inline int64_t tree_root(const Tree &t, LeafKey lk, int lane, uint64_
 {
     uint64_t k = ~0ull;
     int64_t i = INT64_MAX;
-    if (lane < t.cnt[t.T]) {
+    if (lane < t.top_cnt) {
         if (t.T == 0) {
             k = lk(lane);
             i = lane;
         } else {
-            const TNode n = t.node[t.off[t.T] + lane];
+            const TNode n = t.node[t.top_off + lane];
             k = n.k;
             i = n.i;
         }
@@ -194,9 +242,12 @@ __device__ inline void simplify_emit(const SimplifyArgs &a, int64_t m, Keep keep
     }
 }
 
+// kLds: the state is the dynamic LDS array (native LDS addressing); else the
+// workspace.
+template <bool kLds>
 __device__ inline unsigned char *state_base(const SimplifyArgs &a, unsigned char *lds)
 {
-    return a.in_lds ? lds : a.scratch;
+    return kLds ? lds : a.scratch;
 }
 
 // ------------------------------------------------------------------ VW
@@ -206,12 +257,13 @@ __device__ inline double vw_area(const SimplifyState &s, int64_t p, int64_t j, i
     return fabs((s.X[p] - s.X[q]) * (s.Y[j] - s.Y[p]) - (s.X[p] - s.X[j]) * (s.Y[q] - s.Y[p]));
 }
 
+template <bool kLds>
 __global__ __launch_bounds__(64) void k_simplify_vw(SimplifyArgs a)
 {
     extern __shared__ __align__(16) unsigned char lds[];
     const int lane = threadIdx.x;
     const int64_t m = *a.m_ptr;
-    SimplifyState s = carve_state(state_base(a, lds), a.cap, m);
+    SimplifyState s = carve_state(state_base<kLds>(a, lds), a.cap, m);
     if (!simplify_begin(a, s, m, lane))
         return;
     // A = previous alive point (-2 once removed), N = next alive point, F = area
@@ -280,12 +332,13 @@ __device__ inline void dp_scan(SimplifyState &s, int64_t p, int64_t q, int lane)
     __syncthreads();
 }
 
+template <bool kLds>
 __global__ __launch_bounds__(64) void k_simplify_dp(SimplifyArgs a)
 {
     extern __shared__ __align__(16) unsigned char lds[];
     const int lane = threadIdx.x;
     const int64_t m = *a.m_ptr;
-    SimplifyState s = carve_state(state_base(a, lds), a.cap, m);
+    SimplifyState s = carve_state(state_base<kLds>(a, lds), a.cap, m);
     if (!simplify_begin(a, s, m, lane))
         return;
     // A[p] = farthest point of the segment starting at kept point p (-1: none
@@ -324,12 +377,13 @@ __global__ __launch_bounds__(64) void k_simplify_dp(SimplifyArgs a)
 
 // ------------------------------------------------------------------ LLB
 
+template <bool kLds>
 __global__ __launch_bounds__(64) void k_simplify_llb(SimplifyArgs a)
 {
     extern __shared__ __align__(16) unsigned char lds[];
     const int lane = threadIdx.x;
     const int64_t m = *a.m_ptr;
-    SimplifyState s = carve_state(state_base(a, lds), a.cap, m);
+    SimplifyState s = carve_state(state_base<kLds>(a, lds), a.cap, m);
     if (!simplify_begin(a, s, m, lane))
         return;
     // F = longest total length ending at the point, A = its predecessor
@@ -339,9 +393,50 @@ __global__ __launch_bounds__(64) void k_simplify_llb(SimplifyArgs a)
         s.F[0] = 0.0;
     __syncthreads();
     int64_t p0 = 0, p1 = 1;
+    if (a.cap_bucket <= kWave) {
+        // every bucket fits the wave: lane l holds point l of the previous
+        // bucket (x, y, longest length) in registers and reads the others'
+        // through readlane
+        double px = s.X[0], py = s.Y[0], pf = 0.0;
+        SplitWalker w;
+        w.init(bk, 0);
+        for (int64_t k = 0; k <= B; ++k) {
+            const int64_t s0 = k < B ? 1 + w.lo : m - 1;
+            const int64_t s1 = k < B ? 1 + w.next_lo(bk) : m;
+            if (k < B)
+                w.advance(bk);
+            const int64_t j = s0 + lane;
+            const bool mine = j < s1;
+            const double xj = mine ? s.X[j] : 0.0, yj = mine ? s.Y[j] : 0.0;
+            double best = -1.0;
+            int32_t bi = 0;
+            const int np = (int)(p1 - p0);
+            for (int q = 0; q < np; ++q) {
+                const double xi = readlane_f64(px, q), yi = readlane_f64(py, q), fi = readlane_f64(pf, q);
+                const double dx = xj - xi, dy = yj - yi;
+                const double t = fi + sqrt(dx * dx + dy * dy);
+                if (t > best) { // lowest index on ties
+                    best = t;
+                    bi = q;
+                }
+            }
+            if (mine)
+                s.A[j] = (int32_t)(p0 + bi);
+            px = xj;
+            py = yj;
+            pf = best;
+            p0 = s0;
+            p1 = s1;
+        }
+        __syncthreads();
+    } else {
+    SplitWalker w;
+    w.init(bk, 0);
     for (int64_t k = 0; k <= B; ++k) {
-        const int64_t s0 = k < B ? 1 + split_lo(bk, k) : m - 1;
-        const int64_t s1 = k < B ? 1 + split_lo(bk, k + 1) : m;
+        const int64_t s0 = k < B ? 1 + w.lo : m - 1;
+        const int64_t s1 = k < B ? 1 + w.next_lo(bk) : m;
+        if (k < B)
+            w.advance(bk);
         for (int64_t j = s0 + lane; j < s1; j += kWave) {
             double best = -1.0;
             int64_t bi = p0;
@@ -360,6 +455,7 @@ __global__ __launch_bounds__(64) void k_simplify_llb(SimplifyArgs a)
         p0 = s0;
         p1 = s1;
     }
+    }
     if (lane == 0) {
         int64_t j = m - 1;
         for (int64_t k = a.n_out - 1; k >= 0; --k) {
@@ -376,15 +472,24 @@ int64_t simplify_scratch_bytes(int64_t cap) { return simplify_state_bytes(cap); 
 hipError_t launch_simplify(int alg, const SimplifyArgs &a, hipStream_t s)
 {
     const size_t lds = a.in_lds ? (size_t)simplify_state_bytes(a.cap) : 0;
-    switch (alg) {
-    case 1:
-        hipLaunchKernelGGL(k_simplify_vw, dim3(1), dim3(kWave), lds, s, a);
-        break;
+    switch (alg * 2 + (a.in_lds ? 1 : 0)) {
     case 2:
-        hipLaunchKernelGGL(k_simplify_dp, dim3(1), dim3(kWave), lds, s, a);
+        hipLaunchKernelGGL(k_simplify_vw<false>, dim3(1), dim3(kWave), 0, s, a);
+        break;
+    case 3:
+        hipLaunchKernelGGL(k_simplify_vw<true>, dim3(1), dim3(kWave), lds, s, a);
+        break;
+    case 4:
+        hipLaunchKernelGGL(k_simplify_dp<false>, dim3(1), dim3(kWave), 0, s, a);
+        break;
+    case 5:
+        hipLaunchKernelGGL(k_simplify_dp<true>, dim3(1), dim3(kWave), lds, s, a);
+        break;
+    case 6:
+        hipLaunchKernelGGL(k_simplify_llb<false>, dim3(1), dim3(kWave), 0, s, a);
         break;
     default:
-        hipLaunchKernelGGL(k_simplify_llb, dim3(1), dim3(kWave), lds, s, a);
+        hipLaunchKernelGGL(k_simplify_llb<true>, dim3(1), dim3(kWave), lds, s, a);
         break;
     }
     return hipGetLastError();
@@ -393,8 +498,8 @@ hipError_t launch_simplify(int alg, const SimplifyArgs &a, hipStream_t s)
 hipError_t simplify_allow_lds(size_t bytes)
 {
     hipError_t e = hipSuccess;
-    for (auto f : {reinterpret_cast<const void *>(k_simplify_vw), reinterpret_cast<const void *>(k_simplify_dp),
-                   reinterpret_cast<const void *>(k_simplify_llb)}) {
+    for (auto f : {reinterpret_cast<const void *>(k_simplify_vw<true>), reinterpret_cast<const void *>(k_simplify_dp<true>),
+                   reinterpret_cast<const void *>(k_simplify_llb<true>)}) {
         hipError_t r = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
         e = (e == hipSuccess) ? r : e;
     }
