@@ -108,6 +108,18 @@ __device__ inline SimplifyState carve_state(unsigned char *base, int64_t cap, in
     return s;
 }
 
+// Smallest int32 over the wave; every lane active.
+__device__ inline int32_t wave_min_i32(int32_t v)
+{
+    v = min(v, dpp_i32<0xB1>(v));
+    v = min(v, dpp_i32<0x4E>(v));
+    v = min(v, dpp_i32<0x141>(v));
+    v = min(v, dpp_i32<0x140>(v));
+    const int32_t a = min(__builtin_amdgcn_readlane(v, 0), __builtin_amdgcn_readlane(v, 16));
+    const int32_t b = min(__builtin_amdgcn_readlane(v, 32), __builtin_amdgcn_readlane(v, 48));
+    return min(a, b);
+}
+
 // Smallest key over the wave, lowest index on ties; every lane active. DPP
 // within rows of 16 lanes, then the four row results through readlane.
 __device__ inline void wave_argmin(uint64_t k, int64_t i64, uint64_t &ko, int64_t &io)
@@ -310,16 +322,16 @@ __device__ inline void dp_scan(SimplifyState &s, int64_t p, int64_t q, int lane)
 {
     const double xp = s.X[p], yp = s.Y[p], dx = s.X[q] - xp, dy = s.Y[q] - yp;
     double best = -1.0;
-    int64_t bj = INT64_MAX;
+    int32_t bj = INT32_MAX;
     for (int64_t j = p + 1 + lane; j < q; j += kWave) {
         const double c = fabs(dx * (s.Y[j] - yp) - (s.X[j] - xp) * dy);
         if (c > best) { // increasing j per lane: lowest index on ties
             best = c;
-            bj = j;
+            bj = (int32_t)j;
         }
     }
     const double wb = wave_max_f64(best);
-    const int64_t j = wave_min_i64(best == wb ? bj : INT64_MAX);
+    const int32_t j = wave_min_i32(best == wb ? bj : INT32_MAX);
     if (lane == 0) {
         if (wb > -1.0) {
             double key = wb * wb / (dx * dx + dy * dy);
