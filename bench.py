@@ -98,8 +98,8 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(the design notes describe how the work would shard).", file=sys.stderr)
+        print("bench.py measures one GPU only: libmmlttb has no multi-GPU path; splitting the bins (one "
+              "series) or the series (batches) across GPUs is a design, not code here.", file=sys.stderr)
         sys.exit(2)
 
     import torch

@@ -53,7 +53,7 @@ typedef enum {
     MMLTTB_EINVAL = -1,  /* bad argument; nothing enqueued */
     MMLTTB_ENOMEM = -2,  /* ws_bytes below the required workspace size */
     MMLTTB_EDEVICE = -3, /* a HIP call or kernel launch failed */
-    MMLTTB_ENOTSUP = -4  /* valid request this build does not handle */
+    MMLTTB_ENOTSUP = -4  /* valid request the library does not handle */
 } mmlttb_status_t;
 
 typedef enum {
