@@ -595,7 +595,7 @@ def bench_batched(args):
     torch.cuda.synchronize()
     ops.profile_enable(False)
     kern = {}
-    for k in ("batch_init", "batch_minmax_large", "batch_minmax_small", "batch_compact_means",
+    for k in ("batch_init", "batch_minmax_large", "batch_minmax_small", "batch_compact", "batch_means",
               "batch_chain", "batch_chain_seq", "batch_link_emit"):
         tot, cnt = ops.profile_read(k)
         if cnt:

@@ -587,6 +587,11 @@ int plan_batch(int xk, const mmlttb_segment_t *in, int64_t n_segs, BatchPlan &pl
     h.n_small_tiles = tiles;
     h.n_chain_units = cw;
     h.max_stage_cap = max_stage;
+    int64_t max_B = 0;
+    for (const BatchSeg &g : plan.segs)
+        if (g.mode != kSegIdentity && g.B > max_B)
+            max_B = g.B;
+    h.max_B = max_B;
     size_t off = 0;
     auto take = [&](size_t bytes) {
         size_t o = off;
@@ -647,6 +652,7 @@ int enqueue_batch(const BatchPlan &plan, int xk, const int64_t *x_base, const fl
     b.n_large_items = h.n_large_items;
     b.n_small_tiles = h.n_small_tiles;
     b.n_chain_units = h.n_chain_units;
+    b.max_B = h.max_B;
     b.stage_cap_max = (int)(h.max_stage_cap > 0 ? h.max_stage_cap : kSegLen);
     if (h.n_large_items > 0) {
         MMLTTB_LAUNCH("batch_init", s, launch_batch_init(b, s));
@@ -655,7 +661,8 @@ int enqueue_batch(const BatchPlan &plan, int xk, const int64_t *x_base, const fl
     if (h.n_small_tiles > 0) {
         MMLTTB_LAUNCH("batch_minmax_small", s, launch_batch_small(b, tuning().tile, s));
     }
-    MMLTTB_LAUNCH("batch_compact_means", s, launch_batch_compact_means(b, s));
+    MMLTTB_LAUNCH("batch_compact", s, launch_batch_compact(b, s));
+    MMLTTB_LAUNCH("batch_means", s, launch_batch_means(b, s));
     MMLTTB_LAUNCH("batch_chain", s, launch_batch_chain(b, s));
     if (plan.any_seq) {
         MMLTTB_LAUNCH("batch_chain_seq", s, launch_batch_chain_seq(b, s));

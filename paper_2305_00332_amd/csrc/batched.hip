@@ -191,10 +191,9 @@ __global__ __launch_bounds__(kTileThreads) void k_batch_small(BatchPtrs b)
 
 // One workgroup per series: compaction, then the next-bucket means over P.
 // Identity series (n <= n_out) write their output here.
-__global__ __launch_bounds__(1024) void k_batch_compact_means(BatchPtrs b)
+__global__ __launch_bounds__(1024) void k_batch_compact(BatchPtrs b)
 {
     __shared__ int wave_tot[17];
-    __shared__ int64_t s_m;
     const int tid = threadIdx.x;
     for (int64_t s = blockIdx.x; s < b.n_segs; s += gridDim.x) {
         const BatchSeg &g = b.segs[s];
@@ -220,17 +219,25 @@ __global__ __launch_bounds__(1024) void k_batch_compact_means(BatchPtrs b)
         } else {
             compact_keys(b.keys + 2 * g.key0, g.bins, n, x, y, P, XP, YP, b.m + s, wave_tot);
         }
-        __threadfence_block();
-        __syncthreads();
-        if (tid == 0)
-            s_m = b.m[s];
-        __syncthreads();
-        const int64_t m = s_m;
-        const Split bk = make_split(m - 2, g.B);
-        for (int64_t k = tid; k < g.B; k += blockDim.x)
-            bucket_mean_one(XP, YP, bk, m, k, b.MX[g.b0 + k], b.MY[g.b0 + k]);
         __syncthreads();
     }
+}
+
+// Next-bucket means over P: series blockIdx.x, buckets blockIdx.y * 256 + t
+// (+ gridDim.y * 256 ...), one thread per bucket. A kernel of its own so the
+// register-heavy exact sums do not limit the compaction's occupancy.
+__global__ __launch_bounds__(256) void k_batch_means(BatchPtrs b)
+{
+    const int64_t s = blockIdx.x;
+    const BatchSeg &g = b.segs[s];
+    if (g.mode == kSegIdentity)
+        return;
+    const int64_t m = b.m[s];
+    const Split bk = make_split(m - 2, g.B);
+    const int64_t *XP = b.XP + g.p0;
+    const float *YP = b.YP + g.p0;
+    for (int64_t k = (int64_t)blockIdx.y * blockDim.x + threadIdx.x; k < g.B; k += (int64_t)gridDim.y * blockDim.x)
+        bucket_mean_one(XP, YP, bk, m, k, b.MX[g.b0 + k], b.MY[g.b0 + k]);
 }
 
 // Segmented chain, phase 1: one wave per (series, chain segment) walks the
@@ -383,9 +390,20 @@ hipError_t launch_batch_small(const BatchPtrs &b, int tile, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_batch_compact_means(const BatchPtrs &b, hipStream_t s)
+hipError_t launch_batch_compact(const BatchPtrs &b, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_batch_compact_means, dim3(cap_grid(b.n_segs, 4096)), dim3(1024), 0, s, b);
+    hipLaunchKernelGGL(k_batch_compact, dim3(cap_grid(b.n_segs, 4096)), dim3(1024), 0, s, b);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_means(const BatchPtrs &b, hipStream_t s)
+{
+    if (b.max_B <= 0)
+        return hipSuccess;
+    if (b.n_segs > 0x7fffffff)
+        return hipErrorInvalidConfiguration;
+    const dim3 grid((unsigned)b.n_segs, cap_grid((b.max_B + 255) / 256, 65535));
+    hipLaunchKernelGGL(k_batch_means, grid, dim3(256), 0, s, b);
     return hipGetLastError();
 }
 

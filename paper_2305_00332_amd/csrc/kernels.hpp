@@ -90,6 +90,7 @@ struct BatchHeader {
     int64_t n_keys;
     int64_t n_large_items, n_small_tiles, n_chain_units;
     int64_t max_stage_cap;
+    int64_t max_B; // most interior LTTB buckets of any series
     int64_t off_segs, off_keys, off_P, off_XP, off_YP, off_m, off_MX, off_MY, off_path, off_finals, off_start;
     int32_t own_large[kOwnerTable + 1], own_small[kOwnerTable + 1], own_chain[kOwnerTable + 1];
 };
@@ -109,13 +110,15 @@ struct BatchPtrs {
     double *MX, *MY;
     uint8_t *path, *finals, *start;
     int64_t n_keys, n_large_items, n_small_tiles, n_chain_units;
+    int64_t max_B;
     int stage_cap_max;
 };
 
 hipError_t launch_batch_init(const BatchPtrs &b, hipStream_t s);
 hipError_t launch_batch_large(const BatchPtrs &b, int unroll, hipStream_t s);
 hipError_t launch_batch_small(const BatchPtrs &b, int tile, hipStream_t s);
-hipError_t launch_batch_compact_means(const BatchPtrs &b, hipStream_t s);
+hipError_t launch_batch_compact(const BatchPtrs &b, hipStream_t s);
+hipError_t launch_batch_means(const BatchPtrs &b, hipStream_t s);
 hipError_t launch_batch_chain(const BatchPtrs &b, hipStream_t s);
 hipError_t launch_batch_link_emit(const BatchPtrs &b, hipStream_t s);
 hipError_t launch_batch_chain_seq(const BatchPtrs &b, hipStream_t s);

@@ -22,6 +22,14 @@ __device__ inline unsigned long long pack_max_key(float v, int64_t off)
 
 __device__ inline int64_t min_key_offset(unsigned long long k) { return (int64_t)(uint32_t)(k & 0xffffffffull); }
 
+// The value a key holds (inverse of f32_order_key; -0.0 comes back as +0.0,
+// which no sum or area can tell apart).
+__device__ inline float key_value(unsigned long long k)
+{
+    const uint32_t o = (uint32_t)(k >> 32);
+    return __uint_as_float((o & 0x80000000u) ? (o ^ 0x80000000u) : ~o);
+}
+
 __device__ inline int64_t max_key_offset(unsigned long long k)
 {
     return (int64_t)(0xffffffffu - (uint32_t)(k & 0xffffffffull));
@@ -175,8 +183,9 @@ __device__ inline int block_exclusive_scan(int c, int *wave_tot, int &total)
 // Decode the bin keys into the sorted distinct preselection P (section 3: the
 // first and last points join the per-bin extrema). Bins are disjoint and in
 // index order, so emitting each bin's pair in index order yields P sorted.
-// Called by a whole workgroup of 1024 threads. Optionally gathers XP (raw x,
-// or the index for implicit x) and YP at the same time. wave_tot: 17 ints of LDS.
+// Called by a whole workgroup of 1024 threads. Optionally writes XP (raw x,
+// gathered, or the index for implicit x) and YP (decoded from the keys, so y
+// is not read again) at the same time. wave_tot: 17 ints of LDS.
 __device__ inline void compact_keys(const unsigned long long *__restrict__ keys, const Split &bins, int64_t n,
                                     const int64_t *__restrict__ x, const float *__restrict__ y,
                                     int64_t *__restrict__ P, int64_t *__restrict__ XP, float *__restrict__ YP,
@@ -196,12 +205,17 @@ __device__ inline void compact_keys(const unsigned long long *__restrict__ keys,
         const int64_t b = base + tid;
         int c = 0;
         int64_t i0 = 0, i1 = 0;
+        float v0 = 0.0f, v1 = 0.0f;
         if (b < nb) {
             const int64_t blo = 1 + split_lo(bins, b);
-            const int64_t imin = blo + min_key_offset(keys[2 * b]);
-            const int64_t imax = blo + max_key_offset(keys[2 * b + 1]);
-            i0 = imin < imax ? imin : imax;
-            i1 = imin < imax ? imax : imin;
+            const unsigned long long kmin = keys[2 * b], kmax = keys[2 * b + 1];
+            const int64_t imin = blo + min_key_offset(kmin);
+            const int64_t imax = blo + max_key_offset(kmax);
+            const bool lo_min = imin < imax;
+            i0 = lo_min ? imin : imax;
+            i1 = lo_min ? imax : imin;
+            v0 = key_value(lo_min ? kmin : kmax);
+            v1 = key_value(lo_min ? kmax : kmin);
             c = (imin == imax) ? 1 : 2;
         }
         int total;
@@ -210,14 +224,14 @@ __device__ inline void compact_keys(const unsigned long long *__restrict__ keys,
             P[off] = i0;
             if (XP) {
                 XP[off] = x ? x[i0] : i0;
-                YP[off] = y[i0];
+                YP[off] = v0;
             }
         }
         if (c == 2) {
             P[off + 1] = i1;
             if (XP) {
                 XP[off + 1] = x ? x[i1] : i1;
-                YP[off + 1] = y[i1];
+                YP[off + 1] = v1;
             }
         }
         running += total;

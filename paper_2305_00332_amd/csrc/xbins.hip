@@ -133,14 +133,19 @@ __global__ __launch_bounds__(1024) void k_xbin_compact(const unsigned long long 
         const int64_t b = base + tid;
         int c = 0;
         int64_t i0 = 0, i1 = 0;
+        float v0 = 0.0f, v1 = 0.0f;
         if (b < nb) {
             const int64_t bs = bounds[b], be = bounds[b + 1];
             if (be > bs) {
-                const int64_t imin = bs + min_key_offset(keys[2 * b]);
-                const int64_t imax = bs + max_key_offset(keys[2 * b + 1]);
+                const unsigned long long kmin = keys[2 * b], kmax = keys[2 * b + 1];
+                const int64_t imin = bs + min_key_offset(kmin);
+                const int64_t imax = bs + max_key_offset(kmax);
                 if (imin < be && imax < be) { // always, for increasing x
-                    i0 = imin < imax ? imin : imax;
-                    i1 = imin < imax ? imax : imin;
+                    const bool lo_min = imin < imax;
+                    i0 = lo_min ? imin : imax;
+                    i1 = lo_min ? imax : imin;
+                    v0 = key_value(lo_min ? kmin : kmax); // y from the key, not a second read
+                    v1 = key_value(lo_min ? kmax : kmin);
                     c = (imin == imax) ? 1 : 2;
                 }
             }
@@ -151,14 +156,14 @@ __global__ __launch_bounds__(1024) void k_xbin_compact(const unsigned long long 
             P[off] = i0;
             if (XP) {
                 XP[off] = x[i0];
-                YP[off] = y[i0];
+                YP[off] = v0;
             }
         }
         if (c == 2) {
             P[off + 1] = i1;
             if (XP) {
                 XP[off + 1] = x[i1];
-                YP[off + 1] = y[i1];
+                YP[off + 1] = v1;
             }
         }
         running += total;
