@@ -548,7 +548,7 @@ int plan_batch(int xk, const mmlttb_segment_t *in, int64_t n_segs, BatchPlan &pl
         if (g.mode == kSegMinMax) {
             g.bins = make_split(q.n - 2, nb);
             const int64_t maxbin = g.bins.q + (g.bins.r ? 1 : 0);
-            if (maxbin <= tn.tile / 4) {
+            if (maxbin <= tn.tile / 4 && nb < ((int64_t)1 << 26)) {
                 int64_t G = 256;
                 while (G * maxbin > tn.tile)
                     G >>= 1;

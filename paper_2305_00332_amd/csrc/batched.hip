@@ -90,102 +90,179 @@ __global__ __launch_bounds__(256) void k_batch_large(BatchPtrs b)
     }
 }
 
+// floor(t / d) for 0 <= t < 2^52 and d >= 1, given inv = RN(1/d): the
+// binary64 product is within one of the quotient, and one integer step
+// corrects it (cheaper than a 64-bit integer division on the GPU).
+__device__ inline int64_t div_near(int64_t t, int64_t d, double inv)
+{
+    int64_t q = (int64_t)((double)t * inv);
+    const int64_t r = t - q * d;
+    q += (r < 0) ? -1 : (r >= d ? 1 : 0);
+    return q;
+}
+
+// Packed-key min / max over a power-of-two group of tpb <= 64 lanes (aligned
+// groups; every lane of the wave takes part). The DPP steps pair lanes within
+// quads, half-rows and rows; the last two cross rows.
+template <int CTRL>
+__device__ inline unsigned long long dpp_u64(unsigned long long v)
+{
+    const int lo = dpp_i32<CTRL>((int)(uint32_t)v);
+    const int hi = dpp_i32<CTRL>((int)(uint32_t)(v >> 32));
+    return ((unsigned long long)(uint32_t)hi << 32) | (uint32_t)lo;
+}
+
+template <int CTRL>
+__device__ inline void group_step(unsigned long long &kmin, unsigned long long &kmax)
+{
+    const unsigned long long a = dpp_u64<CTRL>(kmin), c = dpp_u64<CTRL>(kmax);
+    kmin = a < kmin ? a : kmin;
+    kmax = c > kmax ? c : kmax;
+}
+
+__device__ inline void group_minmax(int tpb, unsigned long long &kmin, unsigned long long &kmax)
+{
+    if (tpb >= 2)
+        group_step<0xB1>(kmin, kmax);
+    if (tpb >= 4)
+        group_step<0x4E>(kmin, kmax);
+    if (tpb >= 8)
+        group_step<0x141>(kmin, kmax);
+    if (tpb >= 16)
+        group_step<0x140>(kmin, kmax);
+    for (int off = 16; off < tpb; off <<= 1) {
+        const unsigned long long a = __shfl_xor(kmin, off), c = __shfl_xor(kmax, off);
+        kmin = a < kmin ? a : kmin;
+        kmax = c > kmax ? c : kmax;
+    }
+}
+
+// Reduce tile[q] for q = q0, q0 + step, ... < end (q0 < end) in increasing q:
+// value and lowest position of the minimum and of the maximum.
+__device__ inline void strided_minmax(const float *tile, int q0, int end, int step, float &vmin, int &imin,
+                                      float &vmax, int &imax)
+{
+    vmin = vmax = tile[q0];
+    imin = imax = q0;
+    int q = q0 + step;
+    for (; q + 3 * step < end; q += 4 * step) { // four independent LDS reads per wait
+        const float v0 = tile[q], v1 = tile[q + step], v2 = tile[q + 2 * step], v3 = tile[q + 3 * step];
+        const float v[4] = {v0, v1, v2, v3};
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            if (v[u] < vmin) {
+                vmin = v[u];
+                imin = q + u * step;
+            }
+            if (v[u] > vmax) {
+                vmax = v[u];
+                imax = q + u * step;
+            }
+        }
+    }
+    for (; q < end; q += step) {
+        const float v = tile[q];
+        if (v < vmin) {
+            vmin = v;
+            imin = q;
+        }
+        if (v > vmax) {
+            vmax = v;
+            imax = q;
+        }
+    }
+}
+
+static_assert(kTileThreads == 256, "k_batch_small derives lanes per bin from 2^8 threads");
+
 template <int kTilePoints>
 __global__ __launch_bounds__(kTileThreads) void k_batch_small(BatchPtrs b)
 {
     __shared__ float tile[kTilePoints];
+    __shared__ int32_t bstart[kTileThreads + 1]; // bin starts, relative to the tile's first point
     const int tid = threadIdx.x;
     const int64_t t = blockIdx.x;
     const int64_t total = b.n_small_tiles;
     if (t >= total)
         return;
-    const float kInf = __int_as_float(0x7f800000);
-    {
-        const int64_t s = find_owner(b.segs, b.hdr->own_small, total, t, [](const BatchSeg &g) { return g.ti0; });
-        const BatchSeg &g = b.segs[s];
-        const int G = g.tile_bins;
-        const int tpb = kTileThreads / G; // lanes per bin: power of two <= 64
-        const int64_t nb = g.bins.parts;
-        const int64_t bb0 = (t - g.ti0) * G;
-        const int64_t bb1 = (bb0 + G < nb) ? bb0 + G : nb;
-        const int64_t lo = 1 + split_lo(g.bins, bb0), hi = 1 + split_lo(g.bins, bb1);
-        const float *__restrict__ y = b.y_base + g.offset;
-        // Stage [lo, hi): 16-byte loads of the aligned body, all issued before
-        // any use, plus at most 3 head and 3 tail points.
-        const uint64_t addr = (uint64_t)(uintptr_t)(y + lo);
-        int64_t head = (int64_t)(((16u - (unsigned)(addr & 15u)) & 15u) >> 2);
-        head = head < hi - lo ? head : hi - lo;
-        const int64_t body = lo + head;
-        const int64_t nvec = (hi - body) >> 2;
-        const int64_t tail0 = body + 4 * nvec;
-        const f32x4 *__restrict__ v4 = reinterpret_cast<const f32x4 *>(y + body);
-        constexpr int kVecPerThread = kTilePoints / 4 / kTileThreads;
-        f32x4 d[kVecPerThread];
+    const int64_t s = find_owner(b.segs, b.hdr->own_small, total, t, [](const BatchSeg &g) { return g.ti0; });
+    const BatchSeg &g = b.segs[s];
+    const int G = g.tile_bins;        // power of two, 4..256
+    const int lg = 8 - __builtin_ctz((unsigned)G); // log2 of the lanes per bin (kTileThreads = 2^8)
+    const int tpb = 1 << lg;          // lanes per bin: power of two <= 64
+    const int64_t nb = g.bins.parts, bq = g.bins.q, br = g.bins.r;
+    const int64_t bb0 = (t - g.ti0) * G;
+    const int nbt = (int)((bb0 + G < nb) ? G : nb - bb0); // bins in this tile
+    // Bin bb0 + i starts at split_lo(bb0) + i q + floor((rem0 + i r) / nb), with
+    // rem0 = bb0 r mod nb; the planner routes only nb < 2^26 here, so every
+    // numerator is below 2^52.
+    const double inv = 1.0 / (double)nb;
+    const int64_t t0 = bb0 * br;
+    const int64_t f0 = div_near(t0, nb, inv);
+    const int64_t rem0 = t0 - f0 * nb;
+    const int64_t lo = 1 + bb0 * bq + f0;
+    const int64_t hi = lo + (int64_t)nbt * bq + div_near(rem0 + (int64_t)nbt * br, nb, inv);
+    const float *__restrict__ y = b.y_base + g.offset;
+    // Stage [lo, hi): 16-byte loads of the aligned body, all issued before any
+    // use, plus at most 3 head and 3 tail points.
+    const uint64_t addr = (uint64_t)(uintptr_t)(y + lo);
+    int64_t head = (int64_t)(((16u - (unsigned)(addr & 15u)) & 15u) >> 2);
+    head = head < hi - lo ? head : hi - lo;
+    const int64_t body = lo + head;
+    const int64_t nvec = (hi - body) >> 2;
+    const int64_t tail0 = body + 4 * nvec;
+    const f32x4 *__restrict__ v4 = reinterpret_cast<const f32x4 *>(y + body);
+    constexpr int kVecPerThread = kTilePoints / 4 / kTileThreads;
+    f32x4 d[kVecPerThread];
 #pragma unroll
-        for (int u = 0; u < kVecPerThread; ++u) {
-            const int64_t q = tid + (int64_t)u * kTileThreads;
-            if (q < nvec)
-                d[u] = __builtin_nontemporal_load(v4 + q);
-        }
-        float hv = 0.0f;
-        int64_t hq = -1;
-        if (tid < head)
-            hq = lo + tid;
-        else if (tid >= 4 && tid < 4 + (hi - tail0))
-            hq = tail0 + (tid - 4);
-        if (hq >= 0)
-            hv = y[hq];
+    for (int u = 0; u < kVecPerThread; ++u) {
+        const int64_t q = tid + (int64_t)u * kTileThreads;
+        if (q < nvec)
+            d[u] = __builtin_nontemporal_load(v4 + q);
+    }
+    float hv = 0.0f;
+    int64_t hq = -1;
+    if (tid < head)
+        hq = lo + tid;
+    else if (tid >= 4 && tid < 4 + (hi - tail0))
+        hq = tail0 + (tid - 4);
+    if (hq >= 0)
+        hv = y[hq];
+    for (int i = tid; i <= nbt; i += kTileThreads)
+        bstart[i] = (int32_t)((int64_t)i * bq + div_near(rem0 + (int64_t)i * br, nb, inv));
 #pragma unroll
-        for (int u = 0; u < kVecPerThread; ++u) {
-            const int64_t q = tid + (int64_t)u * kTileThreads;
-            if (q < nvec) {
-                float *dst = tile + (body - lo) + 4 * q;
-                dst[0] = d[u].x;
-                dst[1] = d[u].y;
-                dst[2] = d[u].z;
-                dst[3] = d[u].w;
-            }
+    for (int u = 0; u < kVecPerThread; ++u) {
+        const int64_t q = tid + (int64_t)u * kTileThreads;
+        if (q < nvec) {
+            float *dst = tile + (body - lo) + 4 * q;
+            dst[0] = d[u].x;
+            dst[1] = d[u].y;
+            dst[2] = d[u].z;
+            dst[3] = d[u].w;
         }
-        if (hq >= 0)
-            tile[hq - lo] = hv;
-        __syncthreads();
-        const int64_t bin = bb0 + tid / tpb;
-        const int sub = tid % tpb;
-        float vmin = kInf, vmax = -kInf;
-        int64_t imin = INT64_MAX, imax = INT64_MAX, bl = 0;
-        if (bin < bb1) {
-            bl = 1 + split_lo(g.bins, bin);
-            const int64_t bh = 1 + split_lo(g.bins, bin + 1);
-            for (int64_t q = bl + sub; q < bh; q += tpb) { // increasing index: strict keeps the lowest
-                const float v = tile[q - lo];
-                if (v < vmin) {
-                    vmin = v;
-                    imin = q;
-                }
-                if (v > vmax) {
-                    vmax = v;
-                    imax = q;
-                }
-            }
+    }
+    if (hq >= 0)
+        tile[hq - lo] = hv;
+    __syncthreads();
+    const int gi = tid >> lg, sub = tid & (tpb - 1);
+    unsigned long long kmin = ~0ull, kmax = 0ull; // identities: lanes with no point never win
+    int bs = 0;
+    if (gi < nbt) {
+        bs = bstart[gi];
+        const int be = bstart[gi + 1];
+        if (bs + sub < be) {
+            float vmin, vmax;
+            int imin, imax;
+            strided_minmax(tile, bs + sub, be, tpb, vmin, imin, vmax, imax);
+            kmin = pack_min_key(vmin, imin - bs);
+            kmax = pack_max_key(vmax, imax - bs);
         }
-        for (int off = tpb >> 1; off >= 1; off >>= 1) {
-            const float ov = __shfl_xor(vmin, off);
-            const int64_t oi = __shfl_xor(imin, off);
-            if (ov < vmin || (ov == vmin && oi < imin)) {
-                vmin = ov;
-                imin = oi;
-            }
-            const float ow = __shfl_xor(vmax, off);
-            const int64_t oj = __shfl_xor(imax, off);
-            if (ow > vmax || (ow == vmax && oj < imax)) {
-                vmax = ow;
-                imax = oj;
-            }
-        }
-        if (sub == 0 && bin < bb1) {
-            b.keys[2 * (g.key0 + bin)] = pack_min_key(vmin, imin - bl);
-            b.keys[2 * (g.key0 + bin) + 1] = pack_max_key(vmax, imax - bl);
-        }
+    }
+    group_minmax(tpb, kmin, kmax);
+    if (sub == 0 && gi < nbt) {
+        unsigned long long *k = b.keys + 2 * (g.key0 + bb0 + gi);
+        k[0] = kmin;
+        k[1] = kmax;
     }
 }
 
@@ -241,7 +318,7 @@ __global__ __launch_bounds__(256) void k_batch_means(BatchPtrs b)
 }
 
 // Segmented chain, phase 1: one wave per (series, chain segment) walks the
-// segment from every start point (seg_walk).
+// segment from every start point (seg_walk: transition tables, then lookups).
 __global__ __launch_bounds__(kSegStarts) void k_batch_chain(BatchPtrs b)
 {
     extern __shared__ double lds[];
@@ -253,7 +330,8 @@ __global__ __launch_bounds__(kSegStarts) void k_batch_chain(BatchPtrs b)
     const BatchSeg &g = b.segs[s];
     const int64_t m = b.m[s];
     const Split bk = make_split(m - 2, g.B);
-    seg_walk(b.XP + g.p0, b.YP + g.p0, bk, b.MX + g.b0, b.MY + g.b0, u - g.cw0, g.stage_cap, lds,
+    seg_walk(b.XP + g.p0, b.YP + g.p0, bk, b.MX + g.b0, b.MY + g.b0, u - g.cw0, g.stage_cap,
+             reinterpret_cast<unsigned char *>(lds),
              b.path + (size_t)g.c0 * kSegStarts * kSegLen, b.finals + (size_t)g.c0 * kSegStarts);
 }
 
@@ -411,7 +489,7 @@ hipError_t launch_batch_chain(const BatchPtrs &b, hipStream_t s)
 {
     if (b.n_chain_units == 0)
         return hipSuccess;
-    const size_t lds = (size_t)(2 * b.stage_cap_max + 2 * kSegLen) * sizeof(double);
+    const size_t lds = seg_walk_lds_bytes(b.stage_cap_max);
     hipLaunchKernelGGL(k_batch_chain, dim3(cap_grid(b.n_chain_units, 0x7fffffff)), dim3(kSegStarts), lds, s, b);
     return hipGetLastError();
 }

@@ -44,24 +44,34 @@ __device__ inline void bucket_mean_one(const int64_t *__restrict__ XP, const flo
 // Phase 1 of the segmented chain for chain segment s (buckets
 // [s*kSegLen, min(B, (s+1)*kSegLen))), one wave of kSegStarts lanes.
 // A segment's walk depends only on its start point, which lies in the bucket
-// just before the segment (point 0 for the first segment). Lane l walks the
-// segment from start candidate l, with the segment's points and means staged
-// in LDS (`lds`: 2*stage_cap + 2*kSegLen doubles), and records each pick's
-// offset inside its bucket in path[(s*kSegStarts + l)*kSegLen + t] and the
-// last one in finals[s*kSegStarts + l]. Every walk evaluates the same binary64
-// area on the same operands as the sequential pass, so the walk from the true
-// start repeats the sequential picks exactly.
+// just before the segment (point 0 for the first segment). The pick in bucket
+// k depends only on the pick in bucket k-1, so the wave first tabulates, for
+// every point of the segment's buckets but the last, its pick in the next
+// bucket (one lane per point, all in parallel), and for every start its pick
+// in the segment's first bucket; lane l then follows the table from start l.
+// Each table entry evaluates the same binary64 area on the same operands as
+// the sequential pass, so the walk from the true start repeats its picks
+// exactly. Points, means, bucket starts and tables live in LDS
+// (seg_walk_lds_bytes(stage_cap)). Lane l records each pick's offset inside
+// its bucket in path[(s*kSegStarts + l)*kSegLen + t] and the last one in
+// finals[s*kSegStarts + l].
 template <class XT, class YT>
 __device__ inline void seg_walk(const XT *__restrict__ XP, const YT *__restrict__ YP, const Split &bk,
                                 const double *__restrict__ MX, const double *__restrict__ MY, int64_t s,
-                                int stage_cap, double *lds, uint8_t *__restrict__ path,
+                                int stage_cap, unsigned char *lds, uint8_t *__restrict__ path,
                                 uint8_t *__restrict__ finals)
 {
     const int lane = threadIdx.x;
     const int64_t B = bk.parts;
     const int64_t k0 = s * kSegLen, k1 = (k0 + kSegLen < B) ? k0 + kSegLen : B;
-    const int64_t p0 = 1 + split_lo(bk, k0), p1 = 1 + split_lo(bk, k1);
-    double *sx = lds, *sy = lds + stage_cap, *smx = lds + 2 * stage_cap, *smy = smx + kSegLen;
+    const int nk = (int)(k1 - k0);
+    SplitWalker w;
+    w.init(bk, k0);
+    const int64_t p0 = 1 + w.lo;
+    const int64_t p1 = 1 + split_lo(bk, k1);
+    double *sx = reinterpret_cast<double *>(lds), *sy = sx + stage_cap, *smx = sy + stage_cap, *smy = smx + kSegLen;
+    int32_t *sb = reinterpret_cast<int32_t *>(smy + kSegLen); // bucket starts relative to p0, nk + 1 of them
+    uint8_t *T = reinterpret_cast<uint8_t *>(sb + kSegLen + 1); // point -> offset of its pick in the next bucket
     for (int64_t p = p0 + lane; p < p1; p += kSegStarts) {
         sx[p - p0] = (double)(XP ? XP[p] : p);
         sy[p - p0] = (double)YP[p];
@@ -70,43 +80,73 @@ __device__ inline void seg_walk(const XT *__restrict__ XP, const YT *__restrict_
         smx[k - k0] = MX[k];
         smy[k - k0] = MY[k];
     }
-    __syncthreads();
-
+    if (lane == 0) {
+        SplitWalker v = w;
+        for (int i = 0; i <= nk; ++i) {
+            sb[i] = (int32_t)(1 + v.lo - p0);
+            v.advance(bk);
+        }
+    }
+    // start l: the l-th point of bucket k0 - 1 (the last one for lanes past
+    // its end), whose size is q, plus one when the step into k0 carried
     int64_t apos = 0;
     if (s > 0) {
-        const int64_t sa = 1 + split_lo(bk, k0 - 1);
-        const int64_t ca = p0 - sa; // points of the bucket before the segment (<= kSegStarts)
-        apos = sa + (lane < ca ? lane : ca - 1);
+        const int64_t ca = bk.q + (w.rem < bk.r ? 1 : 0);
+        apos = p0 - ca + (lane < ca ? lane : ca - 1);
     }
-    double ax = (double)(XP ? XP[apos] : apos);
-    double ay = (double)YP[apos];
-    SplitWalker w;
-    w.init(bk, k0);
-    uint8_t *mypath = path + ((size_t)s * kSegStarts + lane) * kSegLen;
-    int bo = 0;
-    for (int64_t k = k0; k < k1; ++k) {
-        const int64_t s0 = 1 + w.lo, s1 = 1 + w.next_lo(bk);
-        w.advance(bk);
-        const double mx = smx[k - k0], my = smy[k - k0];
-        // the bucket's first point stands unless an area beats -1 (areas are
-        // >= 0, or NaN when binary64 means overflow: NaN never wins)
-        double best = -1.0, bx = sx[s0 - p0], by = sy[s0 - p0];
-        bo = 0;
-        for (int64_t j = s0; j < s1; ++j) {
-            const double xj = sx[j - p0], yj = sy[j - p0];
-            const double ar = lttb_area2(ax, ay, xj, yj, mx, my);
-            if (ar > best) { // strict: lowest position wins ties
+    const double ax0 = (double)(XP ? XP[apos] : apos);
+    const double ay0 = (double)YP[apos];
+    __syncthreads();
+
+    // the bucket's first point stands unless an area beats -1 (areas are >= 0,
+    // or NaN when binary64 means overflow: NaN never wins); strict > keeps
+    // the lowest position on ties
+    auto pick = [&](double ax, double ay, int i) {
+        const int j0 = sb[i], j1 = sb[i + 1];
+        const double mx = smx[i], my = smy[i];
+        double best = -1.0;
+        int bo = 0;
+        for (int j = j0; j < j1; ++j) {
+            const double ar = lttb_area2(ax, ay, sx[j], sy[j], mx, my);
+            if (ar > best) {
                 best = ar;
-                bo = (int)(j - s0);
-                bx = xj;
-                by = yj;
+                bo = j - j0;
             }
         }
-        ax = bx;
-        ay = by;
-        mypath[k - k0] = (uint8_t)bo;
+        return bo;
+    };
+    const int first = pick(ax0, ay0, 0);
+    const int tab_end = sb[nk - 1]; // points of buckets 0 .. nk-2
+    for (int r = lane; r < tab_end; r += kSegStarts) {
+        int lo = 0, hi = nk - 1; // bucket of r: the last i with sb[i] <= r
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (sb[mid] <= r)
+                lo = mid;
+            else
+                hi = mid;
+        }
+        T[r] = (uint8_t)pick(sx[r], sy[r], lo + 1);
     }
-    finals[(size_t)s * kSegStarts + lane] = (uint8_t)bo;
+    __syncthreads();
+
+    uint32_t words[kSegLen / 4];
+#pragma unroll
+    for (int q = 0; q < kSegLen / 4; ++q)
+        words[q] = 0;
+    int o = first;
+    words[0] = (uint32_t)o;
+#pragma unroll
+    for (int i = 1; i < kSegLen; ++i) {
+        if (i < nk) {
+            o = T[sb[i - 1] + o];
+            words[i / 4] |= (uint32_t)o << (8 * (i % 4));
+        }
+    }
+    uint4 *dst = reinterpret_cast<uint4 *>(path + ((size_t)s * kSegStarts + lane) * kSegLen);
+    dst[0] = make_uint4(words[0], words[1], words[2], words[3]);
+    dst[1] = make_uint4(words[4], words[5], words[6], words[7]);
+    finals[(size_t)s * kSegStarts + lane] = (uint8_t)o;
 }
 
 // Phase 2: follow the true start through the segments. The start of segment

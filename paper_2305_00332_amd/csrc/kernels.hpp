@@ -28,6 +28,17 @@ constexpr int kSegLen = 32;
 constexpr int kSegStarts = 64;
 constexpr int kChaseWindow = 512;
 
+static_assert(kSegLen == 32 && kSegStarts <= 256, "segment paths are written as 32-byte rows of byte offsets");
+
+// LDS of one segment walk: x, y of up to stage_cap points and the kSegLen
+// means (binary64), kSegLen + 1 bucket starts, a byte per point (its pick in
+// the next bucket).
+inline size_t seg_walk_lds_bytes(int stage_cap)
+{
+    return (size_t)(2 * stage_cap + 2 * kSegLen) * sizeof(double) + (kSegLen + 1) * sizeof(int32_t) +
+           (size_t)stage_cap;
+}
+
 template <class XT, class YT>
 struct SegChainArgsT {
     const XT *XP;          // x of the points (NULL: x = position)

@@ -266,7 +266,8 @@ __global__ __launch_bounds__(kSegStarts) void k_lttb_chain_seg(Args a)
     extern __shared__ double lds[];
     const int64_t m = a.m_ptr ? *a.m_ptr : a.m_const;
     const Split bk = make_split(m - 2, a.B);
-    seg_walk(a.XP, a.YP, bk, a.MX, a.MY, (int64_t)blockIdx.x, a.stage_cap, lds, a.path, a.finals);
+    seg_walk(a.XP, a.YP, bk, a.MX, a.MY, (int64_t)blockIdx.x, a.stage_cap, reinterpret_cast<unsigned char *>(lds), a.path,
+             a.finals);
 }
 
 template <class Args>
@@ -406,7 +407,7 @@ static hipError_t launch_chain_seg_impl(const Args &a, const int64_t *Pmap, int6
 {
     if (a.S > 0x7fffffff)
         return hipErrorInvalidConfiguration;
-    const size_t lds = (size_t)(2 * a.stage_cap + 2 * kSegLen) * sizeof(double); // points and means of a segment
+    const size_t lds = seg_walk_lds_bytes(a.stage_cap);
     hipLaunchKernelGGL(k_lttb_chain_seg<Args>, dim3((unsigned)a.S), dim3(kSegStarts), lds, s, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess)

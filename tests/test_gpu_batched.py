@@ -143,3 +143,35 @@ def test_tuning_does_not_change_batched_results(tile, chunk, unroll):
         o, n, no, r = segs[i]
         want = oracle.minmaxlttb(y[o:o + n].cpu().numpy(), no, r, x[o:o + n].cpu().numpy())
         assert np.array_equal(g[outoff[i]: outoff[i] + min(n, no)], want)
+
+
+@pytest.mark.parametrize("tile", [2048, 4096, 8192])
+def test_small_tiles_every_lane_group_width(tile):
+    """Small-bin tiles with every bins-per-tile count (4..256, so 64..1 lanes
+    per bin), full and ragged bins, one-point bins; quantised values with
+    signed zeros so ties decide many picks (lowest index must win across lanes)."""
+    rng = np.random.default_rng(tile)
+    lengths, n_outs, r_pss = [], [], []
+    for g in (4, 8, 16, 32, 64, 128, 256):
+        s = tile // g
+        for extra in (0, 1):  # every bin s points; or bins of s - 1 and s points
+            nb = 200
+            lengths.append(nb * (s - extra) + (nb // 2 if extra else 0) + 2)
+            n_outs.append(100)
+            r_pss.append(4)
+    lengths += [202, 1002]  # one-point and five-point bins
+    n_outs += [100, 100]
+    r_pss += [4, 4]
+    lengths = np.array(lengths, dtype=np.int64)
+    total = int(lengths.sum()) + 3 * len(lengths)
+    offsets = np.cumsum(np.concatenate([[1], (lengths + 3)[:-1]]))  # misaligned starts
+    vals = np.round(rng.standard_normal(total) * 2) / 2
+    vals[rng.random(total) < 0.1] = -0.0
+    y = torch.from_numpy(vals.astype(np.float32)).cuda()
+    x = synth.irregular_x(total, tile, device="cuda")
+    old = ops.get_tuning()
+    try:
+        ops.set_tuning(tile=tile)
+        _check_batch(x, y, offsets, lengths, np.array(n_outs), np.array(r_pss))
+    finally:
+        ops.set_tuning(*old)
