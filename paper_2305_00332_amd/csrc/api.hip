@@ -557,9 +557,8 @@ int plan_batch(int xk, const mmlttb_segment_t *in, int64_t n_segs, BatchPlan &pl
                 g.tn = (nb + G - 1) / G;
                 tiles += g.tn;
             } else {
-                g.chunk = tn.chunk;
-                g.chunks_per_bin = (maxbin + g.chunk - 1) / g.chunk;
-                g.ln = nb * g.chunks_per_bin;
+                g.chunk = tn.chunk < kMaxStreamChunk ? tn.chunk : kMaxStreamChunk;
+                g.ln = (q.n - 2 + g.chunk - 1) / g.chunk;
                 large += g.ln;
             }
         }

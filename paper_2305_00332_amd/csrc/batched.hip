@@ -8,9 +8,9 @@
 // the series with a grid-stride.
 //
 //   init      keys to their identities (only when large-bin series exist)
-//   large     series whose bins hold > kSmallBinMax points: one wave per
-//             (bin, chunk) item, as in the single-series stream (16-byte
-//             loads, atomic key merge)
+//   large     series whose bins hold more than tile / 4 points: one wave per
+//             fixed-size chunk of the series, streaming across bin ends
+//             (16-byte loads, one atomic key merge per bin part)
 //   small     series with small bins: a workgroup stages a tile of whole bins
 //             (<= tile points) in LDS; a power-of-two lane group reduces each
 //             bin and stores its keys
@@ -71,23 +71,9 @@ __global__ __launch_bounds__(256) void k_batch_large(BatchPtrs b)
         return;
     const int64_t s = find_owner(b.segs, b.hdr->own_large, total, i, [](const BatchSeg &g) { return g.li0; });
     const BatchSeg &g = b.segs[s];
-    const int64_t li = i - g.li0;
-    const int64_t bb = li / g.chunks_per_bin;
-    const int64_t j = li - bb * g.chunks_per_bin;
-    const int64_t blo = 1 + split_lo(g.bins, bb);
-    const int64_t bhi = 1 + split_lo(g.bins, bb + 1);
-    const int64_t lo = blo + j * g.chunk;
-    if (lo >= bhi)
-        return;
-    const int64_t hi = (lo + g.chunk < bhi) ? lo + g.chunk : bhi;
-    unsigned long long *keys = b.keys + 2 * (g.key0 + bb);
-    float vmin, vmax;
-    int64_t imin, imax;
-    wave_reduce_range<U>(b.y_base + g.offset, lo, hi, lane, vmin, imin, vmax, imax);
-    if (lane == 0) {
-        atomicMin(&keys[0], pack_min_key(vmin, imin - blo));
-        atomicMax(&keys[1], pack_max_key(vmax, imax - blo));
-    }
+    const int64_t lo = 1 + (i - g.li0) * g.chunk;
+    const int64_t hi = (lo + g.chunk < g.n - 1) ? lo + g.chunk : g.n - 1;
+    wave_stream_bins<U>(b.y_base + g.offset, lo, hi, g.bins, b.keys + 2 * g.key0, lane);
 }
 
 // floor(t / d) for 0 <= t < 2^52 and d >= 1, given inv = RN(1/d): the
@@ -99,42 +85,6 @@ __device__ inline int64_t div_near(int64_t t, int64_t d, double inv)
     const int64_t r = t - q * d;
     q += (r < 0) ? -1 : (r >= d ? 1 : 0);
     return q;
-}
-
-// Packed-key min / max over a power-of-two group of tpb <= 64 lanes (aligned
-// groups; every lane of the wave takes part). The DPP steps pair lanes within
-// quads, half-rows and rows; the last two cross rows.
-template <int CTRL>
-__device__ inline unsigned long long dpp_u64(unsigned long long v)
-{
-    const int lo = dpp_i32<CTRL>((int)(uint32_t)v);
-    const int hi = dpp_i32<CTRL>((int)(uint32_t)(v >> 32));
-    return ((unsigned long long)(uint32_t)hi << 32) | (uint32_t)lo;
-}
-
-template <int CTRL>
-__device__ inline void group_step(unsigned long long &kmin, unsigned long long &kmax)
-{
-    const unsigned long long a = dpp_u64<CTRL>(kmin), c = dpp_u64<CTRL>(kmax);
-    kmin = a < kmin ? a : kmin;
-    kmax = c > kmax ? c : kmax;
-}
-
-__device__ inline void group_minmax(int tpb, unsigned long long &kmin, unsigned long long &kmax)
-{
-    if (tpb >= 2)
-        group_step<0xB1>(kmin, kmax);
-    if (tpb >= 4)
-        group_step<0x4E>(kmin, kmax);
-    if (tpb >= 8)
-        group_step<0x141>(kmin, kmax);
-    if (tpb >= 16)
-        group_step<0x140>(kmin, kmax);
-    for (int off = 16; off < tpb; off <<= 1) {
-        const unsigned long long a = __shfl_xor(kmin, off), c = __shfl_xor(kmax, off);
-        kmin = a < kmin ? a : kmin;
-        kmax = c > kmax ? c : kmax;
-    }
 }
 
 // Reduce tile[q] for q = q0, q0 + step, ... < end (q0 < end) in increasing q:

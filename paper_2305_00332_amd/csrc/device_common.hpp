@@ -92,6 +92,65 @@ __device__ inline double dpp_f64(double v)
     return __hiloint2double(dpp_i32<CTRL>(hi), dpp_i32<CTRL>(lo));
 }
 
+// Packed-key min / max over a power-of-two group of tpb <= 64 lanes (aligned
+// groups; every lane of the wave takes part). The DPP steps pair lanes within
+// quads, half-rows and rows; shuffles by 16 and 32 lanes cross rows.
+template <int CTRL>
+__device__ inline unsigned long long dpp_u64(unsigned long long v)
+{
+    const int lo = dpp_i32<CTRL>((int)(uint32_t)v);
+    const int hi = dpp_i32<CTRL>((int)(uint32_t)(v >> 32));
+    return ((unsigned long long)(uint32_t)hi << 32) | (uint32_t)lo;
+}
+
+template <int CTRL>
+__device__ inline void group_step(unsigned long long &kmin, unsigned long long &kmax)
+{
+    const unsigned long long a = dpp_u64<CTRL>(kmin), c = dpp_u64<CTRL>(kmax);
+    kmin = a < kmin ? a : kmin;
+    kmax = c > kmax ? c : kmax;
+}
+
+__device__ inline void group_minmax(int tpb, unsigned long long &kmin, unsigned long long &kmax)
+{
+    if (tpb >= 2)
+        group_step<0xB1>(kmin, kmax);
+    if (tpb >= 4)
+        group_step<0x4E>(kmin, kmax);
+    if (tpb >= 8)
+        group_step<0x141>(kmin, kmax);
+    if (tpb >= 16)
+        group_step<0x140>(kmin, kmax);
+    for (int off = 16; off < tpb; off <<= 1) {
+        const unsigned long long a = __shfl_xor(kmin, off), c = __shfl_xor(kmax, off);
+        kmin = a < kmin ? a : kmin;
+        kmax = c > kmax ? c : kmax;
+    }
+}
+
+__device__ inline unsigned long long readlane_u64(unsigned long long v, int lane)
+{
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, lane);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), lane);
+    return ((unsigned long long)hi << 32) | lo;
+}
+
+// Packed-key min and max over the full wave (every lane active); the result
+// is uniform across the wave.
+__device__ inline void wave_minmax_u64(unsigned long long &kmin, unsigned long long &kmax)
+{
+    group_minmax(16, kmin, kmax); // every lane holds its row's result
+    unsigned long long a = readlane_u64(kmin, 0), c = readlane_u64(kmax, 0);
+#pragma unroll
+    for (int row = 16; row < 64; row += 16) {
+        const unsigned long long ra = readlane_u64(kmin, row), rc = readlane_u64(kmax, row);
+        a = ra < a ? ra : a;
+        c = rc > c ? rc : c;
+    }
+    kmin = a;
+    kmax = c;
+}
+
 __device__ inline float readlane_f32(float v, int lane)
 {
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));

@@ -74,8 +74,7 @@ struct BatchSeg {
     int64_t n, n_out, out_offset;
     int32_t r_ps, mode; // SegMode
     Split bins;         // interior split into nb bins (kSegMinMax)
-    int64_t chunk;      // large bins: points per work item
-    int64_t chunks_per_bin;
+    int64_t chunk;      // large bins: points per work item (one wave streams a chunk across bin ends)
     int32_t small;      // 1: bins reduced by LDS tiles
     int32_t tile_bins;  // small: bins per tile (power of two, 4..256)
     int64_t li0, ln;    // large-bin items: start and count in the flat item space
@@ -89,6 +88,9 @@ struct BatchSeg {
     int32_t stage_cap;  // LDS points per chain segment
     int32_t seq;        // 1: sequential chain
 };
+
+// Longest stream of one wave (positions relative to its start fit in int32).
+constexpr int64_t kMaxStreamChunk = (int64_t)1 << 30;
 
 // Coarse owner tables: entry q (0..kOwnerTable) holds the series owning unit
 // min(total - 1, floor(q * total / kOwnerTable)) of a flat work space; unit i

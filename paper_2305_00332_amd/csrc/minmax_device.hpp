@@ -149,6 +149,238 @@ __device__ inline void wave_reduce_range(const float *__restrict__ y, int64_t lo
     o_imax = wave_min_i64(cmax);
 }
 
+// Bin holding interior position p (1 <= p < 1 + bins.len): the last b with
+// 1 + split_lo(bins, b) <= p. A binary64 estimate, corrected exactly.
+__device__ inline int64_t bin_of(const Split &bins, int64_t p)
+{
+    const int64_t r = p - 1;
+    int64_t b = (int64_t)((double)r * ((double)bins.parts / (double)bins.len));
+    b = b < 0 ? 0 : (b >= bins.parts ? bins.parts - 1 : b);
+    while (b > 0 && split_lo(bins, b) > r)
+        --b;
+    while (b + 1 < bins.parts && split_lo(bins, b + 1) <= r)
+        ++b;
+    return b;
+}
+
+// Per-lane running extremes of one bin part, positions relative to the
+// stream's first point (-1: none yet). Points arrive in increasing position
+// per lane, so strict comparisons keep the lowest position of each extreme.
+struct PartAcc {
+    float vmin, vmax;
+    int32_t imin, imax;
+    __device__ void reset()
+    {
+        vmin = __int_as_float(0x7f800000);
+        vmax = -__int_as_float(0x7f800000);
+        imin = imax = -1;
+    }
+    __device__ void add(float v, int32_t i)
+    {
+        if (v < vmin) {
+            vmin = v;
+            imin = i;
+        }
+        if (v > vmax) {
+            vmax = v;
+            imax = i;
+        }
+    }
+    __device__ void add_if(float v, int32_t i, bool in)
+    {
+        const float kInf = __int_as_float(0x7f800000);
+        const float a = in ? v : kInf, b = in ? v : -kInf;
+        if (a < vmin) {
+            vmin = a;
+            imin = i;
+        }
+        if (b > vmax) {
+            vmax = b;
+            imax = i;
+        }
+    }
+};
+
+// MinMax keys of every bin part of y[lo, hi) (1 <= lo < hi <= 1 + bins.len,
+// hi - lo < 2^31) with one full wave, merged into keys[2b], keys[2b + 1] by
+// atomicMin / atomicMax (up to 64 parts per vector atomic), so parts of one
+// bin streamed by different waves combine in any order. Reads stay in flight across bin ends: the body is
+// read in batches of U float4 per lane, the next batch requested before the
+// current one is reduced; a batch cut by bin ends is reduced part by part.
+// Each finished part is reduced across the wave (packed keys) and merged. A
+// part whose values never compare below +inf (or above -inf) reports its
+// first position, so every key that a part touches decodes into its bin.
+template <int U>
+__device__ inline void wave_stream_bins(const float *__restrict__ y, int64_t lo, int64_t hi, const Split &bins,
+                                        unsigned long long *__restrict__ keys, int lane)
+{
+    const float kInf = __int_as_float(0x7f800000);
+    int64_t b = bin_of(bins, lo);
+    SplitWalker w;
+    w.init(bins, b);
+    int64_t blo = 1 + w.lo, bend = 1 + w.next_lo(bins), part_lo = lo;
+    PartAcc acc;
+    acc.reset();
+    // Finished parts wait in lane `held` (one part per lane) and go out as one
+    // vector atomic per 64 parts: an atomic ahead of a load in the queue would
+    // hold up the wait for that load.
+    unsigned long long hold_min = 0, hold_max = 0;
+    int64_t hold_bin = 0;
+    int held = 0;
+    auto release = [&]() {
+        if (lane < held) {
+            atomicMin(&keys[2 * hold_bin], hold_min);
+            atomicMax(&keys[2 * hold_bin + 1], hold_max);
+        }
+        held = 0;
+    };
+    auto merge_part = [&]() {
+        unsigned long long kmin = acc.imin >= 0 ? pack_min_key(acc.vmin, lo + acc.imin - blo) : ~0ull;
+        unsigned long long kmax = acc.imax >= 0 ? pack_max_key(acc.vmax, lo + acc.imax - blo) : 0ull;
+        wave_minmax_u64(kmin, kmax);
+        if (kmin == ~0ull)
+            kmin = pack_min_key(kInf, part_lo - blo);
+        if (kmax == 0ull)
+            kmax = pack_max_key(-kInf, part_lo - blo);
+        if (lane == held) {
+            hold_min = kmin;
+            hold_max = kmax;
+            hold_bin = b;
+        }
+        if (++held == kWave)
+            release();
+    };
+    auto close_bin = [&]() { // bend reached: merge the part, move to the next bin
+        merge_part();
+        acc.reset();
+        w.advance(bins);
+        ++b;
+        blo = bend;
+        bend = 1 + w.next_lo(bins);
+        part_lo = blo;
+    };
+    // One point per lane (pos < 0: none) covering positions [r0, r1).
+    auto scalar_span = [&](int64_t r0, int64_t r1, float v, int64_t pos) {
+        int64_t c = r0;
+        while (c < r1) {
+            const int64_t e = r1 < bend ? r1 : bend;
+            if (pos >= c && pos < e)
+                acc.add(v, (int32_t)(pos - lo));
+            c = e;
+            if (c == bend)
+                close_bin();
+        }
+    };
+
+    // 16-byte aligned body [body, body_end); head [lo, body) and tail
+    // [body_end, hi) hold at most 3 points each, one per lane.
+    const uint64_t addr = (uint64_t)(uintptr_t)(y + lo);
+    int64_t head = (int64_t)(((16u - (unsigned)(addr & 15u)) & 15u) >> 2);
+    head = head < hi - lo ? head : hi - lo;
+    const int64_t body = lo + head;
+    const int64_t nvec = (hi - body) >> 2;
+    const int64_t body_end = body + 4 * nvec;
+    {
+        const int64_t pos = lane < head ? lo + lane : -1;
+        scalar_span(lo, body, pos >= 0 ? y[pos] : 0.0f, pos);
+    }
+
+    const f32x4 *__restrict__ v4 = reinterpret_cast<const f32x4 *>(y + body);
+    constexpr int64_t kVec = (int64_t)kWave * U; // float4 per batch
+    const int64_t nfull = nvec / kVec; // full batches; a partial one may follow
+    auto load = [&](f32x4(&d)[U], int64_t t) {
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            d[u] = __builtin_nontemporal_load(v4 + t * kVec + (int64_t)u * kWave + lane);
+    };
+    // The points of slab u (one float4 per lane, 4 * kWave positions from
+    // s0) that lie in positions [c, e), for a slab a bin end cuts. Points
+    // outside enter as +inf to the minimum and -inf to the maximum, which
+    // never replace a running extreme: selects, no branch.
+    auto slab_part = [&](const f32x4 &v, int32_t r, int64_t c, int64_t e) {
+        const int32_t rc = (int32_t)(c - lo), re = (int32_t)(e - lo);
+        acc.add_if(v.x, r, r >= rc && r < re);
+        acc.add_if(v.y, r + 1, r + 1 >= rc && r + 1 < re);
+        acc.add_if(v.z, r + 2, r + 2 >= rc && r + 2 < re);
+        acc.add_if(v.w, r + 3, r + 3 >= rc && r + 3 < re);
+    };
+    // A batch inside one bin (the common case) is reduced without a branch.
+    // Otherwise slab by slab: whole slabs before the bin end go in directly,
+    // only the slab holding it is split. Loops and atomics come after the
+    // slab reads they depend on, so each batch's registers are waited for
+    // alone while the next batch stays in flight.
+    auto reduce = [&](const f32x4(&d)[U], int64_t t) {
+        const int64_t base = body + 4 * t * kVec;
+        const int64_t bhi = (base + 4 * kVec < body_end) ? base + 4 * kVec : body_end;
+        const int32_t rel = (int32_t)(base - lo) + 4 * lane; // the lane's first point, relative to lo
+        if (bhi == base + 4 * kVec && bhi < bend) {
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                acc.add(d[u].x, rel + u * 4 * kWave);
+                acc.add(d[u].y, rel + u * 4 * kWave + 1);
+                acc.add(d[u].z, rel + u * 4 * kWave + 2);
+                acc.add(d[u].w, rel + u * 4 * kWave + 3);
+            }
+            return;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t s0 = base + (int64_t)u * 4 * kWave;
+            const int64_t s1 = (s0 + 4 * kWave < bhi) ? s0 + 4 * kWave : bhi;
+            const int32_t r = rel + u * 4 * kWave;
+            if (s0 >= s1)
+                continue; // past the end of a partial batch
+            if (s1 == s0 + 4 * kWave && s1 < bend) {
+                acc.add(d[u].x, r);
+                acc.add(d[u].y, r + 1);
+                acc.add(d[u].z, r + 2);
+                acc.add(d[u].w, r + 3);
+                continue;
+            }
+            int64_t e = s1 < bend ? s1 : bend;
+            slab_part(d[u], r, s0, e);
+            if (e == bend)
+                close_bin();
+            for (int64_t c = e; c < s1; c = e) { // bins shorter than a slab
+                e = s1 < bend ? s1 : bend;
+                slab_part(d[u], r, c, e);
+                if (e == bend)
+                    close_bin();
+            }
+        }
+    };
+    // Two register sets in turn over the full batches: the next batch is in
+    // flight while one is reduced. Loads and reductions pair up on every
+    // path, so each reduction waits for its own batch only.
+    f32x4 da[U], db[U];
+    int64_t t = 0;
+    if (nfull > 0)
+        load(da, 0);
+    for (; t + 1 < nfull; t += 2) { // batch t is in da
+        load(db, t + 1);
+        reduce(da, t);
+        load(da, t + 2 < nfull ? t + 2 : nfull - 1); // the last one again at the end: never reduced
+        reduce(db, t + 1);
+    }
+    if (t < nfull)
+        reduce(da, t);
+    if (nfull * kVec < nvec) { // partial last batch: missing float4 are never read
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t q = nfull * kVec + (int64_t)u * kWave + lane;
+            db[u] = q < nvec ? __builtin_nontemporal_load(v4 + q) : f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+        }
+        reduce(db, nfull);
+    }
+    {
+        const int64_t pos = lane < hi - body_end ? body_end + lane : -1;
+        scalar_span(body_end, hi, pos >= 0 ? y[pos] : 0.0f, pos);
+    }
+    if (part_lo < hi) // the stream ends inside a bin: merge that part
+        merge_part();
+    release();
+}
+
 // Block-wide exclusive scan of small non-negative counts (blockDim 1024).
 __device__ inline int block_exclusive_scan(int c, int *wave_tot, int &total)
 {
