@@ -170,7 +170,7 @@ MmLayout mm_layout(int64_t n_out, int32_t r_ps)
 }
 
 struct LtLayout {
-    size_t MX, MY, path, finals, start, total;
+    size_t MX, MY, path, finals, start, cand_cnt, cand, tab, total;
 };
 
 LtLayout lt_layout(int64_t n_out)
@@ -188,6 +188,10 @@ LtLayout lt_layout(int64_t n_out)
     L.path = take(seg_path_bytes(B));
     L.finals = take(seg_finals_bytes(B));
     L.start = take((size_t)seg_count(B));
+    const size_t tb = B <= kTableMaxBuckets ? (size_t)B : 0; // transition tables (wide buckets)
+    L.cand_cnt = take(4 * tb);
+    L.cand = take(4 * tb * kCandMax);
+    L.tab = take(8 * tb * kCandMax);
     L.total = off;
     return L;
 }
@@ -845,6 +849,12 @@ int mmlttb_lttb(int xk, const int64_t *x, const float *y, int64_t n, int64_t n_o
     if (use_segmented_chain(maxb)) {
         const SegChainArgs a = seg_args(ws, L.path, L.finals, L.start, x, y, nullptr, n, B, MX, MY, maxb);
         MMLTTB_LAUNCH("lttb_chain_seg", s, launch_lttb_chain_seg(a, nullptr, out_idx, s));
+    } else if (tuning().chain != kChainSequential && B <= kTableMaxBuckets) {
+        int32_t *cnt = at<int32_t>(ws, L.cand_cnt), *cand = at<int32_t>(ws, L.cand);
+        int2 *tab = at<int2>(ws, L.tab);
+        MMLTTB_LAUNCH("lttb_hull", s, launch_lttb_hull(x, y, n, B, cnt, cand, s));
+        MMLTTB_LAUNCH("lttb_tables", s, launch_lttb_tables(x, y, n, B, MX, MY, cnt, cand, tab, s));
+        MMLTTB_LAUNCH("lttb_table_walk", s, launch_lttb_table_walk(x, y, n, B, MX, MY, cnt, cand, tab, out_idx, s));
     } else if (maxb <= kChainStage) {
         MMLTTB_LAUNCH("lttb_chain", s, launch_lttb_chain(x, y, nullptr, n, B, MX, MY, nullptr, out_idx, s));
     } else {

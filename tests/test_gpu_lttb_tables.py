@@ -1,0 +1,94 @@
+"""Whole-series LTTB with wide buckets (the transition-table form) == oracle,
+element by element, and == the sequential pass. Shapes give buckets of a few
+hundred to 10^5 points; the series cover hulls of a few vertices (walks,
+sinusoids with spikes), hulls too large for the candidate lists (convex,
+collinear and constant series: every bucket scanned in full), exact ties and
+mixed signs, with implicit, irregular and epoch-nanosecond x."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2305_00332_amd import ops, synth
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda"
+
+
+def _y(kind, n, seed):
+    rng = np.random.default_rng(seed)
+    t = np.arange(n, dtype=np.float64)
+    if kind == "walk":
+        return synth.to_numpy(synth.random_walk(n, seed))
+    if kind == "composite":
+        return synth.to_numpy(synth.composite_series(n, seed, with_x=False)[1])
+    if kind == "ties":
+        return synth.to_numpy(synth.ties_series(n, seed))
+    if kind == "convex":  # every point on the lower hull of its bucket
+        return ((t / n - 0.5) ** 2 * 1e4).astype(np.float32)
+    if kind == "line":  # collinear: every point on both chains
+        return (t * 0.25 - 7.0).astype(np.float32)
+    if kind == "constant":
+        return np.full(n, 2.5, dtype=np.float32)
+    if kind == "sawtooth":  # repeated equal extremes in every bucket
+        return ((t % 97) - 48).astype(np.float32)
+    if kind == "spiky":  # flat noise with rare large spikes of both signs
+        y = rng.standard_normal(n).astype(np.float32) * 0.01
+        idx = rng.choice(n, size=max(1, n // 5000), replace=False)
+        y[idx] = rng.choice([-50.0, 50.0], size=idx.size).astype(np.float32)
+        return y
+    raise ValueError(kind)
+
+
+def _x(seed, n):
+    k = seed % 3
+    if k == 0:
+        return None
+    if k == 1:
+        return synth.to_numpy(synth.irregular_x(n, seed))
+    return synth.to_numpy(synth.epoch_x(n, seed))
+
+
+KINDS = ["walk", "composite", "ties", "convex", "line", "constant", "sawtooth", "spiky"]
+
+
+def _cases():
+    rng = np.random.default_rng(77)
+    out = []
+    for c in range(48):
+        n = int(np.exp(rng.uniform(np.log(2e4), np.log(3e6))))
+        n_out = int(rng.integers(3, max(4, min(400, n // 100))))
+        out.append((c, KINDS[c % len(KINDS)], n, n_out))
+    return out
+
+
+@pytest.mark.parametrize("case", _cases(), ids=lambda c: f"s{c[0]}-{c[1]}-n{c[2]}-o{c[3]}")
+def test_wide_lttb_matches_oracle_and_sequential(case):
+    seed, kind, n, n_out = case
+    y = _y(kind, n, seed)
+    x = _x(seed, n)
+    yd = torch.from_numpy(y).to(DEV)
+    xd = None if x is None else torch.from_numpy(x).to(DEV)
+    got = ops.lttb(yd, n_out, x=xd).cpu().numpy()
+    np.testing.assert_array_equal(got, oracle.lttb(y, n_out, x))
+    old = ops.get_tuning()
+    try:
+        ops.set_tuning(0, 0, ops.CHAIN_SEQUENTIAL)
+        seq = ops.lttb(yd, n_out, x=xd).cpu().numpy()
+    finally:
+        ops.set_tuning(*old)
+    np.testing.assert_array_equal(got, seq)
+
+
+def test_repeated_calls_reuse_the_workspace():
+    n, n_out = 2_000_003, 501
+    y = synth.random_walk(n, 3, device=DEV)
+    ws = torch.empty(ops.lttb_workspace_size(n, n_out), dtype=torch.uint8, device=DEV)
+    first = ops.lttb(y, n_out, ws=ws).clone()
+    z = synth.composite_series(n, 4, with_x=False)[1].to(DEV)
+    second = ops.lttb(z, n_out, ws=ws).cpu().numpy()  # tables of the first call must not leak
+    np.testing.assert_array_equal(second, oracle.lttb(z.cpu().numpy(), n_out, None))
+    np.testing.assert_array_equal(first.cpu().numpy(), oracle.lttb(y.cpu().numpy(), n_out, None))
