@@ -852,7 +852,7 @@ int mmlttb_lttb(int xk, const int64_t *x, const float *y, int64_t n, int64_t n_o
     } else if (tuning().chain != kChainSequential && B <= kTableMaxBuckets) {
         int32_t *cnt = at<int32_t>(ws, L.cand_cnt), *cand = at<int32_t>(ws, L.cand);
         int2 *tab = at<int2>(ws, L.tab);
-        MMLTTB_LAUNCH("lttb_hull", s, launch_lttb_hull(x, y, n, B, cnt, cand, s));
+        MMLTTB_LAUNCH("lttb_hull", s, launch_lttb_hull(x, y, n, B, MX, MY, cnt, cand, s));
         MMLTTB_LAUNCH("lttb_tables", s, launch_lttb_tables(x, y, n, B, MX, MY, cnt, cand, tab, s));
         MMLTTB_LAUNCH("lttb_table_walk", s, launch_lttb_table_walk(x, y, n, B, MX, MY, cnt, cand, tab, out_idx, s));
     } else if (maxb <= kChainStage) {

@@ -216,8 +216,8 @@ hipError_t launch_lttb_chain(const double *XP, const double *YP, const int64_t *
 constexpr int kCandMax = 64;
 // Largest bucket count the table form runs (its grids and tables grow with B).
 constexpr int64_t kTableMaxBuckets = (int64_t)1 << 24;
-hipError_t launch_lttb_hull(const int64_t *X, const float *Y, int64_t n, int64_t B, int32_t *cand_cnt, int32_t *cand,
-                            hipStream_t s);
+hipError_t launch_lttb_hull(const int64_t *X, const float *Y, int64_t n, int64_t B, const double *MX, const double *MY,
+                            int32_t *cand_cnt, int32_t *cand, hipStream_t s);
 hipError_t launch_lttb_tables(const int64_t *X, const float *Y, int64_t n, int64_t B, const double *MX,
                               const double *MY, const int32_t *cand_cnt, const int32_t *cand, int2 *tab,
                               hipStream_t s);

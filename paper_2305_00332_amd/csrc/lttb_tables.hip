@@ -7,11 +7,12 @@
 // linear function of (Xj, Yj), so in exact arithmetic its maximum over the
 // bucket lies on the bucket's convex hull, whatever a and the mean are.
 //
-//   k_lttb_hull    one wave per bucket k < B-1: the candidate picks of bucket
-//                  k, the vertices of its upper and lower hull plus points
-//                  close to a hull edge (a relative tolerance far above
-//                  rounding), at most kCandMax of them, or none (count -1)
-//                  when the hull is larger.
+//   k_lttb_hull    one workgroup per bucket k < B-1: the candidate picks of
+//                  bucket k, the hull vertices (plus points close to a hull
+//                  edge) at which a line with the slope of some line from a
+//                  possible predecessor to the next-bucket mean touches the
+//                  hull; at most kCandMax, or none (count -1) when the search
+//                  overflows.
 //   k_lttb_tables  for every candidate a of bucket k-1 (point 0 for k = 0):
 //                  the pick in bucket k, evaluated over every point of bucket
 //                  k with the exact definition above, and the slot of that
@@ -30,213 +31,386 @@
 
 namespace mmlttb {
 
-// Chunk-hull vertices each lane keeps per chain (upper, lower).
-constexpr int kHullLane = 24;
-// A point stays on a chain unless it lies inside by more than this fraction
-// of the terms of the orientation test (float coordinates relative to the
-// bucket's first point): near-collinear points remain candidates.
-constexpr float kHullTol = 1e-4f;
-// Candidates per table workgroup.
-constexpr int kTabGroup = 8;
-// Buckets of tables staged in LDS per window of the walk.
-constexpr int kWalkWindow = 32;
+// Candidate search for bucket b (one workgroup of kHullThreads):
+//  - the range [g0, g1] of slopes of the lines from the points that can
+//    precede b's pick (bucket b-1, or point 0 for b = 0) to b's next-bucket
+//    mean M_b, from the corners of the predecessors' bounding box, widened by
+//    a margin: the pick is the point farthest from such a line, where a line
+//    of that slope touches the bucket's hull (upper or lower chain);
+//  - the points where lines of kSlopes slopes spread over [g0, g1] touch the
+//    bucket from above and from below: every upper-hull vertex that a slope
+//    between two neighbouring ones touches lies on or above the line through
+//    their two tangent points (the chain is concave), every lower one on or
+//    below the corresponding lower line;
+//  - survivors: the points on the outer side of any of those lines, or within
+//    a relative kSideTol of it, sorted by position (at most kSurvMax);
+//  - the upper and lower monotone chains of the survivors (binary64, points
+//    within a relative kChainTol of an edge kept);
+//  - the chain vertices whose range of tangent slopes meets [g0, g1]: the
+//    candidates.
+// Every threshold only widens the candidate set; it stays an aid, never a
+// part of the result.
+constexpr int kHullThreads = 256;
+constexpr int kSlopes = 6;     // slopes whose tangent points bound the survivors
+constexpr int kSurvMax = 512; // survivors kept per bucket
+constexpr int kChainMax = 128; // vertices per chain
+constexpr double kSideTol = 1e-9;
+constexpr double kChainTol = 1e-9;
+// Candidates per table pass, and workgroups per bucket (each takes every
+// kTabWGs-th group of candidates).
+constexpr int kTabGroup = 4;
+constexpr int kTabWGs = 2;
+// The walk stages the first kWalkSlots entries of kWalkWindow buckets in LDS
+// (entries past them, rare, are read from global memory).
+constexpr int kWalkWindow = 128;
+constexpr int kWalkSlots = 16;
 
 __device__ inline double xval(const int64_t *__restrict__ X, int64_t p) { return X ? (double)X[p] : (double)p; }
 
-// Orientation test of the monotone chain: true when b lies clearly inside
-// (below the segment a-p for the upper chain, above it for the lower one).
-__device__ inline bool hull_pop(float ax, float ay, float bx, float by, float px, float py, bool upper)
+// f(p, x, y) for p = first, first + step, ... < end, in increasing p, with the
+// loads of kDepth points issued together (a scan with one load per step
+// waits a full memory latency per step).
+template <int kDepth, bool kHasX, class F>
+__device__ inline void scan_points_x(const int64_t *__restrict__ X, const float *__restrict__ Y, int64_t first,
+                                     int64_t end, int64_t step, F &&f)
 {
-    const float t1 = (bx - ax) * (py - ay), t2 = (by - ay) * (px - ax);
-    const float cr = t1 - t2, tol = kHullTol * (fabsf(t1) + fabsf(t2));
+    int64_t p = first;
+    for (; p + (kDepth - 1) * step < end; p += kDepth * step) {
+        double xs[kDepth];
+        float ys[kDepth];
+#pragma unroll
+        for (int u = 0; u < kDepth; ++u) {
+            xs[u] = kHasX ? (double)X[p + u * step] : (double)(p + u * step);
+            ys[u] = Y[p + u * step];
+        }
+#pragma unroll
+        for (int u = 0; u < kDepth; ++u)
+            f(p + u * step, xs[u], (double)ys[u]);
+    }
+    for (; p < end; p += step)
+        f(p, kHasX ? (double)X[p] : (double)p, (double)Y[p]);
+}
+
+template <int kDepth = 8, class F>
+__device__ inline void scan_points(const int64_t *__restrict__ X, const float *__restrict__ Y, int64_t first,
+                                   int64_t end, int64_t step, F &&f)
+{
+    if (X)
+        scan_points_x<kDepth, true>(X, Y, first, end, step, f);
+    else
+        scan_points_x<kDepth, false>(X, Y, first, end, step, f);
+}
+
+// Orientation test of the monotone chain: true when b lies inside (below the
+// segment a-p for the upper chain, above it for the lower one) by more than
+// the tolerance.
+__device__ inline bool chain_pop(double ax, double ay, double bx, double by, double px, double py, bool upper)
+{
+    const double t1 = (bx - ax) * (py - ay), t2 = (by - ay) * (px - ax);
+    const double cr = t1 - t2, tol = kChainTol * (fabs(t1) + fabs(t2));
     return upper ? cr > tol : cr < -tol;
 }
 
-// One wave per bucket k in [0, B - 1). Phase 1: lane l builds both chains of
-// its contiguous chunk of the bucket (LDS, kHullLane points each, indexed
-// [i * kWave + lane]). Phase 2: lane 0 (upper) and lane 1 (lower) run the
-// chain again over the chunk chains in lane order, which is position order.
-// Lane 0 then merges both into cand[k * kCandMax ..] (offsets inside the
-// bucket, increasing) and writes their count, or -1 on any overflow.
-__global__ __launch_bounds__(kWave) void k_lttb_hull(const int64_t *__restrict__ X, const float *__restrict__ Y,
-                                                     int64_t n, int64_t B, int32_t *__restrict__ cand_cnt,
-                                                     int32_t *__restrict__ cand)
+__device__ inline double block_min_f64(double v, double *red)
 {
-    __shared__ float hx[2][kHullLane * kWave], hy[2][kHullLane * kWave];
-    __shared__ int32_t hi[2][kHullLane * kWave];
-    __shared__ int32_t hn[2][kWave];
-    __shared__ float mx_[2][kCandMax], my_[2][kCandMax];
-    __shared__ int32_t mi[2][kCandMax];
-    __shared__ int32_t mn[2];
-    __shared__ int32_t ovf;
-    const int lane = threadIdx.x;
-    const int64_t k = blockIdx.x;
-    const Split bk = make_split(n - 2, B);
-    const int64_t s = 1 + split_lo(bk, k), e = 1 + split_lo(bk, k + 1);
-    const double x0 = xval(X, s);
-    const float y0 = Y[s];
+    const int tid = threadIdx.x, lane = tid & (kWave - 1), wid = tid / kWave;
+    v = -wave_max_f64(-v);
+    __syncthreads();
     if (lane == 0)
+        red[wid] = v;
+    __syncthreads();
+    double r = red[0];
+    for (int q = 1; q < kHullThreads / kWave; ++q)
+        r = red[q] < r ? red[q] : r;
+    return r;
+}
+
+__device__ inline double block_max_f64(double v, double *red) { return -block_min_f64(-v, red); }
+
+__global__ __launch_bounds__(kHullThreads) void k_lttb_hull(const int64_t *__restrict__ X, const float *__restrict__ Y,
+                                                            int64_t n, int64_t B, const double *__restrict__ MX,
+                                                            const double *__restrict__ MY,
+                                                            int32_t *__restrict__ cand_cnt, int32_t *__restrict__ cand)
+{
+    __shared__ double red[kHullThreads / kWave];
+    __shared__ double sx[kSurvMax], sy[kSurvMax], tx[kSurvMax], ty[kSurvMax];
+    __shared__ int32_t si[kSurvMax], ti[kSurvMax];
+    __shared__ double cxs[2][kChainMax], cys[2][kChainMax];
+    __shared__ int32_t ci[2][kChainMax], ckeep[2][kChainMax];
+    __shared__ int32_t cn[2], nsurv, ovf;
+    __shared__ double tv[kHullThreads / kWave][2 * kSlopes], tpx[2 * kSlopes], tpy[2 * kSlopes];
+    __shared__ int32_t to[kHullThreads / kWave][2 * kSlopes];
+    const int tid = threadIdx.x;
+    const int64_t b = blockIdx.x;
+    const Split bk = make_split(n - 2, B);
+    const int64_t s = 1 + split_lo(bk, b), e = 1 + split_lo(bk, b + 1);
+    const int64_t ps = b == 0 ? 0 : 1 + split_lo(bk, b - 1), pe = b == 0 ? 1 : s;
+    if (tid == 0) {
+        nsurv = 0;
         ovf = 0;
-    __syncthreads();
+    }
+    const double inf = __longlong_as_double(0x7ff0000000000000ll);
 
-    const int64_t c = (e - s + kWave - 1) / kWave;
-    const int64_t p0 = s + lane * c < e ? s + lane * c : e;
-    const int64_t p1 = p0 + c < e ? p0 + c : e;
-    int cnt[2] = {0, 0};
-    bool bad = false;
-    constexpr int kRun = 16; // points read ahead per lane
-    for (int64_t q = p0; q < p1; q += kRun) {
-        float px[kRun], py[kRun];
+    // slope range from the predecessors' bounding box (M_b lies right of it)
+    double plo = inf, phi = -inf;
+    scan_points(nullptr, Y, ps + tid, pe, kHullThreads, [&](int64_t, double, double v) {
+        plo = v < plo ? v : plo;
+        phi = v > phi ? v : phi;
+    });
+    plo = block_min_f64(plo, red);
+    phi = block_max_f64(phi, red);
+    const double mxb = MX[b], myb = MY[b];
+    const double dx0 = mxb - xval(X, ps), dx1 = mxb - xval(X, pe - 1); // both > 0
+    const double c0 = (myb - phi) / dx0, c1 = (myb - phi) / dx1, c2 = (myb - plo) / dx0, c3 = (myb - plo) / dx1;
+    double g0 = fmin(fmin(c0, c1), fmin(c2, c3)), g1 = fmax(fmax(c0, c1), fmax(c2, c3));
+    const double pad = 1e-6 * (g1 - g0) + 1e-9 * (fabs(g0) + fabs(g1)) + 1e-300;
+    g0 -= pad;
+    g1 += pad;
+    const bool wide = !(g1 - g0 < inf); // a slope the box cannot bound: keep every chain vertex
+
+    // the bucket's y span sets the spacing of kSlopes slopes across [g0, g1]
+    // (even in angle in the bucket's own scale)
+    double ylo = inf, yhi = -inf;
+    scan_points(nullptr, Y, s + tid, e, kHullThreads, [&](int64_t, double, double v) {
+        ylo = v < ylo ? v : ylo;
+        yhi = v > yhi ? v : yhi;
+    });
+    ylo = block_min_f64(ylo, red);
+    yhi = block_max_f64(yhi, red);
+    const double x0 = xval(X, s);
+    double r = (xval(X, e - 1) - x0) / (yhi - ylo);
+    r = (r > 0.0 && r < inf) ? r : 1.0;
+    double gs[kSlopes];
+    {
+        const double t0 = atan(g0 * r), t1 = atan(g1 * r);
 #pragma unroll
-        for (int u = 0; u < kRun; ++u) {
-            const int64_t p = q + u < p1 ? q + u : p1 - 1;
-            px[u] = (float)(xval(X, p) - x0);
-            py[u] = Y[p] - y0;
-        }
+        for (int i = 0; i < kSlopes; ++i)
+            gs[i] = i == 0 ? g0 : (i == kSlopes - 1 ? g1 : tan(t0 + (t1 - t0) * i / (kSlopes - 1)) / r);
+    }
+
+    // tangent points of those slopes, from above and from below
+    double fmax_[kSlopes], fmin_[kSlopes];
+    int32_t omax[kSlopes], omin[kSlopes];
 #pragma unroll
-        for (int u = 0; u < kRun; ++u) {
-            if (q + u >= p1)
-                break;
+    for (int i = 0; i < kSlopes; ++i) {
+        fmax_[i] = -inf;
+        fmin_[i] = inf;
+        omax[i] = omin[i] = 0;
+    }
+    scan_points<2>(X, Y, s + tid, e, kHullThreads, [&](int64_t p, double xr, double y) {
+        const double x = xr - x0;
+        const int32_t o = (int32_t)(p - s);
 #pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                int m = cnt[h];
-                while (m >= 2 && hull_pop(hx[h][(m - 2) * kWave + lane], hy[h][(m - 2) * kWave + lane],
-                                          hx[h][(m - 1) * kWave + lane], hy[h][(m - 1) * kWave + lane], px[u], py[u],
-                                          h == 0))
-                    --m;
-                if (m < kHullLane) {
-                    hx[h][m * kWave + lane] = px[u];
-                    hy[h][m * kWave + lane] = py[u];
-                    hi[h][m * kWave + lane] = (int32_t)(q + u - s);
-                    ++m;
-                } else {
-                    bad = true;
-                }
-                cnt[h] = m;
+        for (int i = 0; i < kSlopes; ++i) {
+            const double f = y - gs[i] * x;
+            if (f > fmax_[i]) {
+                fmax_[i] = f;
+                omax[i] = o;
+            }
+            if (f < fmin_[i]) {
+                fmin_[i] = f;
+                omin[i] = o;
             }
         }
+    });
+    {
+        const int lane = tid & (kWave - 1), wid = tid / kWave;
+#pragma unroll
+        for (int i = 0; i < kSlopes; ++i) {
+            const double vmax = wave_max_f64(fmax_[i]), vmin = -wave_max_f64(-fmin_[i]);
+            const int64_t cmax = wave_min_i64(fmax_[i] == vmax ? omax[i] : INT64_MAX);
+            const int64_t cmin = wave_min_i64(fmin_[i] == vmin ? omin[i] : INT64_MAX);
+            if (lane == 0) {
+                tv[wid][i] = vmax;
+                tv[wid][kSlopes + i] = -vmin;
+                to[wid][i] = (int32_t)cmax;
+                to[wid][kSlopes + i] = (int32_t)cmin;
+            }
+        }
+        __syncthreads();
+        if (tid < 2 * kSlopes) { // tangent point tid: upper for tid < kSlopes, lower after
+            double bv = tv[0][tid];
+            int32_t bo = to[0][tid];
+            for (int q = 1; q < kHullThreads / kWave; ++q) {
+                if (tv[q][tid] > bv || (tv[q][tid] == bv && to[q][tid] < bo)) {
+                    bv = tv[q][tid];
+                    bo = to[q][tid];
+                }
+            }
+            bo = (bo >= 0 && bo < e - s) ? bo : 0; // some thread holds the extreme: never past the bucket
+            tpx[tid] = xval(X, s + bo) - x0;
+            tpy[tid] = (double)Y[s + bo];
+        }
+        __syncthreads();
     }
-    hn[0][lane] = cnt[0];
-    hn[1][lane] = cnt[1];
-    if (bad)
-        ovf = 1;
+
+    // survivors (appended in any order, then sorted by position): points on
+    // the outer side of a chord between tangent points of neighbouring slopes
+    scan_points<2>(X, Y, s + tid, e, kHullThreads, [&](int64_t p, double xr, double y) {
+        const double x = xr - x0;
+        // side of the line through tangent points i and i + 1 (of slopes
+        // gs[i], gs[i + 1]); > 0 on the outer side
+        auto outer = [&](int i, int base, double sgn) {
+            const double ax = tpx[base + i], ay = tpy[base + i];
+            double ex = tpx[base + i + 1] - ax, ey = tpy[base + i + 1] - ay;
+            if (ex < 0.0) { // orient left to right
+                ex = -ex;
+                ey = -ey;
+            }
+            if (ex == 0.0 && ey == 0.0) { // one tangent point: the line of a slope between through it
+                const double g = 0.5 * (gs[i] + gs[i + 1]);
+                const double d = (y - ay) - g * (x - ax);
+                return sgn * d >= -kSideTol * (fabs(y - ay) + fabs(g * (x - ax)));
+            }
+            const double t1 = ex * (y - ay), t2 = ey * (x - ax);
+            return sgn * (t1 - t2) >= -kSideTol * (fabs(t1) + fabs(t2));
+        };
+        bool keep = wide;
+#pragma unroll
+        for (int i = 0; i + 1 < kSlopes; ++i)
+            keep = keep || outer(i, 0, 1.0) || outer(i, kSlopes, -1.0);
+        if (keep) {
+            const int q = atomicAdd(&nsurv, 1);
+            if (q < kSurvMax) {
+                sx[q] = x;
+                sy[q] = y;
+                si[q] = (int32_t)(p - s);
+            }
+        }
+    });
+    __syncthreads();
+    const int total = nsurv;
+    const int ns = total < kSurvMax ? total : kSurvMax;
+    for (int q = tid; q < ns; q += kHullThreads) { // rank sort by position (distinct)
+        const int32_t me = si[q];
+        int r = 0;
+        for (int j = 0; j < ns; ++j)
+            r += si[j] < me ? 1 : 0;
+        tx[r] = sx[q];
+        ty[r] = sy[q];
+        ti[r] = me;
+    }
     __syncthreads();
 
-    if (lane < 2) {
-        const int h = lane;
+    // chains: thread 0 the upper, thread 1 the lower; then the slope filter
+    if (tid < 2 && total <= kSurvMax) {
+        const bool upper = tid == 0;
         int m = 0;
-        for (int l = 0; l < kWave; ++l) {
-            for (int i = 0; i < hn[h][l]; ++i) {
-                const float px = hx[h][i * kWave + l], py = hy[h][i * kWave + l];
-                while (m >= 2 && hull_pop(mx_[h][m - 2], my_[h][m - 2], mx_[h][m - 1], my_[h][m - 1], px, py, h == 0))
-                    --m;
-                if (m < kCandMax) {
-                    mx_[h][m] = px;
-                    my_[h][m] = py;
-                    mi[h][m] = hi[h][i * kWave + l];
-                    ++m;
-                } else {
-                    ovf = 1;
-                }
+        for (int q = 0; q < ns; ++q) {
+            const double x = tx[q], y = ty[q];
+            while (m >= 2 && chain_pop(cxs[tid][m - 2], cys[tid][m - 2], cxs[tid][m - 1], cys[tid][m - 1], x, y, upper))
+                --m;
+            if (m < kChainMax) {
+                cxs[tid][m] = x;
+                cys[tid][m] = y;
+                ci[tid][m] = ti[q];
+                ++m;
+            } else {
+                ovf = 1;
             }
         }
-        mn[h] = m;
+        cn[tid] = m;
+        // upper vertex i is touched by the slopes between its right and left
+        // edge slopes, lower vertex i by those between its left and right ones
+        for (int i = 0; i < m; ++i) {
+            double left = upper ? inf : -inf, right = upper ? -inf : inf;
+            if (i > 0 && cxs[tid][i] > cxs[tid][i - 1])
+                left = (cys[tid][i] - cys[tid][i - 1]) / (cxs[tid][i] - cxs[tid][i - 1]);
+            if (i + 1 < m && cxs[tid][i + 1] > cxs[tid][i])
+                right = (cys[tid][i + 1] - cys[tid][i]) / (cxs[tid][i + 1] - cxs[tid][i]);
+            const double lo = fmin(left, right), hi = fmax(left, right);
+            ckeep[tid][i] = (wide || (hi >= g0 && lo <= g1)) ? 1 : 0;
+        }
     }
     __syncthreads();
 
-    if (lane == 0) {
-        int32_t *out = cand + k * (int64_t)kCandMax;
-        int a = 0, b = 0, m = 0;
-        bool full = ovf != 0;
-        while (!full && (a < mn[0] || b < mn[1])) {
+    if (tid == 0) {
+        int32_t *out = cand + b * (int64_t)kCandMax;
+        int a = 0, c = 0, m = 0;
+        bool full = ovf != 0 || total > kSurvMax;
+        auto next = [&](int h, int &i) { // next kept vertex of chain h at or after i
+            while (i < cn[h] && !ckeep[h][i])
+                ++i;
+        };
+        if (!full) {
+            next(0, a);
+            next(1, c);
+        }
+        while (!full && (a < cn[0] || c < cn[1])) {
             int32_t v;
-            if (b >= mn[1] || (a < mn[0] && mi[0][a] <= mi[1][b])) {
-                v = mi[0][a++];
-                if (b < mn[1] && mi[1][b] == v)
-                    ++b;
+            if (c >= cn[1] || (a < cn[0] && ci[0][a] <= ci[1][c])) {
+                v = ci[0][a++];
+                if (c < cn[1] && ci[1][c] == v)
+                    ++c;
             } else {
-                v = mi[1][b++];
+                v = ci[1][c++];
             }
             if (m < kCandMax)
                 out[m++] = v;
             else
                 full = true;
+            next(0, a);
+            next(1, c);
         }
-        cand_cnt[k] = full ? -1 : m;
+        cand_cnt[b] = full ? -1 : m;
     }
 }
 
-// Workgroup (k, g): candidates g*kTabGroup .. of bucket k-1 (point 0 alone
-// for k = 0) against every point of bucket k. Each thread scans its points in
-// increasing position with a strict comparison; the workgroup then keeps the
-// largest area and the lowest position among equal ones; no area above -1
-// (every one NaN) leaves the bucket's first point, as in the sequential pass.
-__global__ __launch_bounds__(256) void k_lttb_tables(const int64_t *__restrict__ X, const float *__restrict__ Y,
-                                                     int64_t n, int64_t B, const double *__restrict__ MX,
-                                                     const double *__restrict__ MY,
-                                                     const int32_t *__restrict__ cand_cnt,
-                                                     const int32_t *__restrict__ cand, int2 *__restrict__ tab)
+// Table entries c0 .. c0 + kTabGroup - 1 of bucket k (candidates of bucket
+// k-1, or point 0 alone for k = 0) against every point [s, e) of bucket k.
+// Each thread scans its points in increasing position with a strict
+// comparison; the workgroup then keeps the largest area and the lowest
+// position among equal ones; no area above -1 (every one NaN) leaves the
+// bucket's first point, as in the sequential pass.
+__device__ inline void table_group(const int64_t *__restrict__ X, const float *__restrict__ Y, int64_t k, int64_t B,
+                                   int64_t s, int64_t e, int64_t sp, int c0, int nc, double mx, double my,
+                                   const int32_t *__restrict__ cand_cnt, const int32_t *__restrict__ cand,
+                                   int2 *__restrict__ tab, double (*s_best)[kTabGroup], int32_t (*s_idx)[kTabGroup])
 {
-    __shared__ double s_best[4][kTabGroup];
-    __shared__ int64_t s_idx[4][kTabGroup];
-    constexpr int kGroups = kCandMax / kTabGroup;
-    const int64_t k = blockIdx.x / kGroups;
-    const int g = blockIdx.x % kGroups;
     const int tid = threadIdx.x, lane = tid & (kWave - 1), wid = tid / kWave;
-    const int ncand = k == 0 ? 1 : cand_cnt[k - 1];
-    const int c0 = g * kTabGroup;
-    if (c0 >= ncand) // also no candidates at all (-1)
-        return;
-    const int nc = ncand - c0 < kTabGroup ? ncand - c0 : kTabGroup;
-    const Split bk = make_split(n - 2, B);
-    const int64_t s = 1 + split_lo(bk, k), e = 1 + split_lo(bk, k + 1);
-    const int64_t sp = k == 0 ? 0 : 1 + split_lo(bk, k - 1);
-    const double mx = MX[k], my = MY[k];
     double xa[kTabGroup], ya[kTabGroup], best[kTabGroup];
-    int64_t bi[kTabGroup];
+    int32_t bi[kTabGroup];
 #pragma unroll
     for (int c = 0; c < kTabGroup; ++c) {
         const int64_t a = k == 0 ? 0 : sp + cand[(k - 1) * (int64_t)kCandMax + c0 + (c < nc ? c : 0)];
         xa[c] = xval(X, a);
         ya[c] = (double)Y[a];
         best[c] = -1.0;
-        bi[c] = INT64_MAX;
+        bi[c] = 0x7fffffff;
     }
-    for (int64_t j = s + tid; j < e; j += blockDim.x) {
-        const double xj = xval(X, j), yj = (double)Y[j];
+    scan_points<4>(X, Y, s + tid, e, blockDim.x, [&](int64_t p, double xj, double yj) {
 #pragma unroll
         for (int c = 0; c < kTabGroup; ++c) {
             const double ar = lttb_area2(xa[c], ya[c], xj, yj, mx, my);
-            if (ar > best[c]) {
+            if (ar > best[c]) { // strict, positions increasing per thread: the lowest wins ties
                 best[c] = ar;
-                bi[c] = j;
+                bi[c] = (int32_t)(p - s);
             }
         }
-    }
+    });
 #pragma unroll
     for (int c = 0; c < kTabGroup; ++c) {
         const double wb = wave_max_f64(best[c]);
-        const int64_t wi = wave_min_i64(best[c] == wb ? bi[c] : INT64_MAX);
+        const int64_t wi = wave_min_i64(best[c] == wb ? bi[c] : 0x7fffffff);
         if (lane == 0) {
             s_best[wid][c] = wb;
-            s_idx[wid][c] = wi;
+            s_idx[wid][c] = (int32_t)wi;
         }
     }
     __syncthreads();
     if (tid < nc) {
-        double b = -1.0;
-        int64_t p = INT64_MAX;
-        for (int w = 0; w < 4; ++w) {
+        double bb = -1.0;
+        int32_t off = 0x7fffffff;
+        for (int w = 0; w < (int)(blockDim.x / kWave); ++w) {
             const double a = s_best[w][tid];
-            const int64_t i = s_idx[w][tid];
-            if (a > b || (a == b && i < p)) {
-                b = a;
-                p = i;
+            const int32_t i = s_idx[w][tid];
+            if (a > bb || (a == bb && i < off)) {
+                bb = a;
+                off = i;
             }
         }
-        if (!(b > -1.0)) // no numeric area: the bucket's first point
-            p = s;
-        const int32_t off = (int32_t)(p - s);
+        if (!(bb > -1.0)) // no numeric area: the bucket's first point
+            off = 0;
         int32_t next = -1;
         const int nk = k + 1 < B ? cand_cnt[k] : -1;
         if (nk > 0) {
@@ -253,6 +427,34 @@ __global__ __launch_bounds__(256) void k_lttb_tables(const int64_t *__restrict__
         }
         tab[k * (int64_t)kCandMax + c0 + tid] = make_int2(off, next);
     }
+    __syncthreads(); // s_best and s_idx are reused by the next group
+}
+
+// Workgroup (k, g) of kTableThreads: the candidate groups g, g + kTabWGs, ...
+// of bucket k.
+constexpr int kTableThreads = 256;
+__global__ __launch_bounds__(kTableThreads) void k_lttb_tables(const int64_t *__restrict__ X,
+                                                               const float *__restrict__ Y, int64_t n, int64_t B,
+                                                               const double *__restrict__ MX,
+                                                               const double *__restrict__ MY,
+                                                               const int32_t *__restrict__ cand_cnt,
+                                                               const int32_t *__restrict__ cand, int2 *__restrict__ tab)
+{
+    __shared__ double s_best[kTableThreads / kWave][kTabGroup];
+    __shared__ int32_t s_idx[kTableThreads / kWave][kTabGroup];
+    const int64_t k = blockIdx.x / kTabWGs;
+    const int g = blockIdx.x % kTabWGs;
+    const int ncand = k == 0 ? 1 : cand_cnt[k - 1];
+    if (g * kTabGroup >= ncand) // also no candidates at all (-1)
+        return;
+    const Split bk = make_split(n - 2, B);
+    const int64_t s = 1 + split_lo(bk, k), e = 1 + split_lo(bk, k + 1);
+    const int64_t sp = k == 0 ? 0 : 1 + split_lo(bk, k - 1);
+    const double mx = MX[k], my = MY[k];
+    for (int c0 = g * kTabGroup; c0 < ncand; c0 += kTabWGs * kTabGroup) {
+        const int nc = ncand - c0 < kTabGroup ? ncand - c0 : kTabGroup;
+        table_group(X, Y, k, B, s, e, sp, c0, nc, mx, my, cand_cnt, cand, tab, s_best, s_idx);
+    }
 }
 
 // One workgroup of 1024 threads. Thread 0 follows the tables through LDS
@@ -265,7 +467,7 @@ __global__ __launch_bounds__(1024) void k_lttb_table_walk(const int64_t *__restr
                                                           const int32_t *__restrict__ cand,
                                                           const int2 *__restrict__ tab, int64_t *__restrict__ out)
 {
-    __shared__ int2 sT[kWalkWindow * kCandMax];
+    __shared__ int2 sT[kWalkWindow * kWalkSlots];
     __shared__ double s_area[16];
     __shared__ int64_t s_idx[16];
     __shared__ int64_t s_k, s_a;
@@ -278,9 +480,9 @@ __global__ __launch_bounds__(1024) void k_lttb_table_walk(const int64_t *__restr
     while (k < B) {
         if (slot >= 0) {
             const int64_t k1 = k + kWalkWindow < B ? k + kWalkWindow : B;
-            const int64_t words = (k1 - k) * kCandMax;
+            const int64_t words = (k1 - k) * kWalkSlots;
             for (int64_t q = tid; q < words; q += blockDim.x)
-                sT[q] = tab[k * kCandMax + q];
+                sT[q] = tab[(k + q / kWalkSlots) * kCandMax + q % kWalkSlots];
             __syncthreads();
             if (tid == 0) {
                 SplitWalker w;
@@ -288,7 +490,7 @@ __global__ __launch_bounds__(1024) void k_lttb_table_walk(const int64_t *__restr
                 int64_t kk = k;
                 int32_t sl = slot;
                 while (kk < k1 && sl >= 0) {
-                    const int2 t = sT[(kk - k) * kCandMax + sl];
+                    const int2 t = sl < kWalkSlots ? sT[(kk - k) * kWalkSlots + sl] : tab[kk * kCandMax + sl];
                     a = 1 + w.lo + t.x;
                     out[kk + 1] = a;
                     sl = t.y;
@@ -311,13 +513,13 @@ __global__ __launch_bounds__(1024) void k_lttb_table_walk(const int64_t *__restr
         const double ax = xval(X, a), ay = (double)Y[a], mx = MX[k], my = MY[k];
         double best = -1.0;
         int64_t bj = INT64_MAX;
-        for (int64_t j = s0 + tid; j < s1; j += blockDim.x) {
-            const double ar = lttb_area2(ax, ay, xval(X, j), (double)Y[j], mx, my);
+        scan_points(X, Y, s0 + tid, s1, blockDim.x, [&](int64_t j, double xj, double yj) {
+            const double ar = lttb_area2(ax, ay, xj, yj, mx, my);
             if (ar > best) {
                 best = ar;
                 bj = j;
             }
-        }
+        });
         const double wb = wave_max_f64(best);
         const int64_t wsel = wave_min_i64(best == wb ? bj : INT64_MAX);
         if (lane == 0) {
@@ -358,12 +560,13 @@ __global__ __launch_bounds__(1024) void k_lttb_table_walk(const int64_t *__restr
     }
 }
 
-hipError_t launch_lttb_hull(const int64_t *X, const float *Y, int64_t n, int64_t B, int32_t *cand_cnt, int32_t *cand,
-                            hipStream_t s)
+hipError_t launch_lttb_hull(const int64_t *X, const float *Y, int64_t n, int64_t B, const double *MX, const double *MY,
+                            int32_t *cand_cnt, int32_t *cand, hipStream_t s)
 {
     if (B < 2)
         return hipSuccess;
-    hipLaunchKernelGGL(k_lttb_hull, dim3((unsigned)(B - 1)), dim3(kWave), 0, s, X, Y, n, B, cand_cnt, cand);
+    hipLaunchKernelGGL(k_lttb_hull, dim3((unsigned)(B - 1)), dim3(kHullThreads), 0, s, X, Y, n, B, MX, MY, cand_cnt,
+                       cand);
     return hipGetLastError();
 }
 
@@ -371,7 +574,7 @@ hipError_t launch_lttb_tables(const int64_t *X, const float *Y, int64_t n, int64
                               const double *MY, const int32_t *cand_cnt, const int32_t *cand, int2 *tab,
                               hipStream_t s)
 {
-    hipLaunchKernelGGL(k_lttb_tables, dim3((unsigned)(B * (kCandMax / kTabGroup))), dim3(256), 0, s, X, Y, n, B, MX,
+    hipLaunchKernelGGL(k_lttb_tables, dim3((unsigned)(B * kTabWGs)), dim3(kTableThreads), 0, s, X, Y, n, B, MX,
                        MY, cand_cnt, cand, tab);
     return hipGetLastError();
 }
