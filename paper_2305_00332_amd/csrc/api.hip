@@ -170,7 +170,7 @@ MmLayout mm_layout(int64_t n_out, int32_t r_ps)
 }
 
 struct LtLayout {
-    size_t MX, MY, path, finals, start, cand_cnt, cand, tab, total;
+    size_t MX, MY, path, finals, start, yr, cand_cnt, cand, tab, total;
 };
 
 LtLayout lt_layout(int64_t n_out)
@@ -189,6 +189,7 @@ LtLayout lt_layout(int64_t n_out)
     L.finals = take(seg_finals_bytes(B));
     L.start = take((size_t)seg_count(B));
     const size_t tb = B <= kTableMaxBuckets ? (size_t)B : 0; // transition tables (wide buckets)
+    L.yr = take(8 * tb);
     L.cand_cnt = take(4 * tb);
     L.cand = take(4 * tb * kCandMax);
     L.tab = take(8 * tb * kCandMax);
@@ -841,18 +842,22 @@ int mmlttb_lttb(int xk, const int64_t *x, const float *y, int64_t n, int64_t n_o
     double *MX = at<double>(ws, L.MX), *MY = at<double>(ws, L.MY);
     const Split bk = make_split(n - 2, B);
     const int64_t maxb = bk.q + (bk.r ? 1 : 0);
+    const bool seg = use_segmented_chain(maxb);
+    // wide buckets: transition tables unless the sequential pass is asked for
+    const bool tables = !seg && maxb > 64 && tuning().chain != kChainSequential && B <= kTableMaxBuckets;
     if (maxb <= 64) {
         MMLTTB_LAUNCH("bucket_mean", s, launch_bucket_mean_small(x, y, nullptr, n, B, MX, MY, s));
     } else {
-        MMLTTB_LAUNCH("bucket_mean_wide", s, launch_bucket_mean_wide(x, y, n, B, MX, MY, s));
+        float2 *yr = tables ? at<float2>(ws, L.yr) : nullptr; // bucket y ranges, for the tables
+        MMLTTB_LAUNCH("bucket_mean_wide", s, launch_bucket_mean_wide(x, y, n, B, MX, MY, yr, s));
     }
-    if (use_segmented_chain(maxb)) {
+    if (seg) {
         const SegChainArgs a = seg_args(ws, L.path, L.finals, L.start, x, y, nullptr, n, B, MX, MY, maxb);
         MMLTTB_LAUNCH("lttb_chain_seg", s, launch_lttb_chain_seg(a, nullptr, out_idx, s));
-    } else if (tuning().chain != kChainSequential && B <= kTableMaxBuckets) {
+    } else if (tables) {
         int32_t *cnt = at<int32_t>(ws, L.cand_cnt), *cand = at<int32_t>(ws, L.cand);
         int2 *tab = at<int2>(ws, L.tab);
-        MMLTTB_LAUNCH("lttb_hull", s, launch_lttb_hull(x, y, n, B, MX, MY, cnt, cand, s));
+        MMLTTB_LAUNCH("lttb_hull", s, launch_lttb_hull(x, y, n, B, MX, MY, at<float2>(ws, L.yr), cnt, cand, s));
         MMLTTB_LAUNCH("lttb_tables", s, launch_lttb_tables(x, y, n, B, MX, MY, cnt, cand, tab, s));
         MMLTTB_LAUNCH("lttb_table_walk", s, launch_lttb_table_walk(x, y, n, B, MX, MY, cnt, cand, tab, out_idx, s));
     } else if (maxb <= kChainStage) {

@@ -201,8 +201,9 @@ hipError_t launch_xbin_finish(const int64_t *P, const int64_t *m_true, int64_t n
 
 hipError_t launch_bucket_mean_small(const int64_t *XP, const float *YP, const int64_t *m_ptr, int64_t m_const,
                                     int64_t B, double *MX, double *MY, hipStream_t s);
+// YR (may be NULL): the y range of every bucket, for the table form.
 hipError_t launch_bucket_mean_wide(const int64_t *X, const float *Y, int64_t m, int64_t B, double *MX, double *MY,
-                                   hipStream_t s);
+                                   float2 *YR, hipStream_t s);
 hipError_t launch_lttb_chain(const int64_t *XP, const float *YP, const int64_t *m_ptr, int64_t m_const, int64_t B,
                              const double *MX, const double *MY, const int64_t *Pmap, int64_t *out, hipStream_t s);
 hipError_t launch_lttb_chain_seg(const SegChainArgs &a, const int64_t *Pmap, int64_t *out, hipStream_t s);
@@ -217,7 +218,7 @@ constexpr int kCandMax = 64;
 // Largest bucket count the table form runs (its grids and tables grow with B).
 constexpr int64_t kTableMaxBuckets = (int64_t)1 << 24;
 hipError_t launch_lttb_hull(const int64_t *X, const float *Y, int64_t n, int64_t B, const double *MX, const double *MY,
-                            int32_t *cand_cnt, int32_t *cand, hipStream_t s);
+                            const float2 *YR, int32_t *cand_cnt, int32_t *cand, hipStream_t s);
 hipError_t launch_lttb_tables(const int64_t *X, const float *Y, int64_t n, int64_t B, const double *MX,
                               const double *MY, const int32_t *cand_cnt, const int32_t *cand, int2 *tab,
                               hipStream_t s);

@@ -64,14 +64,47 @@ __global__ __launch_bounds__(256) void k_bucket_mean_small(const int64_t *__rest
 }
 
 // One workgroup (256 threads) per bucket (whole-series LTTB: large buckets).
+// Wide buckets: one workgroup per bucket k sums bucket k+1 (8 loads per
+// thread in flight). With YR != NULL it also records the y range of the
+// bucket it reads (YR[k + 1]; workgroup 0 adds YR[0] by one more pass), which
+// the table form of the chain uses.
 __global__ __launch_bounds__(256) void k_bucket_mean_wide(const int64_t *__restrict__ X, const float *__restrict__ Y,
                                                           int64_t m, int64_t B, double *__restrict__ MX,
-                                                          double *__restrict__ MY)
+                                                          double *__restrict__ MY, float2 *__restrict__ YR)
 {
     __shared__ int64_t s_limb[4][9];
     __shared__ int64_t s_xlo[4], s_xhi[4];
+    __shared__ float s_lo[4], s_hi[4];
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     const Split bk = make_split(m - 2, B);
+    const float kInf = __int_as_float(0x7f800000);
+    // the block's y range from per-thread lo, hi into *out (all threads call)
+    auto yrange = [&](float lo, float hi, float2 *out) {
+        lo = wave_min_f32(lo);
+        hi = wave_max_f32(hi);
+        if (lane == 0) {
+            s_lo[wid] = lo;
+            s_hi[wid] = hi;
+        }
+        __syncthreads();
+        if (tid == 0) {
+            for (int w = 1; w < (int)(blockDim.x >> 6); ++w) {
+                lo = fminf(lo, s_lo[w]);
+                hi = fmaxf(hi, s_hi[w]);
+            }
+            *out = make_float2(lo, hi);
+        }
+        __syncthreads();
+    };
+    if (YR && blockIdx.x == 0) { // bucket 0, which no mean reads
+        const int64_t g0 = 1, g1 = 1 + split_lo(bk, 1);
+        float lo = kInf, hi = -kInf;
+        for (int64_t i = g0 + tid; i < g1; i += blockDim.x) {
+            lo = fminf(lo, Y[i]);
+            hi = fmaxf(hi, Y[i]);
+        }
+        yrange(lo, hi, &YR[0]);
+    }
     for (int64_t k = blockIdx.x; k < B; k += gridDim.x) {
         int64_t g0, g1;
         next_bucket_range(bk, m, k, g0, g1);
@@ -79,10 +112,33 @@ __global__ __launch_bounds__(256) void k_bucket_mean_wide(const int64_t *__restr
         F32ExactSum sy;
         sx.clear();
         sy.clear();
-        for (int64_t i = g0 + tid; i < g1; i += blockDim.x) {
+        float lo = kInf, hi = -kInf;
+        constexpr int kDepth = 8;
+        int64_t i = g0 + tid;
+        for (; i + (kDepth - 1) * 256 < g1; i += kDepth * 256) {
+            int64_t xs[kDepth];
+            float ys[kDepth];
+#pragma unroll
+            for (int u = 0; u < kDepth; ++u) {
+                xs[u] = X ? X[i + u * 256] : i + u * 256;
+                ys[u] = Y[i + u * 256];
+            }
+#pragma unroll
+            for (int u = 0; u < kDepth; ++u) {
+                sx.add(xs[u]);
+                sy.add(ys[u]);
+                lo = fminf(lo, ys[u]);
+                hi = fmaxf(hi, ys[u]);
+            }
+        }
+        for (; i < g1; i += blockDim.x) {
             sx.add(X ? X[i] : i);
             sy.add(Y[i]);
+            lo = fminf(lo, Y[i]);
+            hi = fmaxf(hi, Y[i]);
         }
+        if (YR && k + 1 < B)
+            yrange(lo, hi, &YR[k + 1]);
         sy.normalize();
         // wave sums: normalized limbs are < 2^32 (limb 8 small), 64 of them fit
 #pragma unroll
@@ -90,8 +146,8 @@ __global__ __launch_bounds__(256) void k_bucket_mean_wide(const int64_t *__restr
 #pragma unroll
             for (int q = 0; q < 9; ++q)
                 sy.limb[q] += __shfl_xor(sy.limb[q], off);
-            int64_t lo = (int64_t)(uint64_t)sx.s, hi = (int64_t)(sx.s >> 64);
-            int64_t olo = __shfl_xor(lo, off), ohi = __shfl_xor(hi, off);
+            int64_t lo64 = (int64_t)(uint64_t)sx.s, hi64 = (int64_t)(sx.s >> 64);
+            int64_t olo = __shfl_xor(lo64, off), ohi = __shfl_xor(hi64, off);
             sx.s += (__int128)(((unsigned __int128)(uint64_t)ohi << 64) | (uint64_t)olo);
         }
         if (lane == 0) {
@@ -396,9 +452,9 @@ hipError_t launch_bucket_mean_small(const int64_t *XP, const float *YP, const in
 }
 
 hipError_t launch_bucket_mean_wide(const int64_t *X, const float *Y, int64_t m, int64_t B, double *MX, double *MY,
-                                   hipStream_t s)
+                                   float2 *YR, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_bucket_mean_wide, dim3(grid_for(B, 1, 65536)), dim3(256), 0, s, X, Y, m, B, MX, MY);
+    hipLaunchKernelGGL(k_bucket_mean_wide, dim3(grid_for(B, 1, 65536)), dim3(256), 0, s, X, Y, m, B, MX, MY, YR);
     return hipGetLastError();
 }
 

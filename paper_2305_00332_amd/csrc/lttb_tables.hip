@@ -64,6 +64,7 @@ constexpr int kTabWGs = 2;
 // (entries past them, rare, are read from global memory).
 constexpr int kWalkWindow = 128;
 constexpr int kWalkSlots = 16;
+constexpr int kWalkSeg = 16; // buckets per segment followed by one thread
 
 __device__ inline double xval(const int64_t *__restrict__ X, int64_t p) { return X ? (double)X[p] : (double)p; }
 
@@ -111,28 +112,12 @@ __device__ inline bool chain_pop(double ax, double ay, double bx, double by, dou
     return upper ? cr > tol : cr < -tol;
 }
 
-__device__ inline double block_min_f64(double v, double *red)
-{
-    const int tid = threadIdx.x, lane = tid & (kWave - 1), wid = tid / kWave;
-    v = -wave_max_f64(-v);
-    __syncthreads();
-    if (lane == 0)
-        red[wid] = v;
-    __syncthreads();
-    double r = red[0];
-    for (int q = 1; q < kHullThreads / kWave; ++q)
-        r = red[q] < r ? red[q] : r;
-    return r;
-}
-
-__device__ inline double block_max_f64(double v, double *red) { return -block_min_f64(-v, red); }
-
 __global__ __launch_bounds__(kHullThreads) void k_lttb_hull(const int64_t *__restrict__ X, const float *__restrict__ Y,
                                                             int64_t n, int64_t B, const double *__restrict__ MX,
                                                             const double *__restrict__ MY,
+                                                            const float2 *__restrict__ YR,
                                                             int32_t *__restrict__ cand_cnt, int32_t *__restrict__ cand)
 {
-    __shared__ double red[kHullThreads / kWave];
     __shared__ double sx[kSurvMax], sy[kSurvMax], tx[kSurvMax], ty[kSurvMax];
     __shared__ int32_t si[kSurvMax], ti[kSurvMax];
     __shared__ double cxs[2][kChainMax], cys[2][kChainMax];
@@ -152,13 +137,8 @@ __global__ __launch_bounds__(kHullThreads) void k_lttb_hull(const int64_t *__res
     const double inf = __longlong_as_double(0x7ff0000000000000ll);
 
     // slope range from the predecessors' bounding box (M_b lies right of it)
-    double plo = inf, phi = -inf;
-    scan_points(nullptr, Y, ps + tid, pe, kHullThreads, [&](int64_t, double, double v) {
-        plo = v < plo ? v : plo;
-        phi = v > phi ? v : phi;
-    });
-    plo = block_min_f64(plo, red);
-    phi = block_max_f64(phi, red);
+    const float2 pr = b == 0 ? make_float2(Y[0], Y[0]) : YR[b - 1];
+    const double plo = (double)pr.x, phi = (double)pr.y;
     const double mxb = MX[b], myb = MY[b];
     const double dx0 = mxb - xval(X, ps), dx1 = mxb - xval(X, pe - 1); // both > 0
     const double c0 = (myb - phi) / dx0, c1 = (myb - phi) / dx1, c2 = (myb - plo) / dx0, c3 = (myb - plo) / dx1;
@@ -170,13 +150,7 @@ __global__ __launch_bounds__(kHullThreads) void k_lttb_hull(const int64_t *__res
 
     // the bucket's y span sets the spacing of kSlopes slopes across [g0, g1]
     // (even in angle in the bucket's own scale)
-    double ylo = inf, yhi = -inf;
-    scan_points(nullptr, Y, s + tid, e, kHullThreads, [&](int64_t, double, double v) {
-        ylo = v < ylo ? v : ylo;
-        yhi = v > yhi ? v : yhi;
-    });
-    ylo = block_min_f64(ylo, red);
-    yhi = block_max_f64(yhi, red);
+    const double ylo = (double)YR[b].x, yhi = (double)YR[b].y;
     const double x0 = xval(X, s);
     double r = (xval(X, e - 1) - x0) / (yhi - ylo);
     r = (r > 0.0 && r < inf) ? r : 1.0;
@@ -457,9 +431,13 @@ __global__ __launch_bounds__(kTableThreads) void k_lttb_tables(const int64_t *__
     }
 }
 
-// One workgroup of 1024 threads. Thread 0 follows the tables through LDS
-// windows of kWalkWindow buckets; where the slot is -1 the whole workgroup
-// scans that bucket for the pick of the known predecessor.
+// One workgroup of 1024 threads. Windows of kWalkWindow buckets: their first
+// kWalkSlots table entries are staged in LDS, every segment of kWalkSeg
+// buckets is followed from every entry slot at once (one thread each), thread
+// 0 links the segments from the true entry slot, and the picks of the window
+// are written in parallel. The window ends early where a slot is -1 (the
+// predecessor is not a candidate: the whole workgroup then scans that bucket
+// for its pick) or past the staged entries (one step from global memory).
 __global__ __launch_bounds__(1024) void k_lttb_table_walk(const int64_t *__restrict__ X, const float *__restrict__ Y,
                                                           int64_t n, int64_t B, const double *__restrict__ MX,
                                                           const double *__restrict__ MY,
@@ -467,7 +445,10 @@ __global__ __launch_bounds__(1024) void k_lttb_table_walk(const int64_t *__restr
                                                           const int32_t *__restrict__ cand,
                                                           const int2 *__restrict__ tab, int64_t *__restrict__ out)
 {
+    constexpr int kSegs = kWalkWindow / kWalkSeg;
     __shared__ int2 sT[kWalkWindow * kWalkSlots];
+    __shared__ uint8_t spath[kSegs][kWalkSlots][kWalkSeg]; // slot used at each bucket of the segment
+    __shared__ int32_t sdone[kSegs][kWalkSlots], sexit[kSegs][kWalkSlots], sent[kSegs];
     __shared__ double s_area[16];
     __shared__ int64_t s_idx[16];
     __shared__ int64_t s_k, s_a;
@@ -478,34 +459,68 @@ __global__ __launch_bounds__(1024) void k_lttb_table_walk(const int64_t *__restr
     int64_t k = 0, a = 0; // next bucket to pick in, previous pick (a position)
     int32_t slot = 0;     // a's slot among the candidates of bucket k-1 (point 0 for k = 0)
     while (k < B) {
-        if (slot >= 0) {
+        if (slot >= 0 && slot < kWalkSlots) {
             const int64_t k1 = k + kWalkWindow < B ? k + kWalkWindow : B;
-            const int64_t words = (k1 - k) * kWalkSlots;
-            for (int64_t q = tid; q < words; q += blockDim.x)
+            const int W = (int)(k1 - k), nseg = (W + kWalkSeg - 1) / kWalkSeg;
+            for (int q = tid; q < W * kWalkSlots; q += blockDim.x)
                 sT[q] = tab[(k + q / kWalkSlots) * kCandMax + q % kWalkSlots];
             __syncthreads();
-            if (tid == 0) {
-                SplitWalker w;
-                w.init(bk, k);
-                int64_t kk = k;
-                int32_t sl = slot;
-                while (kk < k1 && sl >= 0) {
-                    const int2 t = sl < kWalkSlots ? sT[(kk - k) * kWalkSlots + sl] : tab[kk * kCandMax + sl];
-                    a = 1 + w.lo + t.x;
-                    out[kk + 1] = a;
-                    sl = t.y;
-                    w.advance(bk);
-                    ++kk;
+            if (tid < nseg * kWalkSlots) { // segment g from entry slot e
+                const int g = tid / kWalkSlots, e = tid % kWalkSlots;
+                const int len = W - g * kWalkSeg < kWalkSeg ? W - g * kWalkSeg : kWalkSeg;
+                int sl = e, i = 0;
+                for (; i < len && sl >= 0 && sl < kWalkSlots; ++i) {
+                    spath[g][e][i] = (uint8_t)sl;
+                    sl = sT[(g * kWalkSeg + i) * kWalkSlots + sl].y;
                 }
-                s_k = kk;
-                s_a = a;
-                s_slot = sl;
+                sdone[g][e] = i; // steps taken from the tables
+                sexit[g][e] = sl; // the slot after them
             }
             __syncthreads();
-            k = s_k;
+            if (tid == 0) {
+                int cur = slot;
+                int64_t stop = k1;
+                for (int g = 0; g < nseg; ++g) {
+                    sent[g] = cur;
+                    const int len = W - g * kWalkSeg < kWalkSeg ? W - g * kWalkSeg : kWalkSeg;
+                    const int done = sdone[g][cur];
+                    cur = sexit[g][cur];
+                    if (done < len) {
+                        stop = k + g * kWalkSeg + done;
+                        break;
+                    }
+                    if (cur < 0 || cur >= kWalkSlots) { // the next segment cannot start from the tables
+                        stop = k + (int64_t)g * kWalkSeg + len; // <= k1: the last segment may be short
+                        break;
+                    }
+                }
+                s_k = stop;
+                s_slot = cur;
+            }
+            __syncthreads();
+            const int64_t stop = s_k; // k < stop <= k1 <= B
+            for (int t = tid; t < (int)(stop - k); t += blockDim.x) { // the picks of buckets k .. stop-1
+                const int g = t / kWalkSeg, i = t % kWalkSeg;
+                const int sl = spath[g][sent[g]][i];
+                const int64_t pick = 1 + split_lo(bk, k + t) + sT[t * kWalkSlots + sl].x;
+                out[k + t + 1] = pick;
+                if (k + t + 1 == stop)
+                    s_a = pick;
+            }
+            __syncthreads();
+            k = stop;
             a = s_a;
             slot = s_slot;
             __syncthreads();
+            continue;
+        }
+        if (slot >= kWalkSlots) { // an entry past the staged ones: one step from global memory
+            const int2 t = tab[k * kCandMax + slot];
+            a = 1 + split_lo(bk, k) + t.x;
+            if (tid == 0)
+                out[k + 1] = a;
+            slot = t.y;
+            ++k;
             continue;
         }
         // slot -1: scan bucket k for the pick of a
@@ -561,12 +576,12 @@ __global__ __launch_bounds__(1024) void k_lttb_table_walk(const int64_t *__restr
 }
 
 hipError_t launch_lttb_hull(const int64_t *X, const float *Y, int64_t n, int64_t B, const double *MX, const double *MY,
-                            int32_t *cand_cnt, int32_t *cand, hipStream_t s)
+                            const float2 *YR, int32_t *cand_cnt, int32_t *cand, hipStream_t s)
 {
     if (B < 2)
         return hipSuccess;
-    hipLaunchKernelGGL(k_lttb_hull, dim3((unsigned)(B - 1)), dim3(kHullThreads), 0, s, X, Y, n, B, MX, MY, cand_cnt,
-                       cand);
+    hipLaunchKernelGGL(k_lttb_hull, dim3((unsigned)(B - 1)), dim3(kHullThreads), 0, s, X, Y, n, B, MX, MY, YR,
+                       cand_cnt, cand);
     return hipGetLastError();
 }
 
