@@ -171,7 +171,7 @@ __global__ __launch_bounds__(kHullThreads) void k_lttb_hull(const int64_t *__res
         fmin_[i] = inf;
         omax[i] = omin[i] = 0;
     }
-    scan_points<2>(X, Y, s + tid, e, kHullThreads, [&](int64_t p, double xr, double y) {
+    scan_points<4>(X, Y, s + tid, e, kHullThreads, [&](int64_t p, double xr, double y) {
         const double x = xr - x0;
         const int32_t o = (int32_t)(p - s);
 #pragma unroll
@@ -219,30 +219,34 @@ __global__ __launch_bounds__(kHullThreads) void k_lttb_hull(const int64_t *__res
     }
 
     // survivors (appended in any order, then sorted by position): points on
-    // the outer side of a chord between tangent points of neighbouring slopes
-    scan_points<2>(X, Y, s + tid, e, kHullThreads, [&](int64_t p, double xr, double y) {
+    // the outer side of a chord between tangent points of neighbouring slopes.
+    // Such a point also lies outside the chord between the outermost tangent
+    // points (the arc between them is concave), which is tested first.
+    auto side = [&](int i0, int i1, int gi, double sgn, double x, double y) {
+        // > 0 outside the line through tangent points i0, i1 (slopes gs[gi], gs[gi + 1])
+        const double ax = tpx[i0], ay = tpy[i0];
+        double ex = tpx[i1] - ax, ey = tpy[i1] - ay;
+        if (ex < 0.0) { // orient left to right
+            ex = -ex;
+            ey = -ey;
+        }
+        if (ex == 0.0 && ey == 0.0) { // one tangent point: the line of a slope between through it
+            const double g = 0.5 * (gs[gi] + gs[gi + 1]);
+            const double d = (y - ay) - g * (x - ax);
+            return sgn * d >= -kSideTol * (fabs(y - ay) + fabs(g * (x - ax)));
+        }
+        const double t1 = ex * (y - ay), t2 = ey * (x - ax);
+        return sgn * (t1 - t2) >= -kSideTol * (fabs(t1) + fabs(t2));
+    };
+    scan_points<4>(X, Y, s + tid, e, kHullThreads, [&](int64_t p, double xr, double y) {
         const double x = xr - x0;
-        // side of the line through tangent points i and i + 1 (of slopes
-        // gs[i], gs[i + 1]); > 0 on the outer side
-        auto outer = [&](int i, int base, double sgn) {
-            const double ax = tpx[base + i], ay = tpy[base + i];
-            double ex = tpx[base + i + 1] - ax, ey = tpy[base + i + 1] - ay;
-            if (ex < 0.0) { // orient left to right
-                ex = -ex;
-                ey = -ey;
-            }
-            if (ex == 0.0 && ey == 0.0) { // one tangent point: the line of a slope between through it
-                const double g = 0.5 * (gs[i] + gs[i + 1]);
-                const double d = (y - ay) - g * (x - ax);
-                return sgn * d >= -kSideTol * (fabs(y - ay) + fabs(g * (x - ax)));
-            }
-            const double t1 = ex * (y - ay), t2 = ey * (x - ax);
-            return sgn * (t1 - t2) >= -kSideTol * (fabs(t1) + fabs(t2));
-        };
+        const bool up = side(0, kSlopes - 1, 0, 1.0, x, y), dn = side(kSlopes, 2 * kSlopes - 1, 0, -1.0, x, y);
         bool keep = wide;
-#pragma unroll
-        for (int i = 0; i + 1 < kSlopes; ++i)
-            keep = keep || outer(i, 0, 1.0) || outer(i, kSlopes, -1.0);
+        if (!keep && (up || dn)) {
+            for (int i = 0; i + 1 < kSlopes; ++i)
+                keep = keep || (up && side(i, i + 1, i, 1.0, x, y)) ||
+                       (dn && side(kSlopes + i, kSlopes + i + 1, i, -1.0, x, y));
+        }
         if (keep) {
             const int q = atomicAdd(&nsurv, 1);
             if (q < kSurvMax) {
