@@ -535,7 +535,24 @@ def bench_comparator(args):
     c0 = time.perf_counter()
     want_l = oracle.lttb(y_np, n_out, x_np)
     t_lc = time.perf_counter() - c0
+    ops.profile_enable(True)
+    ops.profile_reset()
+    ops.lttb(y, n_out, x=x)
+    torch.cuda.synchronize()
+    ops.profile_enable(False)
+    k_l = {}
+    for k in ("bucket_mean_wide", "lttb_hull", "lttb_tables", "lttb_table_walk"):
+        tot, cnt = ops.profile_read(k)
+        if cnt:
+            k_l[k] = round(tot / cnt, 4)
+    old = ops.get_tuning()
+    ops.set_tuning(0, 0, ops.CHAIN_SEQUENTIAL)
+    t_seq, out_seq = gpu_time(lambda: ops.lttb(y, n_out, x=x), 1)
+    ops.set_tuning(*old)
     res["lttb"] = {"gpu_ms": round(t_l * 1e3, 4), "gpu_gpts_per_s": round(n / t_l / 1e9, 3),
+                   "kernel_ms": k_l, "form": "transition tables over hull candidates",
+                   "sequential_form_ms": round(t_seq * 1e3, 3),
+                   "sequential_form_identical": bool(torch.equal(out_seq, out_l)),
                    "cpu_oracle_s": round(t_lc, 3), "parity_vs_oracle": bool(np.array_equal(out_l.cpu().numpy(), want_l))}
     for r_ps in (2, 4, 8):
         log(f"comparator: MinMaxLTTB r_ps={r_ps}")
