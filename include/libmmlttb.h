@@ -92,8 +92,10 @@ const char *mmlttb_last_error(void);
  * mmlttb_minmax). Returns 0 on invalid arguments. */
 size_t mmlttb_workspace_size(int64_t n, int64_t n_out, int32_t r_ps);
 
-/* Workspace bytes for mmlttb_lttb (next-bucket means and chain scratch);
- * independent of n. Returns 0 on invalid arguments. */
+/* Workspace bytes for mmlttb_lttb (next-bucket means and chain scratch:
+ * about 850 bytes per bucket for n_out - 2 <= 2^24 buckets, which includes the
+ * candidate lists and transition tables of wide buckets); independent of n.
+ * Returns 0 on invalid arguments. */
 size_t mmlttb_lttb_workspace_size(int64_t n, int64_t n_out);
 
 /* MinMax preselection alone (section 2.2.1 MinMax; section 3 step (i)).
@@ -115,7 +117,11 @@ int mmlttb_minmax(int xk, const int64_t *x, const float *y, int64_t n, int64_t n
  * mean is the exact sum of x and of y, each rounded once to binary64, divided
  * by the count (last bucket: the last point); the area is
  * |(Xa-MX)*(Yj-Ya) - (Xa-Xj)*(MY-Ya)| in binary64, one rounding per operation,
- * and ties go to the lowest index. n <= n_out returns 0..n-1. */
+ * and ties go to the lowest index. n <= n_out returns 0..n-1. Buckets wider
+ * than 64 points are run by transition tables (each candidate predecessor's
+ * pick computed in parallel with the same arithmetic, exact scans where a
+ * pick is not a candidate) unless the sequential pass is chosen with
+ * mmlttb_set_tuning; both give the same indices. */
 int mmlttb_lttb(int xk, const int64_t *x, const float *y, int64_t n, int64_t n_out, int64_t *out_idx, void *ws,
                 size_t ws_bytes, void *stream);
 
