@@ -346,6 +346,13 @@ __global__ __launch_bounds__(kWave) void k_batch_chain_seq(BatchPtrs b)
             }
             const double wb = wave_max_f64(best);
             const int64_t sel = wave_min_i64(best == wb ? bj : INT64_MAX);
+            if (sel == INT64_MAX) { // no area above -1 (all NaN): the bucket's first point stands
+                ax = (double)XP[s0];
+                ay = (double)YP[s0];
+                if (lane == 0)
+                    out[k + 1] = s0;
+                continue;
+            }
             const int win = __builtin_ctzll(__builtin_amdgcn_ballot_w64(bj == sel));
             ax = readlane_f64(bx, win);
             ay = readlane_f64(by, win);

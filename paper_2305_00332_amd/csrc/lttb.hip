@@ -406,9 +406,15 @@ __global__ __launch_bounds__(1024) void k_lttb_chain_wide(const int64_t *__restr
                     bw = q;
                 }
             }
+            if (bi == INT64_MAX) { // no area above -1 (all NaN): the bucket's first point stands
+                bi = s0;
+                s_ax = (double)(X ? X[s0] : s0);
+                s_ay = (double)Y[s0];
+            } else {
+                s_ax = s_x[bw];
+                s_ay = s_y[bw];
+            }
             out[k + 1] = bi;
-            s_ax = s_x[bw];
-            s_ay = s_y[bw];
         }
         __syncthreads();
         ax = s_ax;

@@ -415,9 +415,16 @@ __device__ inline int block_exclusive_scan(int c, int *wave_tot, int &total)
 // Decode the bin keys into the sorted distinct preselection P (section 3: the
 // first and last points join the per-bin extrema). Bins are disjoint and in
 // index order, so emitting each bin's pair in index order yields P sorted.
-// Called by a whole workgroup of 1024 threads. Optionally writes XP (raw x,
-// gathered, or the index for implicit x) and YP (decoded from the keys, so y
-// is not read again) at the same time. wave_tot: 17 ints of LDS.
+// Called by a whole workgroup (blockDim a multiple of 64, at most 1024). A
+// round covers kCompactBins slabs of blockDim consecutive bins, bin
+// base + u*blockDim + tid for thread tid: the keys of all slabs are decoded
+// and scanned slab by slab, then the x gathers of all of them are in flight
+// together. Optionally writes
+// XP (raw x, gathered, or the index for implicit x) and YP (decoded from the
+// keys, so y is not read again). A key offset past its bin (keys no part ever
+// reached, or values that never compare, such as NaN) decodes to the bin's
+// first point, so every index stays inside its bin. wave_tot: 17 ints of LDS.
+constexpr int kCompactBins = 4;
 __device__ inline void compact_keys(const unsigned long long *__restrict__ keys, const Split &bins, int64_t n,
                                     const int64_t *__restrict__ x, const float *__restrict__ y,
                                     int64_t *__restrict__ P, int64_t *__restrict__ XP, float *__restrict__ YP,
@@ -433,40 +440,68 @@ __device__ inline void compact_keys(const unsigned long long *__restrict__ keys,
         }
     }
     const int64_t nb = bins.parts;
-    for (int64_t base = 0; base < nb; base += blockDim.x) {
-        const int64_t b = base + tid;
-        int c = 0;
-        int64_t i0 = 0, i1 = 0;
-        float v0 = 0.0f, v1 = 0.0f;
-        if (b < nb) {
-            const int64_t blo = 1 + split_lo(bins, b);
-            const unsigned long long kmin = keys[2 * b], kmax = keys[2 * b + 1];
-            const int64_t imin = blo + min_key_offset(kmin);
-            const int64_t imax = blo + max_key_offset(kmax);
-            const bool lo_min = imin < imax;
-            i0 = lo_min ? imin : imax;
-            i1 = lo_min ? imax : imin;
-            v0 = key_value(lo_min ? kmin : kmax);
-            v1 = key_value(lo_min ? kmax : kmin);
-            c = (imin == imax) ? 1 : 2;
-        }
-        int total;
-        const int64_t off = running + block_exclusive_scan(c, wave_tot, total);
-        if (c >= 1) {
-            P[off] = i0;
-            if (XP) {
-                XP[off] = x ? x[i0] : i0;
-                YP[off] = v0;
+    for (int64_t base = 0; base < nb; base += (int64_t)blockDim.x * kCompactBins) {
+        int64_t i0[kCompactBins], i1[kCompactBins], off[kCompactBins];
+        float v0[kCompactBins], v1[kCompactBins];
+        int cnt[kCompactBins];
+        unsigned long long kmin[kCompactBins], kmax[kCompactBins];
+#pragma unroll
+        for (int u = 0; u < kCompactBins; ++u) {
+            const int64_t b = base + (int64_t)u * blockDim.x + tid;
+            if (b < nb) {
+                kmin[u] = keys[2 * b];
+                kmax[u] = keys[2 * b + 1];
             }
         }
-        if (c == 2) {
-            P[off + 1] = i1;
-            if (XP) {
-                XP[off + 1] = x ? x[i1] : i1;
-                YP[off + 1] = v1;
+#pragma unroll
+        for (int u = 0; u < kCompactBins; ++u) {
+            const int64_t b = base + (int64_t)u * blockDim.x + tid;
+            cnt[u] = 0;
+            i0[u] = i1[u] = 0;
+            v0[u] = v1[u] = 0.0f;
+            if (b < nb) {
+                const int64_t blo = split_lo(bins, b), len = split_lo(bins, b + 1) - blo;
+                int64_t omin = min_key_offset(kmin[u]), omax = max_key_offset(kmax[u]);
+                omin = omin < len ? omin : 0;
+                omax = omax < len ? omax : 0;
+                const int64_t imin = 1 + blo + omin, imax = 1 + blo + omax;
+                const float vmin = key_value(kmin[u]), vmax = key_value(kmax[u]);
+                const bool lo_min = imin < imax;
+                i0[u] = lo_min ? imin : imax;
+                i1[u] = lo_min ? imax : imin;
+                v0[u] = lo_min ? vmin : vmax;
+                v1[u] = lo_min ? vmax : vmin;
+                cnt[u] = (imin == imax) ? 1 : 2;
+            }
+            int total;
+            off[u] = running + block_exclusive_scan(cnt[u], wave_tot, total);
+            running += total;
+        }
+        int64_t xs0[kCompactBins], xs1[kCompactBins];
+        if (XP) {
+#pragma unroll
+            for (int u = 0; u < kCompactBins; ++u) { // gathers first, all in flight
+                xs0[u] = (x && cnt[u] >= 1) ? x[i0[u]] : i0[u];
+                xs1[u] = (x && cnt[u] == 2) ? x[i1[u]] : i1[u];
             }
         }
-        running += total;
+#pragma unroll
+        for (int u = 0; u < kCompactBins; ++u) {
+            if (cnt[u] >= 1) {
+                P[off[u]] = i0[u];
+                if (XP) {
+                    XP[off[u]] = xs0[u];
+                    YP[off[u]] = v0[u];
+                }
+            }
+            if (cnt[u] == 2) {
+                P[off[u] + 1] = i1[u];
+                if (XP) {
+                    XP[off[u] + 1] = xs1[u];
+                    YP[off[u] + 1] = v1[u];
+                }
+            }
+        }
     }
     if (tid == 0) {
         P[running] = n - 1;
