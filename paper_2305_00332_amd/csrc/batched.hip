@@ -125,66 +125,85 @@ __device__ inline void strided_minmax(const float *tile, int q0, int end, int st
 
 static_assert(kTileThreads == 256, "k_batch_small derives lanes per bin from 2^8 threads");
 
-template <int kTilePoints>
-__global__ __launch_bounds__(kTileThreads) void k_batch_small(BatchPtrs b)
+// One small-bin tile: its bins, its point range [lo, hi) split into an
+// aligned body of nvec float4 and at most 3 head and 3 tail points.
+struct SmallTile {
+    const float *y;
+    unsigned long long *keys; // key pair of the tile's first bin
+    int64_t lo, hi, body, nvec, tail0, nb, bq, br, rem0;
+    double inv;
+    int nbt, lg;
+};
+
+__device__ inline SmallTile plan_small_tile(const BatchPtrs &b, int64_t t)
 {
-    __shared__ float tile[kTilePoints];
-    __shared__ int32_t bstart[kTileThreads + 1]; // bin starts, relative to the tile's first point
-    const int tid = threadIdx.x;
-    const int64_t t = blockIdx.x;
-    const int64_t total = b.n_small_tiles;
-    if (t >= total)
-        return;
-    const int64_t s = find_owner(b.segs, b.hdr->own_small, total, t, [](const BatchSeg &g) { return g.ti0; });
+    const int64_t s = find_owner(b.segs, b.hdr->own_small, b.n_small_tiles, t, [](const BatchSeg &g) { return g.ti0; });
     const BatchSeg &g = b.segs[s];
-    const int G = g.tile_bins;        // power of two, 4..256
-    const int lg = 8 - __builtin_ctz((unsigned)G); // log2 of the lanes per bin (kTileThreads = 2^8)
-    const int tpb = 1 << lg;          // lanes per bin: power of two <= 64
-    const int64_t nb = g.bins.parts, bq = g.bins.q, br = g.bins.r;
+    SmallTile T;
+    const int G = g.tile_bins;                 // power of two, 4..256
+    T.lg = 8 - __builtin_ctz((unsigned)G);     // log2 of the lanes per bin (kTileThreads = 2^8)
+    T.nb = g.bins.parts;
+    T.bq = g.bins.q;
+    T.br = g.bins.r;
     const int64_t bb0 = (t - g.ti0) * G;
-    const int nbt = (int)((bb0 + G < nb) ? G : nb - bb0); // bins in this tile
+    T.nbt = (int)((bb0 + G < T.nb) ? G : T.nb - bb0); // bins in this tile
     // Bin bb0 + i starts at split_lo(bb0) + i q + floor((rem0 + i r) / nb), with
     // rem0 = bb0 r mod nb; the planner routes only nb < 2^26 here, so every
     // numerator is below 2^52.
-    const double inv = 1.0 / (double)nb;
-    const int64_t t0 = bb0 * br;
-    const int64_t f0 = div_near(t0, nb, inv);
-    const int64_t rem0 = t0 - f0 * nb;
-    const int64_t lo = 1 + bb0 * bq + f0;
-    const int64_t hi = lo + (int64_t)nbt * bq + div_near(rem0 + (int64_t)nbt * br, nb, inv);
-    const float *__restrict__ y = b.y_base + g.offset;
-    // Stage [lo, hi): 16-byte loads of the aligned body, all issued before any
-    // use, plus at most 3 head and 3 tail points.
-    const uint64_t addr = (uint64_t)(uintptr_t)(y + lo);
+    T.inv = 1.0 / (double)T.nb;
+    const int64_t t0 = bb0 * T.br;
+    const int64_t f0 = div_near(t0, T.nb, T.inv);
+    T.rem0 = t0 - f0 * T.nb;
+    T.lo = 1 + bb0 * T.bq + f0;
+    T.hi = T.lo + (int64_t)T.nbt * T.bq + div_near(T.rem0 + (int64_t)T.nbt * T.br, T.nb, T.inv);
+    T.y = b.y_base + g.offset;
+    T.keys = b.keys + 2 * (g.key0 + bb0);
+    const uint64_t addr = (uint64_t)(uintptr_t)(T.y + T.lo);
     int64_t head = (int64_t)(((16u - (unsigned)(addr & 15u)) & 15u) >> 2);
-    head = head < hi - lo ? head : hi - lo;
-    const int64_t body = lo + head;
-    const int64_t nvec = (hi - body) >> 2;
-    const int64_t tail0 = body + 4 * nvec;
-    const f32x4 *__restrict__ v4 = reinterpret_cast<const f32x4 *>(y + body);
-    constexpr int kVecPerThread = kTilePoints / 4 / kTileThreads;
-    f32x4 d[kVecPerThread];
+    head = head < T.hi - T.lo ? head : T.hi - T.lo;
+    T.body = T.lo + head;
+    T.nvec = (T.hi - T.body) >> 2;
+    T.tail0 = T.body + 4 * T.nvec;
+    return T;
+}
+
+// Issue the tile's loads: 16-byte loads of the body, plus one head or tail
+// point for threads 0-2 and 4-6 (hq < 0: none).
+template <int kVec>
+__device__ inline void load_small_tile(const SmallTile &T, f32x4 (&d)[kVec], float &hv, int64_t &hq)
+{
+    const int tid = threadIdx.x;
+    const f32x4 *__restrict__ v4 = reinterpret_cast<const f32x4 *>(T.y + T.body);
 #pragma unroll
-    for (int u = 0; u < kVecPerThread; ++u) {
+    for (int u = 0; u < kVec; ++u) {
         const int64_t q = tid + (int64_t)u * kTileThreads;
-        if (q < nvec)
+        if (q < T.nvec)
             d[u] = __builtin_nontemporal_load(v4 + q);
     }
-    float hv = 0.0f;
-    int64_t hq = -1;
-    if (tid < head)
-        hq = lo + tid;
-    else if (tid >= 4 && tid < 4 + (hi - tail0))
-        hq = tail0 + (tid - 4);
+    hv = 0.0f;
+    hq = -1;
+    if (tid < T.body - T.lo)
+        hq = T.lo + tid;
+    else if (tid >= 4 && tid < 4 + (T.hi - T.tail0))
+        hq = T.tail0 + (tid - 4);
     if (hq >= 0)
-        hv = y[hq];
-    for (int i = tid; i <= nbt; i += kTileThreads)
-        bstart[i] = (int32_t)((int64_t)i * bq + div_near(rem0 + (int64_t)i * br, nb, inv));
+        hv = T.y[hq];
+}
+
+// Stage the loaded tile and its bin starts in LDS (the caller then waits at a
+// barrier before reduce_small_tile).
+template <int kVec>
+__device__ inline void stage_small_tile(const SmallTile &T, const f32x4 (&d)[kVec], float hv, int64_t hq, float *tile,
+                                        int32_t *bstart)
+{
+    const int tid = threadIdx.x;
+    for (int i = tid; i <= T.nbt; i += kTileThreads)
+        bstart[i] = (int32_t)((int64_t)i * T.bq + div_near(T.rem0 + (int64_t)i * T.br, T.nb, T.inv));
 #pragma unroll
-    for (int u = 0; u < kVecPerThread; ++u) {
+    for (int u = 0; u < kVec; ++u) {
         const int64_t q = tid + (int64_t)u * kTileThreads;
-        if (q < nvec) {
-            float *dst = tile + (body - lo) + 4 * q;
+        if (q < T.nvec) {
+            float *dst = tile + (T.body - T.lo) + 4 * q;
             dst[0] = d[u].x;
             dst[1] = d[u].y;
             dst[2] = d[u].z;
@@ -192,14 +211,19 @@ __global__ __launch_bounds__(kTileThreads) void k_batch_small(BatchPtrs b)
         }
     }
     if (hq >= 0)
-        tile[hq - lo] = hv;
-    __syncthreads();
-    const int gi = tid >> lg, sub = tid & (tpb - 1);
+        tile[hq - T.lo] = hv;
+}
+
+// Every bin's key pair from the staged tile: a power-of-two group of
+// 2^(8 - lg) lanes per bin.
+__device__ inline void reduce_small_tile(const SmallTile &T, const float *tile, const int32_t *bstart)
+{
+    const int tid = threadIdx.x;
+    const int tpb = 1 << T.lg; // lanes per bin: power of two <= 64
+    const int gi = tid >> T.lg, sub = tid & (tpb - 1);
     unsigned long long kmin = ~0ull, kmax = 0ull; // identities: lanes with no point never win
-    int bs = 0;
-    if (gi < nbt) {
-        bs = bstart[gi];
-        const int be = bstart[gi + 1];
+    if (gi < T.nbt) {
+        const int bs = bstart[gi], be = bstart[gi + 1];
         if (bs + sub < be) {
             float vmin, vmax;
             int imin, imax;
@@ -209,10 +233,48 @@ __global__ __launch_bounds__(kTileThreads) void k_batch_small(BatchPtrs b)
         }
     }
     group_minmax(tpb, kmin, kmax);
-    if (sub == 0 && gi < nbt) {
-        unsigned long long *k = b.keys + 2 * (g.key0 + bb0 + gi);
-        k[0] = kmin;
-        k[1] = kmax;
+    if (sub == 0 && gi < T.nbt) {
+        T.keys[2 * gi] = kmin;
+        T.keys[2 * gi + 1] = kmax;
+    }
+}
+
+// kSmallTilesPerBlock consecutive tiles per workgroup: a tile's loads are
+// issued once the previous tile is staged in LDS, so they are in flight while
+// that tile is reduced; the next tile's owner lookup overlaps the previous
+// tile's loads.
+constexpr int kSmallTilesPerBlock = 2;
+static_assert(kSmallTilesPerBlock == 2, "k_batch_small is written for two tiles per workgroup");
+
+template <int kTilePoints>
+__global__ __launch_bounds__(kTileThreads) void k_batch_small(BatchPtrs b)
+{
+    __shared__ float tile[kTilePoints];
+    __shared__ int32_t bstart[kTileThreads + 1]; // bin starts, relative to the tile's first point
+    constexpr int kVec = kTilePoints / 4 / kTileThreads;
+    const int64_t total = b.n_small_tiles;
+    const int64_t t0 = (int64_t)blockIdx.x * kSmallTilesPerBlock;
+    if (t0 >= total)
+        return;
+    const int64_t t1 = t0 + 1 < total ? t0 + 1 : -1; // kSmallTilesPerBlock = 2
+    f32x4 d0[kVec], d1[kVec];
+    float hv0, hv1;
+    int64_t hq0, hq1;
+    const SmallTile T0 = plan_small_tile(b, t0);
+    load_small_tile(T0, d0, hv0, hq0);
+    SmallTile T1;
+    if (t1 >= 0)
+        T1 = plan_small_tile(b, t1);
+    stage_small_tile(T0, d0, hv0, hq0, tile, bstart);
+    if (t1 >= 0)
+        load_small_tile(T1, d1, hv1, hq1);
+    __syncthreads();
+    reduce_small_tile(T0, tile, bstart);
+    if (t1 >= 0) {
+        __syncthreads(); // tile 0's readers are done with the LDS arrays
+        stage_small_tile(T1, d1, hv1, hq1, tile, bstart);
+        __syncthreads();
+        reduce_small_tile(T1, tile, bstart);
     }
 }
 
@@ -410,7 +472,7 @@ hipError_t launch_batch_small(const BatchPtrs &b, int tile, hipStream_t s)
 {
     if (b.n_small_tiles == 0)
         return hipSuccess;
-    const dim3 grid(cap_grid(b.n_small_tiles, 0x7fffffff));
+    const dim3 grid(cap_grid((b.n_small_tiles + kSmallTilesPerBlock - 1) / kSmallTilesPerBlock, 0x7fffffff));
     switch (tile) {
     case 2048:
         hipLaunchKernelGGL(k_batch_small<2048>, grid, dim3(kTileThreads), 0, s, b);
