@@ -20,7 +20,11 @@
  * - `stream` is a hipStream_t (NULL = the default stream). Work is enqueued on
  *   it in order; calls return before the device finishes. ws must not be
  *   reused by another call until the stream has passed this call.
- * - y: float32[n], finite (precondition, not checked on the device).
+ * - y: float32[n], finite (precondition, not checked on the device). With NaN
+ *   or infinite values the output is unspecified, but every index the float32
+ *   paths produce or read still lies inside its bin and the series (decoded
+ *   key offsets are clamped to their bin; a bucket whose areas are all NaN
+ *   keeps its first point).
  * - x: with MMLTTB_X_IMPLICIT, x must be NULL and x_i = i; with MMLTTB_X_INT64,
  *   x is int64[n], strictly increasing (precondition, not checked). x never
  *   affects binning (bins are equal-index); it enters only the LTTB means and

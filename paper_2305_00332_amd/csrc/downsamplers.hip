@@ -59,27 +59,35 @@ __global__ __launch_bounds__(1024) void k_m4_compact(const unsigned long long *_
     for (int64_t base = 0; base < nb; base += blockDim.x) {
         const int64_t b = base + threadIdx.x;
         int c = 0;
-        int64_t v[4] = {0, 0, 0, 0};
+        int64_t lo = 0, a0 = 0, a1 = 0, last = 0;
+        bool k0 = false, k1 = false, k2 = false;
         if (b < nb) {
-            const int64_t lo = split_lo(bins, b);
-            const int64_t last = split_lo(bins, b + 1) - 1;
-            const int64_t imin = lo + min_key_offset(keys[2 * b]);
-            const int64_t imax = lo + max_key_offset(keys[2 * b + 1]);
-            const int64_t a0 = imin < imax ? imin : imax;
-            const int64_t a1 = imin < imax ? imax : imin;
+            lo = split_lo(bins, b);
+            last = split_lo(bins, b + 1) - 1;
+            const int64_t len = last - lo + 1;
+            int64_t omin = min_key_offset(keys[2 * b]), omax = max_key_offset(keys[2 * b + 1]);
+            omin = omin < len ? omin : 0; // keys always decode inside their bin
+            omax = omax < len ? omax : 0;
+            const int64_t imin = lo + omin, imax = lo + omax;
+            a0 = imin < imax ? imin : imax;
+            a1 = imin < imax ? imax : imin;
             // lo <= a0 <= a1 <= last: keep each value that differs from the one before
-            v[c++] = lo;
-            if (a0 != lo)
-                v[c++] = a0;
-            if (a1 != a0)
-                v[c++] = a1;
-            if (last != a1)
-                v[c++] = last;
+            k0 = a0 != lo;
+            k1 = a1 != a0;
+            k2 = last != a1;
+            c = 1 + (int)k0 + (int)k1 + (int)k2;
         }
         int total;
-        const int64_t off = running + block_exclusive_scan(c, wave_tot, total);
-        for (int i = 0; i < c; ++i)
-            out[off + i] = v[i];
+        int64_t off = running + block_exclusive_scan(c, wave_tot, total);
+        if (c > 0) {
+            out[off++] = lo;
+            if (k0)
+                out[off++] = a0;
+            if (k1)
+                out[off++] = a1;
+            if (k2)
+                out[off++] = last;
+        }
         running += total;
     }
     if (threadIdx.x == 0)
