@@ -183,6 +183,10 @@ def bench_headline(args):
               "lttb_chain", "lttb_chain_seg"):
         tot, cnt = ops.profile_read(k)
         kern[k] = round(tot / cnt, 5) if cnt else None
+    # device time of each timed call (events before its first and after its last launch)
+    spans = ops.profile_samples("call_minmaxlttb")
+    step_ms = ({"median": round(float(np.median(spans)), 5), "min": round(min(spans), 5),
+                "max": round(max(spans), 5), "calls": len(spans)} if spans else None)
     stable = bool(torch.equal(out, ref_out))
 
     # the LTTB pass in its sequential form on the same data (identical picks)
@@ -229,6 +233,7 @@ def bench_headline(args):
                                f"implicit x, resident in HBM; MinMaxLTTB n_out={n_out}, r_ps={r_ps}",
                    "n": n, "n_out": n_out, "r_ps": r_ps, "mode": "plain single-series call"},
         "kernel_avg_ms": kern,
+        "step_device_ms": step_ms,
         "chain_forms": chain_forms,
         "tuning": dict(zip(("unroll", "chunk", "chain", "tile"), ops.get_tuning())),
         "roofline": roofline,
@@ -247,10 +252,22 @@ def bench_headline(args):
             want = oracle.minmaxlttb(y_np, n_out, r_ps)
             times.append(time.perf_counter() - c0)
         t = float(np.median(times))
+        omp = oracle.load_openmp()
+        omp_times = []
+        for _ in range(max(1, args.cpu_reps)):
+            c0 = time.perf_counter()
+            want_omp = oracle.minmaxlttb(y_np, n_out, r_ps, _lib_override=omp)
+            omp_times.append(time.perf_counter() - c0)
+        t_omp = float(np.median(omp_times))
         result["cpu_baseline"] = {"value": round(n / t / 1e9, 4), "unit": "Gpts/s", "cores": 1, "kind": "oracle",
                                   "host_cpu": host_cpu_model(),
                                   "sample": f"the full workload (n={n}) run {len(times)} times single-threaded, "
                                             f"median {t:.3f} s"}
+        result["cpu_openmp"] = {"value": round(n / t_omp / 1e9, 4), "unit": "Gpts/s", "cores": oracle.threads(omp),
+                                "kind": "oracle source built with -fopenmp: the MinMax bin loop and the finiteness "
+                                        "check on all threads, the rest single-threaded",
+                                "sample": f"the full workload run {len(omp_times)} times, median {t_omp:.3f} s",
+                                "identical": bool(np.array_equal(want_omp, want))}
         result["parity_vs_oracle"] = bool(np.array_equal(out.cpu().numpy(), want))
         del y_np
     del y, ws
@@ -528,8 +545,10 @@ def bench_comparator(args):
         torch.cuda.synchronize()
         return (time.perf_counter() - t0) / reps, out
 
+    omp = oracle.load_openmp()
     res = {"workload": f"one series, n={n}, float32 random walk + 3 sinusoids + noise + 0.01% spikes (seed 2), "
-                       f"int64 irregular x; n_out={n_out}", "n": n, "n_out": n_out}
+                       f"int64 irregular x; n_out={n_out}", "n": n, "n_out": n_out,
+           "cpu_openmp_threads": oracle.threads(omp)}
     log("comparator: GPU whole-series LTTB")
     t_l, out_l = gpu_time(lambda: ops.lttb(y, n_out, x=x), 3)
     c0 = time.perf_counter()
@@ -560,10 +579,15 @@ def bench_comparator(args):
         c0 = time.perf_counter()
         want_m = oracle.minmaxlttb(y_np, n_out, r_ps, x_np)
         t_mc = time.perf_counter() - c0
+        c0 = time.perf_counter()
+        want_omp = oracle.minmaxlttb(y_np, n_out, r_ps, x_np, _lib_override=omp)
+        t_mo = time.perf_counter() - c0
         res[f"minmaxlttb_r{r_ps}"] = {
             "gpu_ms": round(t_m * 1e3, 4), "gpu_gpts_per_s": round(n / t_m / 1e9, 3), "cpu_oracle_s": round(t_mc, 3),
+            "cpu_openmp_s": round(t_mo, 3),
             "gpu_speedup_vs_gpu_lttb": round(t_l / t_m, 2), "cpu_speedup_vs_cpu_lttb": round(t_lc / t_mc, 2),
-            "parity_vs_oracle": bool(np.array_equal(out_m.cpu().numpy(), want_m))}
+            "cpu_openmp_speedup_vs_cpu_lttb": round(t_lc / t_mo, 2),
+            "parity_vs_oracle": bool(np.array_equal(out_m.cpu().numpy(), want_m) and np.array_equal(want_omp, want_m))}
     del x, y, y_np, x_np
     torch.cuda.empty_cache()
     res["paper_context"] = {
@@ -571,8 +595,9 @@ def bench_comparator(args):
         "parallel_speedup_vs_lttb": "30x",
         "source": "section 3.2: CPU implementations (a C LTTB, tsdownsample's MinMaxLTTB); hardware, core "
                   "count, N, n_out and r_ps are not stated",
-        "here": "cpu_speedup_vs_cpu_lttb compares the two single-thread oracle runs; gpu_speedup_vs_gpu_lttb "
-                "the two GPU paths",
+        "here": "cpu_speedup_vs_cpu_lttb compares the two single-thread oracle runs; "
+                "cpu_openmp_speedup_vs_cpu_lttb the oracle built with OpenMP over the MinMax bins (all host "
+                "threads) against the single-thread LTTB oracle; gpu_speedup_vs_gpu_lttb the two GPU paths",
     }
     return res
 

@@ -294,6 +294,15 @@ int mmlttb_get_tuning(int *unroll, int64_t *chunk, int *chain, int *tile);
 int mmlttb_profile_enable(int on);
 int mmlttb_profile_reset(void);
 int mmlttb_profile_read(const char *kernel, double *total_ms, int64_t *launches);
+/* The individual durations behind mmlttb_profile_read, in launch order: copies
+ * the first min(cap, available) of them (milliseconds) into the HOST array `ms`
+ * and sets *count to the number available (at most 65536 per name are kept
+ * since the last reset). Besides the kernel names, "call_minmaxlttb" holds one
+ * span per successful mmlttb_minmaxlttb call: from an event recorded on its
+ * stream before its first launch to one recorded after its last, so back-to-back
+ * calls give the device time per call. MMLTTB_EINVAL for a NULL name or count,
+ * a negative cap, or ms == NULL with cap > 0. Not thread-safe. */
+int mmlttb_profile_samples(const char *name, float *ms, int64_t cap, int64_t *count);
 
 #ifdef __cplusplus
 }

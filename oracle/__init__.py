@@ -28,6 +28,8 @@ from .oracle import (  # noqa: F401
     minmax_xbins,
     minmaxlttb_xbins,
     minmaxlttb,
+    load_openmp,
+    threads,
     XK_IMPLICIT,
     XK_INT64,
 )

@@ -109,6 +109,9 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define ORC_OK 0
 #define ORC_EINVAL (-1)
@@ -345,9 +348,15 @@ int oracle_minmax(const float *y, int64_t n, int64_t n_out, int32_t r_ps, int64_
 {
     if (n < 1 || n_out < 3 || r_ps < 1)
         return ORC_EINVAL;
+    int64_t bad = 0;
+#ifdef _OPENMP
+#pragma omp parallel for schedule(static) reduction(| : bad)
+#endif
     for (int64_t i = 0; i < n; i++)
         if (!is_finite_f32(y[i]))
-            return ORC_ENOTFINITE;
+            bad = 1;
+    if (bad)
+        return ORC_ENOTFINITE;
     int64_t cnt = 0;
     if (n <= 2) {
         for (int64_t i = 0; i < n; i++)
@@ -357,23 +366,47 @@ int oracle_minmax(const float *y, int64_t n, int64_t n_out, int32_t r_ps, int64_
     }
     int64_t nb = (int64_t)(((__int128)n_out * r_ps) / 2); /* R1 */
     int64_t L = n - 2;
-    P[cnt++] = 0;
+    /* Per-bin argmin and argmax first (-1 marks an empty bin), then P in bin
+     * order. The bins are independent: this is the loop the paper runs in
+     * parallel (section 3.2); a build with -fopenmp spreads it over all cores,
+     * with the same result. */
+    int64_t *bmin = (int64_t *)malloc(sizeof(int64_t) * (size_t)nb);
+    int64_t *bmax = (int64_t *)malloc(sizeof(int64_t) * (size_t)nb);
+    if (!bmin || !bmax) {
+        free(bmin);
+        free(bmax);
+        return ORC_ENOMEM;
+    }
+#ifdef _OPENMP
+#pragma omp parallel for schedule(static)
+#endif
     for (int64_t b = 0; b < nb; b++) {
         int64_t lo = 1 + floor_frac(b, L, nb); /* R2 */
         int64_t hi = 1 + floor_frac(b + 1, L, nb);
-        if (lo == hi)
-            continue;
-        int64_t imin = lo, imax = lo;
-        for (int64_t i = lo + 1; i < hi; i++) {
-            if (y[i] < y[imin]) /* strict: lowest index wins ties (R3) */
-                imin = i;
-            if (y[i] > y[imax])
-                imax = i;
+        int64_t imin = -1, imax = -1;
+        if (lo < hi) {
+            imin = lo;
+            imax = lo;
+            for (int64_t i = lo + 1; i < hi; i++) {
+                if (y[i] < y[imin]) /* strict: lowest index wins ties (R3) */
+                    imin = i;
+                if (y[i] > y[imax])
+                    imax = i;
+            }
         }
-        P[cnt++] = imin;
-        if (imax != imin)
-            P[cnt++] = imax;
+        bmin[b] = imin;
+        bmax[b] = imax;
     }
+    P[cnt++] = 0;
+    for (int64_t b = 0; b < nb; b++) {
+        if (bmin[b] < 0) /* empty bin */
+            continue;
+        P[cnt++] = bmin[b];
+        if (bmax[b] != bmin[b])
+            P[cnt++] = bmax[b];
+    }
+    free(bmin);
+    free(bmax);
     P[cnt++] = n - 1;
     qsort(P, (size_t)cnt, sizeof(int64_t), cmp_i64);
     int64_t d = 0;
@@ -1110,6 +1143,17 @@ int oracle_m4(const float *y, int64_t n, int64_t n_out, int64_t *out, int64_t *c
 }
 
 /* out: capacity min(n, n_out). */
+/* Threads the parallel loops of this build may use: 1 unless built with
+ * -fopenmp (then OpenMP's limit, e.g. OMP_NUM_THREADS). */
+int oracle_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
 int oracle_everynth(int64_t n, int64_t n_out, int64_t *out)
 {
     if (n < 1 || n_out < 1)

@@ -18,6 +18,10 @@ XK_INT64 = 1
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "mmlttb_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
+# The same source built with -fopenmp: the independent MinMax bin loop (and the
+# finiteness check) run on all cores; everything else, and every result, is the
+# single-threaded oracle's. Timed beside it as the paper's parallel CPU case.
+_LIB_OMP = os.path.join(_HERE, "liboracle_omp.so")
 
 # No fast-math and no contraction: every double operation is one IEEE binary64
 # operation rounded to nearest-even.
@@ -29,11 +33,13 @@ def lib_path() -> str:
 
 
 def build(force: bool = True) -> str:
-    """Compile the oracle with gcc into ``oracle/liboracle.so``."""
-    if force or not os.path.exists(_LIB):
-        tmp = _LIB + ".tmp"
-        subprocess.check_call(["gcc", *CFLAGS, "-o", tmp, _SRC, "-lm"])
-        os.replace(tmp, _LIB)
+    """Compile the oracle with gcc into ``oracle/liboracle.so`` and, with
+    -fopenmp, ``oracle/liboracle_omp.so``."""
+    for path, extra in ((_LIB, []), (_LIB_OMP, ["-fopenmp"])):
+        if force or not os.path.exists(path):
+            tmp = path + ".tmp"
+            subprocess.check_call(["gcc", *CFLAGS, *extra, "-o", tmp, _SRC, "-lm"])
+            os.replace(tmp, path)
     return _LIB
 
 
@@ -72,16 +78,18 @@ def _bind(path: str):
     lib.oracle_minmaxlttb_xbins.argtypes = [_i64p, _f32p, ctypes.c_int64, ctypes.c_int64, ctypes.c_int32, _i64p,
                                             _i64p]
     lib.oracle_everynth.argtypes = [ctypes.c_int64, ctypes.c_int64, _i64p]
+    lib.oracle_threads.argtypes = []
     for f in ("oracle_minmax", "oracle_lttb", "oracle_minmaxlttb", "oracle_lttb_means",
               "oracle_exact_sum_f32", "oracle_exact_sum_i64", "oracle_m4", "oracle_everynth",
               "oracle_minmax_xbins", "oracle_minmaxlttb_xbins", "oracle_minmax_typed", "oracle_minmaxlttb_typed",
               "oracle_exact_sum_f64", "oracle_lttb_means_typed", "oracle_minmax_simplify",
-              "oracle_simplify_points"):
+              "oracle_simplify_points", "oracle_threads"):
         getattr(lib, f).restype = ctypes.c_int
     return lib
 
 
 _lib = None
+_lib_omp = None
 
 
 def _load():
@@ -91,6 +99,21 @@ def _load():
             build(force=False)
         _lib = _bind(_LIB)
     return _lib
+
+
+def load_openmp():
+    """The OpenMP build of the same source (pass it as ``_lib_override``)."""
+    global _lib_omp
+    if _lib_omp is None:
+        if not os.path.exists(_LIB_OMP):
+            build(force=False)
+        _lib_omp = _bind(_LIB_OMP)
+    return _lib_omp
+
+
+def threads(lib=None) -> int:
+    """Threads the given build's parallel loops may use (1 for the plain build)."""
+    return int((lib or _load()).oracle_threads())
 
 
 def compile_variant(src_text: str, out_path: str):

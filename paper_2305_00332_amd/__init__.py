@@ -27,6 +27,7 @@ from .ops import (  # noqa: F401
     minmaxlttb,
     profile_enable,
     profile_read,
+    profile_samples,
     profile_reset,
     workspace_size,
     set_tuning,

@@ -48,6 +48,7 @@ EXPORTS = (
     "mmlttb_profile_enable",
     "mmlttb_profile_reset",
     "mmlttb_profile_read",
+    "mmlttb_profile_samples",
 )
 
 
@@ -119,11 +120,14 @@ def load(path: str = LIB_PATH):
                                       ctypes.POINTER(ctypes.c_int)]
     lib.mmlttb_profile_enable.argtypes = [ctypes.c_int]
     lib.mmlttb_profile_read.argtypes = [ctypes.c_char_p, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_i64)]
+    lib.mmlttb_profile_samples.argtypes = [ctypes.c_char_p, ctypes.POINTER(ctypes.c_float), _i64,
+                                           ctypes.POINTER(_i64)]
     for f in ("mmlttb_minmax", "mmlttb_lttb", "mmlttb_minmaxlttb", "mmlttb_minmaxlttb_batched", "mmlttb_m4",
               "mmlttb_minmax_xbins", "mmlttb_minmaxlttb_xbins", "mmlttb_minmax_typed", "mmlttb_minmaxlttb_typed",
               "mmlttb_minmax_simplify",
               "mmlttb_everynth", "mmlttb_set_graph_cache", "mmlttb_graph_cache_stats", "mmlttb_set_tuning",
-              "mmlttb_get_tuning", "mmlttb_profile_enable", "mmlttb_profile_reset", "mmlttb_profile_read"):
+              "mmlttb_get_tuning", "mmlttb_profile_enable", "mmlttb_profile_reset", "mmlttb_profile_read",
+              "mmlttb_profile_samples"):
         getattr(lib, f).restype = ctypes.c_int
     _lib = lib
     return lib

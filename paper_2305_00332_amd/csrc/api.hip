@@ -87,6 +87,8 @@ bool g_prof = false;
 std::vector<Pending> g_pending;
 std::vector<hipEvent_t> g_event_pool;
 std::map<std::string, std::pair<double, int64_t>> g_totals;
+std::map<std::string, std::vector<float>> g_samples; // per-launch durations, in launch order
+constexpr size_t kMaxSamples = size_t(1) << 16;     // kept per name since the last reset
 
 // Timing-only events: no system-scope fence on record, so recording them
 // neither writes back nor invalidates caches around the timed kernel.
@@ -118,6 +120,39 @@ hipError_t timed(const char *name, hipStream_t s, F &&launch)
     return e;
 }
 
+// Brackets a whole entry-point call with timing-only events while profiling is
+// on: the span from before its first launch to after its last lands under
+// `name` when close() runs (only on success; an early error return hands the
+// opening event back to the pool unused).
+struct CallSpan {
+    const char *name;
+    hipStream_t s;
+    hipEvent_t a = nullptr;
+    CallSpan(const char *nm, hipStream_t st) : name(nm), s(st)
+    {
+        if (g_prof && (a = take_event()))
+            (void)hipEventRecord(a, s);
+    }
+    void close()
+    {
+        if (!a)
+            return;
+        hipEvent_t b = take_event();
+        if (b) {
+            (void)hipEventRecord(b, s);
+            g_pending.push_back({name, a, b});
+        } else {
+            g_event_pool.push_back(a);
+        }
+        a = nullptr;
+    }
+    ~CallSpan()
+    {
+        if (a)
+            g_event_pool.push_back(a);
+    }
+};
+
 void drain_pending()
 {
     for (auto &p : g_pending) {
@@ -126,6 +161,9 @@ void drain_pending()
             auto &t = g_totals[p.name];
             t.first += ms;
             t.second += 1;
+            auto &v = g_samples[p.name];
+            if (v.size() < kMaxSamples)
+                v.push_back(ms);
         }
         g_event_pool.push_back(p.a);
         g_event_pool.push_back(p.b);
@@ -880,7 +918,9 @@ int mmlttb_minmaxlttb(int xk, const int64_t *x, const float *y, int64_t n, int64
         return fail(MMLTTB_EINVAL, "out_idx must not be NULL");
     hipStream_t s = (hipStream_t)stream;
     if (n <= n_out) {
+        CallSpan span("call_minmaxlttb", s);
         MMLTTB_LAUNCH("iota", s, launch_iota(out_idx, n, nullptr, s));
+        span.close();
         return ok();
     }
     const MmLayout L = mm_layout(n_out, r_ps);
@@ -888,6 +928,7 @@ int mmlttb_minmaxlttb(int xk, const int64_t *x, const float *y, int64_t n, int64
         return fail(MMLTTB_EINVAL, "ws must not be NULL");
     if (ws_bytes < L.total)
         return fail(MMLTTB_ENOMEM, "workspace of %zu bytes is below the %zu required", ws_bytes, L.total);
+    CallSpan span("call_minmaxlttb", s);
     int64_t *P = at<int64_t>(ws, L.P), *XP = at<int64_t>(ws, L.XP), *m = at<int64_t>(ws, L.m);
     float *YP = at<float>(ws, L.YP);
     double *MX = at<double>(ws, L.MX), *MY = at<double>(ws, L.MY);
@@ -912,6 +953,7 @@ int mmlttb_minmaxlttb(int xk, const int64_t *x, const float *y, int64_t n, int64
     } else {
         MMLTTB_LAUNCH("lttb_chain", s, launch_lttb_chain(XP, YP, m, 0, B, MX, MY, P, out_idx, s));
     }
+    span.close();
     return ok();
 }
 
@@ -1355,6 +1397,7 @@ int mmlttb_profile_reset(void)
 {
     drain_pending();
     g_totals.clear();
+    g_samples.clear();
     return MMLTTB_OK;
 }
 
@@ -1366,6 +1409,19 @@ int mmlttb_profile_read(const char *kernel, double *total_ms, int64_t *launches)
     auto it = g_totals.find(kernel);
     *total_ms = it == g_totals.end() ? 0.0 : it->second.first;
     *launches = it == g_totals.end() ? 0 : it->second.second;
+    return MMLTTB_OK;
+}
+
+int mmlttb_profile_samples(const char *name, float *ms, int64_t cap, int64_t *count)
+{
+    if (!name || !count || cap < 0 || (cap > 0 && !ms))
+        return fail(MMLTTB_EINVAL, "NULL argument or negative capacity");
+    drain_pending();
+    auto it = g_samples.find(name);
+    const int64_t have = it == g_samples.end() ? 0 : (int64_t)it->second.size();
+    for (int64_t i = 0; i < have && i < cap; i++)
+        ms[i] = it->second[(size_t)i];
+    *count = have;
     return MMLTTB_OK;
 }
 

@@ -332,3 +332,17 @@ def profile_read(kernel: str):
     cnt = ctypes.c_int64(0)
     _lib.check(_lib.load().mmlttb_profile_read(kernel.encode(), ctypes.byref(ms), ctypes.byref(cnt)))
     return ms.value, cnt.value
+
+
+def profile_samples(name: str):
+    """The individual durations (milliseconds, launch order) recorded under
+    `name` since the last reset: a kernel name, or "call_minmaxlttb" for whole
+    minmaxlttb calls."""
+    import ctypes
+
+    lib = _lib.load()
+    cnt = ctypes.c_int64(0)
+    _lib.check(lib.mmlttb_profile_samples(name.encode(), None, 0, ctypes.byref(cnt)))
+    buf = (ctypes.c_float * max(cnt.value, 1))()
+    _lib.check(lib.mmlttb_profile_samples(name.encode(), buf, cnt.value, ctypes.byref(cnt)))
+    return [float(buf[i]) for i in range(min(cnt.value, len(buf)))]

@@ -173,3 +173,30 @@ def test_new_calls_reject_invalid_arguments_on_host(lib):
     assert lib.mmlttb_minmax_xbins(fake, fake, 100, 10, 0, fake, fake, ws, 1 << 20, None) == -1
     assert lib.mmlttb_minmaxlttb_xbins(fake, fake, 100, 10, 1, fake, fake, ws, 1 << 20, None) == -1
     assert lib.mmlttb_minmaxlttb_xbins(fake, fake, 10 ** 6, 1000, 4, fake, fake, ws, 16, None) == -2
+
+
+def test_profile_samples_host_checks(lib):
+    """Per-launch samples: argument checks, and nothing recorded for calls the
+    host rejects (no HIP call is made on this path)."""
+    _setup(lib)
+    i64 = ctypes.c_int64
+    lib.mmlttb_profile_samples.argtypes = [ctypes.c_char_p, ctypes.POINTER(ctypes.c_float), i64, ctypes.POINTER(i64)]
+    lib.mmlttb_profile_enable.argtypes = [ctypes.c_int]
+    cnt = i64(-1)
+    buf = (ctypes.c_float * 4)()
+    assert lib.mmlttb_profile_samples(None, buf, 4, ctypes.byref(cnt)) == -1
+    assert lib.mmlttb_profile_samples(b"call_minmaxlttb", buf, 4, None) == -1
+    assert lib.mmlttb_profile_samples(b"call_minmaxlttb", buf, -1, ctypes.byref(cnt)) == -1
+    assert lib.mmlttb_profile_samples(b"call_minmaxlttb", None, 4, ctypes.byref(cnt)) == -1
+    assert lib.mmlttb_profile_reset() == 0
+    assert lib.mmlttb_profile_enable(1) == 0
+    try:
+        fake = ctypes.c_void_p(0x100000)
+        assert lib.mmlttb_minmaxlttb(0, None, fake, 10 ** 6, 1000, 1, fake, fake, 1 << 20, None) == -1  # r_ps
+        assert lib.mmlttb_minmaxlttb(0, None, fake, 10 ** 6, 1000, 4, fake, fake, 16, None) == -2       # ws
+        assert lib.mmlttb_profile_samples(b"call_minmaxlttb", None, 0, ctypes.byref(cnt)) == 0
+        assert cnt.value == 0
+        assert lib.mmlttb_profile_samples(b"no_such_kernel", buf, 4, ctypes.byref(cnt)) == 0
+        assert cnt.value == 0
+    finally:
+        assert lib.mmlttb_profile_enable(0) == 0

@@ -180,3 +180,34 @@ def test_errors_on_gpu():
     # a failed call leaves the next one unaffected
     np.testing.assert_array_equal(ops.minmaxlttb(y, 100, 4).cpu().numpy(),
                                   oracle.minmaxlttb(y.cpu().numpy(), 100, 4))
+
+
+def test_profile_call_spans_cover_their_kernels():
+    """Each successful call leaves one whole-call span, at least as long as the
+    kernels launched inside it; a call rejected on the host leaves none."""
+    y = _dev(_series("walk", 2_000_001, 5))
+    names = ("init_keys", "minmax_bin_reduce", "preselect_compact_means", "lttb_chain_seg", "lttb_chain")
+    ops.minmaxlttb(y, 1000, 4)
+    torch.cuda.synchronize()
+    ops.profile_enable(True)
+    try:
+        ops.profile_reset()
+        for _ in range(4):
+            ops.minmaxlttb(y, 1000, 4)
+        with pytest.raises(RuntimeError):
+            ops.minmaxlttb(y, 1000, 1)
+        ops.minmaxlttb(y[:500], 1000, 4)  # n <= n_out: one iota launch, still one span
+        torch.cuda.synchronize()
+        spans = ops.profile_samples("call_minmaxlttb")
+        per_kernel = {k: ops.profile_samples(k) for k in names}
+    finally:
+        ops.profile_enable(False)
+        ops.profile_reset()
+    assert len(spans) == 5
+    launched = [k for k in names if per_kernel[k]]
+    for k in launched:
+        assert len(per_kernel[k]) == 4, k
+    for i in range(4):
+        inside = sum(per_kernel[k][i] for k in launched)
+        assert spans[i] >= 0.95 * inside, (i, spans[i], inside)
+    assert spans[4] > 0

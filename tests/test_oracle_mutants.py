@@ -4,6 +4,7 @@ operand, a wrong tie rule, a wrong bucket, a wrong bin count or boundary, a
 wrong rounding, a lost chain update."""
 from __future__ import annotations
 
+import faulthandler
 import math
 import multiprocessing
 
@@ -26,8 +27,10 @@ HALFWAY_CASES = [
 
 MUTANTS = {
     "min_tie_highest": ("if (y[i] < y[imin]) /* strict", "if (y[i] <= y[imin]) /* strict"),
-    "max_tie_highest": ("if (y[i] > y[imax])\n                imax = i;\n        }\n        P[cnt++] = imin;",
-                        "if (y[i] >= y[imax])\n                imax = i;\n        }\n        P[cnt++] = imin;"),
+    "max_tie_highest": ("if (y[i] > y[imax])\n                    imax = i;\n            }\n        }\n        bmin[b] = imin;",
+                        "if (y[i] >= y[imax])\n                    imax = i;\n            }\n        }\n        bmin[b] = imin;"),
+    "empty_bin_kept": ("        if (bmin[b] < 0) /* empty bin */\n            continue;\n", ""),
+    "max_dropped_when_distinct": ("        if (bmax[b] != bmin[b])\n            P[cnt++] = bmax[b];\n", ""),
     "m4_min_tie_highest": ("if (y[i] < y[imin]) /* lowest index on ties (R12) */",
                            "if (y[i] <= y[imin]) /* lowest index on ties (R12) */"),
     "m4_max_tie_highest": ("if (y[i] > y[imax]) /* lowest index on ties (R12) */",
@@ -241,6 +244,9 @@ def _run_isolated(src: str, so_path: str) -> bool:
     q = ctx.Queue()
 
     def child():
+        # a mutant that overruns a buffer may abort here; that exit code is the
+        # expected outcome, so keep pytest's fault handler from printing a trace
+        faulthandler.disable()
         q.put(_passes_pins(oracle.compile_variant(src, so_path)))
 
     p = ctx.Process(target=child)

@@ -306,3 +306,27 @@ def test_planted_mistakes_are_caught():
             bad[1] = alt[0]
             with pytest.raises(AssertionError):
                 pins.check_lttb_near_optimal(xs, y, bad, n_out, rel=0.0)
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_openmp_build_gives_the_same_indices(seed):
+    """The -fopenmp build of the same source splits only the independent bin loop
+    (and the finiteness check) across threads: every result, empty bins and ties
+    included, equals the plain build's."""
+    omp = oracle.load_openmp()
+    assert oracle.threads() == 1
+    rng = np.random.default_rng(900 + seed)
+    n = int(rng.integers(3, 400_000))
+    n_out = int(rng.integers(3, 3000))
+    r_ps = int(rng.integers(1, 9))
+    y = np.cumsum(rng.standard_normal(n)).astype(np.float32)
+    if seed % 2:
+        y = np.round(y).astype(np.float32)  # many ties
+    np.testing.assert_array_equal(oracle.minmax(y, n_out, r_ps, _lib_override=omp), oracle.minmax(y, n_out, r_ps))
+    if r_ps >= 2:
+        np.testing.assert_array_equal(oracle.minmaxlttb(y, n_out, r_ps, _lib_override=omp),
+                                      oracle.minmaxlttb(y, n_out, r_ps))
+    bad = y.copy()
+    bad[n // 2] = np.nan
+    with pytest.raises(oracle.OracleError):
+        oracle.minmax(bad, n_out, r_ps, _lib_override=omp)
