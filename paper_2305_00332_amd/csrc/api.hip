@@ -305,6 +305,10 @@ int64_t chunks_per_bin(int64_t maxbin, int64_t nb, int64_t chunk)
     return cpb < 1 ? 1 : cpb;
 }
 
+// Work items merge into their bin's keys with atomics only when bins are cut
+// into several items; a single item per bin stores its keys.
+bool keys_need_init(const MinMaxGeom &g) { return g.chunks_per_bin > 1; }
+
 // Bins over `len` points (the interior n-2 for MinMax, all n for M4).
 MinMaxGeom minmax_geom(int64_t len, int64_t nb)
 {
@@ -363,7 +367,8 @@ int enqueue_preselect(const int64_t *x, const float *y, int64_t n, int64_t n_out
     }
     unsigned long long *keys = at<unsigned long long>(ws, L.keys);
     const MinMaxGeom g = minmax_geom(n - 2, nb);
-    MMLTTB_LAUNCH("init_keys", s, launch_init_keys(keys, nb, s));
+    if (keys_need_init(g))
+        MMLTTB_LAUNCH("init_keys", s, launch_init_keys(keys, nb, s));
     MMLTTB_LAUNCH("minmax_bin_reduce", s, launch_minmax_bin_reduce(y, g, tuning().unroll, keys, s));
     MMLTTB_LAUNCH("preselect_compact", s, launch_preselect_compact(keys, g.bins, n, x, y, P, XP, YP, m_out, s));
     return MMLTTB_OK;
@@ -940,7 +945,8 @@ int mmlttb_minmaxlttb(int xk, const int64_t *x, const float *y, int64_t n, int64
     } else {
         unsigned long long *keys = at<unsigned long long>(ws, L.keys);
         const MinMaxGeom g = minmax_geom(n - 2, nb);
-        MMLTTB_LAUNCH("init_keys", s, launch_init_keys(keys, nb, s));
+        if (keys_need_init(g))
+            MMLTTB_LAUNCH("init_keys", s, launch_init_keys(keys, nb, s));
         MMLTTB_LAUNCH("minmax_bin_reduce", s, launch_minmax_bin_reduce(y, g, tuning().unroll, keys, s));
         MMLTTB_LAUNCH("preselect_compact_means", s,
                       launch_preselect_compact_means(keys, g.bins, n, x, y, P, XP, YP, m, B, MX, MY, s));
@@ -1208,7 +1214,8 @@ int mmlttb_m4(const float *y, int64_t n, int64_t n_out, int64_t *out_idx, int64_
         return fail(MMLTTB_ENOMEM, "workspace of %zu bytes is below the %zu required", ws_bytes, need);
     unsigned long long *keys = static_cast<unsigned long long *>(ws);
     const MinMaxGeom g = minmax_geom(n, nb);
-    MMLTTB_LAUNCH("init_keys", s, launch_init_keys(keys, nb, s));
+    if (keys_need_init(g))
+        MMLTTB_LAUNCH("init_keys", s, launch_init_keys(keys, nb, s));
     MMLTTB_LAUNCH("m4_bin_reduce", s, launch_m4_bin_reduce(y, g, tuning().unroll, keys, s));
     MMLTTB_LAUNCH("m4_compact", s, launch_m4_compact(keys, g.bins, out_idx, out_count, s));
     return ok();

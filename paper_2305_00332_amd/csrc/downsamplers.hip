@@ -37,16 +37,18 @@ __global__ __launch_bounds__(256) void k_m4_bin_reduce(const float *__restrict__
     const int64_t blo = split_lo(g.bins, b);
     const int64_t bhi = split_lo(g.bins, b + 1);
     const int64_t lo = blo + j * g.chunk;
-    if (lo >= bhi)
-        return; // trailing chunk of a shorter bin
+    const bool whole = g.chunks_per_bin == 1; // the item is the bin: keys stored, not merged
+    if (lo >= bhi) { // trailing chunk of a shorter bin, or an empty bin
+        if (whole && lane == 0)
+            put_bin_keys(keys, b, true, ~0ull, 0ull);
+        return;
+    }
     const int64_t hi = (lo + g.chunk < bhi) ? lo + g.chunk : bhi;
     float vmin, vmax;
     int64_t imin, imax;
     wave_reduce_range<U>(y, lo, hi, lane, vmin, imin, vmax, imax);
-    if (lane == 0) {
-        atomicMin(&keys[2 * b], pack_min_key(vmin, imin - blo));
-        atomicMax(&keys[2 * b + 1], pack_max_key(vmax, imax - blo));
-    }
+    if (lane == 0)
+        put_bin_keys(keys, b, whole, pack_min_key(vmin, imin - blo), pack_max_key(vmax, imax - blo));
 }
 
 // One workgroup of 1024 threads; one thread per bin and round.

@@ -8,7 +8,9 @@
 // reduction of the values, then a re-read of only the winning batch to find
 // the lowest index holding the extreme. The item's (value, index) pairs merge
 // into the bin's two 64-bit keys with order-independent atomic min/max, so
-// the result does not depend on chunking, grid size or timing.
+// the result does not depend on chunking, grid size or timing; when every bin
+// is a single item, the item stores its keys instead and the keys need no
+// initialising launch.
 //
 // Key layout: high 32 bits = order key of the value (f32_order_key, -0 == +0),
 // low 32 bits = offset of the index inside its bin (min key) or its
@@ -50,16 +52,18 @@ __global__ __launch_bounds__(256) void k_minmax_bin_reduce(const float *__restri
     const int64_t blo = 1 + split_lo(g.bins, b);
     const int64_t bhi = 1 + split_lo(g.bins, b + 1);
     const int64_t lo = blo + j * g.chunk;
-    if (lo >= bhi)
-        return; // trailing chunk of a shorter bin
+    const bool whole = g.chunks_per_bin == 1; // the item is the bin: keys stored, not merged
+    if (lo >= bhi) { // trailing chunk of a shorter bin, or an empty bin
+        if (whole && lane == 0)
+            put_bin_keys(keys, b, true, ~0ull, 0ull);
+        return;
+    }
     const int64_t hi = (lo + g.chunk < bhi) ? lo + g.chunk : bhi;
     float vmin, vmax;
     int64_t imin, imax;
     wave_reduce_range<U>(y, lo, hi, lane, vmin, imin, vmax, imax);
-    if (lane == 0) {
-        atomicMin(&keys[2 * b], pack_min_key(vmin, imin - blo));
-        atomicMax(&keys[2 * b + 1], pack_max_key(vmax, imax - blo));
-    }
+    if (lane == 0)
+        put_bin_keys(keys, b, whole, pack_min_key(vmin, imin - blo), pack_max_key(vmax, imax - blo));
 }
 
 // One workgroup of 1024 threads builds P for one series.

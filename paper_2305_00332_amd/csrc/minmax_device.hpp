@@ -20,6 +20,23 @@ __device__ inline unsigned long long pack_max_key(float v, int64_t off)
     return ((unsigned long long)f32_order_key(v) << 32) | (unsigned long long)(0xffffffffu - (uint32_t)off);
 }
 
+// Puts one work item's key pair into its bin. A bin that is a single work
+// item (`whole`) has no other contributor, so a plain store gives what an
+// atomic merge into identity keys would, and the keys need no initialisation;
+// otherwise the item merges with atomicMin / atomicMax into keys that start
+// at the identities (~0 for the min key, 0 for the max key).
+__device__ inline void put_bin_keys(unsigned long long *keys, int64_t b, bool whole, unsigned long long kmin,
+                                    unsigned long long kmax)
+{
+    if (whole) {
+        keys[2 * b] = kmin;
+        keys[2 * b + 1] = kmax;
+    } else {
+        atomicMin(&keys[2 * b], kmin);
+        atomicMax(&keys[2 * b + 1], kmax);
+    }
+}
+
 __device__ inline int64_t min_key_offset(unsigned long long k) { return (int64_t)(uint32_t)(k & 0xffffffffull); }
 
 // The value a key holds (inverse of f32_order_key; -0.0 comes back as +0.0,

@@ -211,3 +211,30 @@ def test_profile_call_spans_cover_their_kernels():
         inside = sum(per_kernel[k][i] for k in launched)
         assert spans[i] >= 0.95 * inside, (i, spans[i], inside)
     assert spans[4] > 0
+
+
+@pytest.mark.parametrize("unroll,chunk", [(4, 1 << 22), (1, 256)], ids=["item-per-bin", "items-per-bin"])
+@pytest.mark.parametrize("fill", [0x00, 0xFF, 0x5A])
+def test_stale_workspace_bytes_do_not_leak(unroll, chunk, fill):
+    """With 1500-2000 bins and chunks longer than a bin, each bin is one work
+    item that stores its keys (no initialising launch); with 256-point chunks
+    bins of 500-2000 points are several items merging into initialised keys.
+    Either way, bytes left in the workspace (all zeros, all ones, a pattern)
+    never reach the result."""
+    old = ops.get_tuning()
+    try:
+        ops.set_tuning(unroll, chunk)
+        for seed, n, n_out, r_ps, m4_out in [(11, 1_000_003, 1000, 4, 8000), (12, 3_000_001, 1500, 2, 6000)]:
+            y_np = _series("ties" if seed % 2 else "walk", n, seed)
+            y = _dev(y_np)
+            ws = torch.full((ops.workspace_size(n, n_out, r_ps),), fill, dtype=torch.uint8, device=DEV)
+            got = ops.minmaxlttb(y, n_out, r_ps, ws=ws)
+            np.testing.assert_array_equal(got.cpu().numpy(), oracle.minmaxlttb(y_np, n_out, r_ps))
+            ws.fill_(fill)
+            P, m = ops.minmax(y, n_out, r_ps, ws=ws)
+            np.testing.assert_array_equal(P[: int(m)].cpu().numpy(), oracle.minmax(y_np, n_out, r_ps))
+            m4_ws = torch.full((ops.m4_workspace_size(n, m4_out),), fill, dtype=torch.uint8, device=DEV)
+            idx4, m4 = ops.m4(y, m4_out, ws=m4_ws)  # 2000 / 1500 M4 bins
+            np.testing.assert_array_equal(idx4[: int(m4)].cpu().numpy(), oracle.m4(y_np, m4_out))
+    finally:
+        ops.set_tuning(*old)
