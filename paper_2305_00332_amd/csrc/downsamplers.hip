@@ -23,32 +23,32 @@ __global__ __launch_bounds__(256) void k_m4_bin_reduce(const float *__restrict__
 {
     const int lane = threadIdx.x & (kWave - 1);
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
-    const int64_t item = (int64_t)blockIdx.x * (blockDim.x / kWave) + wave;
-    if (item >= g.n_items)
-        return;
-    int64_t b, j;
-    if (g.chunks_per_bin == 1) {
-        b = item;
-        j = 0;
-    } else {
-        b = item / g.chunks_per_bin;
-        j = item - b * g.chunks_per_bin;
+    const int64_t waves = (int64_t)gridDim.x * (blockDim.x / kWave);
+    const bool whole = g.chunks_per_bin == 1; // an item is a whole bin: keys stored, not merged
+    for (int64_t item = (int64_t)blockIdx.x * (blockDim.x / kWave) + wave; item < g.n_items; item += waves) {
+        int64_t b, j;
+        if (whole) {
+            b = item;
+            j = 0;
+        } else {
+            b = item / g.chunks_per_bin;
+            j = item - b * g.chunks_per_bin;
+        }
+        const int64_t blo = split_lo(g.bins, b);
+        const int64_t bhi = split_lo(g.bins, b + 1);
+        const int64_t lo = blo + j * g.chunk;
+        if (lo >= bhi) { // trailing chunk of a shorter bin, or an empty bin
+            if (whole && lane == 0)
+                put_bin_keys(keys, b, true, ~0ull, 0ull);
+            continue;
+        }
+        const int64_t hi = (lo + g.chunk < bhi) ? lo + g.chunk : bhi;
+        float vmin, vmax;
+        int64_t imin, imax;
+        wave_reduce_range<U>(y, lo, hi, lane, vmin, imin, vmax, imax);
+        if (lane == 0)
+            put_bin_keys(keys, b, whole, pack_min_key(vmin, imin - blo), pack_max_key(vmax, imax - blo));
     }
-    const int64_t blo = split_lo(g.bins, b);
-    const int64_t bhi = split_lo(g.bins, b + 1);
-    const int64_t lo = blo + j * g.chunk;
-    const bool whole = g.chunks_per_bin == 1; // the item is the bin: keys stored, not merged
-    if (lo >= bhi) { // trailing chunk of a shorter bin, or an empty bin
-        if (whole && lane == 0)
-            put_bin_keys(keys, b, true, ~0ull, 0ull);
-        return;
-    }
-    const int64_t hi = (lo + g.chunk < bhi) ? lo + g.chunk : bhi;
-    float vmin, vmax;
-    int64_t imin, imax;
-    wave_reduce_range<U>(y, lo, hi, lane, vmin, imin, vmax, imax);
-    if (lane == 0)
-        put_bin_keys(keys, b, whole, pack_min_key(vmin, imin - blo), pack_max_key(vmax, imax - blo));
 }
 
 // One workgroup of 1024 threads; one thread per bin and round.
@@ -108,8 +108,7 @@ __global__ __launch_bounds__(256) void k_everynth(Split s, int64_t *__restrict__
 hipError_t launch_m4_bin_reduce(const float *y, const MinMaxGeom &g, int unroll, unsigned long long *keys,
                                 hipStream_t s)
 {
-    const int64_t waves_per_block = 4;
-    const int64_t blocks = (g.n_items + waves_per_block - 1) / waves_per_block;
+    const int64_t blocks = stream_blocks(g);
     if (blocks > 0x7fffffff)
         return hipErrorInvalidConfiguration;
     switch (unroll) {

@@ -238,3 +238,26 @@ def test_stale_workspace_bytes_do_not_leak(unroll, chunk, fill):
             np.testing.assert_array_equal(idx4[: int(m4)].cpu().numpy(), oracle.m4(y_np, m4_out))
     finally:
         ops.set_tuning(*old)
+
+
+@pytest.mark.parametrize("unroll,chunk,n_out,r_ps", [(4, 1 << 20, 3000, 4), (4, 65536, 1000, 4), (2, 1 << 20, 4000, 8)],
+                         ids=["whole-bins", "split-bins", "r8"])
+def test_waves_looping_over_long_items(unroll, chunk, n_out, r_ps):
+    """Items of >= 32768 points and more than 2048 of them: the stream grid is
+    capped at 2048 waves and each wave loops over several items (whole bins
+    storing their keys, or bin pieces merging by atomics); with r_ps = 8 the
+    16000 items of 12500 points keep one wave each."""
+    n = 200_000_003
+    y_np = _series("walk", n, 21)
+    y = _dev(y_np)
+    old = ops.get_tuning()
+    try:
+        ops.set_tuning(unroll, chunk)
+        got = ops.minmaxlttb(y, n_out, r_ps)
+        np.testing.assert_array_equal(got.cpu().numpy(), oracle.minmaxlttb(y_np, n_out, r_ps))
+        P, m = ops.minmax(y, n_out, r_ps)
+        np.testing.assert_array_equal(P[: int(m)].cpu().numpy(), oracle.minmax(y_np, n_out, r_ps))
+        idx4, m4 = ops.m4(y, 4 * n_out * r_ps // 2)
+        np.testing.assert_array_equal(idx4[: int(m4)].cpu().numpy(), oracle.m4(y_np, 4 * n_out * r_ps // 2))
+    finally:
+        ops.set_tuning(*old)
