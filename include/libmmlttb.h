@@ -129,6 +129,20 @@ int mmlttb_minmax(int xk, const int64_t *x, const float *y, int64_t n, int64_t n
 int mmlttb_lttb(int xk, const int64_t *x, const float *y, int64_t n, int64_t n_out, int64_t *out_idx, void *ws,
                 size_t ws_bytes, void *stream);
 
+/* The next-bucket means of LTTB over m given points (section 2.2.1 LTTB:
+ * each bucket's third vertex is the average point of the bucket after it),
+ * the step MinMaxLTTB runs on the preselected points. With B = n_out-2
+ * interior buckets 1 + floor(k*(m-2)/B), MX[k] and MY[k] (k < B) are the
+ * mean x and y of bucket k+1 (k = B-1: the last point alone): the exact sum
+ * of the x (int64, or the position when xk is MMLTTB_X_IMPLICIT and x is NULL)
+ * and of the float32 y, each rounded once to binary64, divided by the count in
+ * binary64. MX and MY are device arrays of n_out-2 doubles owned by the
+ * caller; nothing else is written and no workspace is needed.
+ * MMLTTB_EINVAL unless m > n_out >= 3 (LTTB keeps every point otherwise) and
+ * the pointers are valid as for mmlttb_lttb. */
+int mmlttb_lttb_means(int xk, const int64_t *x, const float *y, int64_t m, int64_t n_out, double *MX, double *MY,
+                      void *stream);
+
 /* MinMaxLTTB (section 3): MinMax preselection (as mmlttb_minmax), then LTTB
  * (as mmlttb_lttb) on the preselected points only, with buckets, means and
  * areas taken over the preselected set. out_idx receives exactly

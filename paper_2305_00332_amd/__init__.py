@@ -25,6 +25,7 @@ from .ops import (  # noqa: F401
     minmaxlttb_xbins,
     xbins_workspace_size,
     minmaxlttb,
+    lttb_means,
     profile_enable,
     profile_read,
     profile_samples,

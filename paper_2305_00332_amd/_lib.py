@@ -28,6 +28,7 @@ EXPORTS = (
     "mmlttb_minmax",
     "mmlttb_lttb",
     "mmlttb_minmaxlttb",
+    "mmlttb_lttb_means",
     "mmlttb_batched_workspace_size",
     "mmlttb_minmaxlttb_batched",
     "mmlttb_simplify_workspace_size",
@@ -118,11 +119,13 @@ def load(path: str = LIB_PATH):
     lib.mmlttb_set_tuning.argtypes = [ctypes.c_int, _i64, ctypes.c_int, ctypes.c_int]
     lib.mmlttb_get_tuning.argtypes = [ctypes.POINTER(ctypes.c_int), ctypes.POINTER(_i64), ctypes.POINTER(ctypes.c_int),
                                       ctypes.POINTER(ctypes.c_int)]
+    lib.mmlttb_lttb_means.argtypes = [ctypes.c_int, _vp, _vp, _i64, _i64, _vp, _vp, _vp]
     lib.mmlttb_profile_enable.argtypes = [ctypes.c_int]
     lib.mmlttb_profile_read.argtypes = [ctypes.c_char_p, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_i64)]
     lib.mmlttb_profile_samples.argtypes = [ctypes.c_char_p, ctypes.POINTER(ctypes.c_float), _i64,
                                            ctypes.POINTER(_i64)]
-    for f in ("mmlttb_minmax", "mmlttb_lttb", "mmlttb_minmaxlttb", "mmlttb_minmaxlttb_batched", "mmlttb_m4",
+    for f in ("mmlttb_minmax", "mmlttb_lttb", "mmlttb_minmaxlttb", "mmlttb_lttb_means", "mmlttb_minmaxlttb_batched",
+              "mmlttb_m4",
               "mmlttb_minmax_xbins", "mmlttb_minmaxlttb_xbins", "mmlttb_minmax_typed", "mmlttb_minmaxlttb_typed",
               "mmlttb_minmax_simplify",
               "mmlttb_everynth", "mmlttb_set_graph_cache", "mmlttb_graph_cache_stats", "mmlttb_set_tuning",

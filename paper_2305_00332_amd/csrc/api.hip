@@ -911,6 +911,30 @@ int mmlttb_lttb(int xk, const int64_t *x, const float *y, int64_t n, int64_t n_o
     return ok();
 }
 
+int mmlttb_lttb_means(int xk, const int64_t *x, const float *y, int64_t m, int64_t n_out, double *MX, double *MY,
+                      void *stream)
+{
+    int rc = check_series(xk, x, y, m, n_out);
+    if (rc)
+        return rc;
+    if (m <= n_out)
+        return fail(MMLTTB_EINVAL, "m must exceed n_out (LTTB keeps every point otherwise), got m=%lld n_out=%lld",
+                    (long long)m, (long long)n_out);
+    if (!MX || !MY || ((uintptr_t)MX & 7u) || ((uintptr_t)MY & 7u))
+        return fail(MMLTTB_EINVAL, "MX and MY must be non-NULL and 8-byte aligned");
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t B = n_out - 2;
+    const Split bk = make_split(m - 2, B);
+    const int64_t maxb = bk.q + (bk.r ? 1 : 0);
+    // as in mmlttb_lttb: one thread per bucket up to 64 points, else a workgroup per bucket
+    if (maxb <= 64) {
+        MMLTTB_LAUNCH("bucket_mean", s, launch_bucket_mean_small(x, y, nullptr, m, B, MX, MY, s));
+    } else {
+        MMLTTB_LAUNCH("bucket_mean_wide", s, launch_bucket_mean_wide(x, y, m, B, MX, MY, nullptr, s));
+    }
+    return ok();
+}
+
 int mmlttb_minmaxlttb(int xk, const int64_t *x, const float *y, int64_t n, int64_t n_out, int32_t r_ps,
                       int64_t *out_idx, void *ws, size_t ws_bytes, void *stream)
 {

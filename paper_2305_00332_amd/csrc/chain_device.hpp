@@ -23,11 +23,25 @@ __device__ inline void next_bucket_range(const Split &bk, int64_t m, int64_t k, 
 // Next-bucket mean of bucket k by one thread: exact sums of X and Y, each
 // rounded once to binary64, then one binary64 division by the count.
 // XP == NULL means x = position.
-__device__ inline void bucket_mean_one(const int64_t *__restrict__ XP, const float *__restrict__ YP, const Split &bk,
-                                       int64_t m, int64_t k, double &mx, double &my)
+//
+// Buckets of at most kFastMean points take a short form that gives the same
+// two binary64 values, with the loads of up to kFastLoad points issued
+// together:
+//  - X: every |x| at most 2^48, so the int64 sum of at most 16 stays within
+//    2^52 and converts to binary64 exactly;
+//  - Y: a float32 is mant * 2^(s - 149) with mant < 2^24 and s = max(E, 1) - 1
+//    (E: biased exponent). If the nonzero values span s_min..s_max with
+//    (s_max - s_min) + 24 + bits(count) <= 53, every partial sum is a multiple
+//    of 2^(s_min - 149) below 2^(s_min - 149 + 53) in magnitude, so the
+//    binary64 additions are exact and the sum needs no rounding.
+// Otherwise (more points, a larger |x|, or Y values too far apart in scale)
+// the exact accumulators run.
+constexpr int kFastMean = 16;
+constexpr int kFastLoad = 8;
+
+__device__ inline void bucket_mean_exact(const int64_t *__restrict__ XP, const float *__restrict__ YP, int64_t g0,
+                                         int64_t g1, double &mx, double &my)
 {
-    int64_t g0, g1;
-    next_bucket_range(bk, m, k, g0, g1);
     I64ExactSum sx;
     F32ExactSum sy;
     sx.clear();
@@ -39,6 +53,62 @@ __device__ inline void bucket_mean_one(const int64_t *__restrict__ XP, const flo
     const double c = (double)(g1 - g0);
     mx = sx.round() / c;
     my = sy.round() / c;
+}
+
+// Folds one point into the short form's state.
+struct FastMeanAcc {
+    int64_t sx = 0;
+    double sy = 0.0;
+    int smin = 255, smax = -1;
+    bool x_small = true;
+    __device__ void add(int64_t x, float y)
+    {
+        sx = (int64_t)((uint64_t)sx + (uint64_t)x); // wraps, never overflows; used only when every |x| <= 2^48
+        x_small = x_small && (uint64_t)x + (1ull << 48) < (1ull << 49);
+        sy += (double)y;
+        const uint32_t bits = __float_as_uint(y);
+        const int e = (int)((bits >> 23) & 0xffu);
+        const int sc = e ? e - 1 : 0;
+        const bool nz = (bits & 0x7fffffffu) != 0u;
+        smin = (nz && sc < smin) ? sc : smin;
+        smax = (nz && sc > smax) ? sc : smax;
+    }
+};
+
+__device__ inline void bucket_mean_one(const int64_t *__restrict__ XP, const float *__restrict__ YP, const Split &bk,
+                                       int64_t m, int64_t k, double &mx, double &my)
+{
+    int64_t g0, g1;
+    next_bucket_range(bk, m, k, g0, g1);
+    const int cnt = (int)(g1 - g0 < kFastMean + 1 ? g1 - g0 : kFastMean + 1);
+    if (cnt > kFastMean) {
+        bucket_mean_exact(XP, YP, g0, g1, mx, my);
+        return;
+    }
+    int64_t xs[kFastLoad];
+    float ys[kFastLoad];
+#pragma unroll
+    for (int u = 0; u < kFastLoad; ++u) {
+        if (u < cnt) {
+            xs[u] = XP ? XP[g0 + u] : g0 + u;
+            ys[u] = YP[g0 + u];
+        }
+    }
+    FastMeanAcc a;
+#pragma unroll
+    for (int u = 0; u < kFastLoad; ++u)
+        if (u < cnt)
+            a.add(xs[u], ys[u]);
+    for (int u = kFastLoad; u < cnt; ++u)
+        a.add(XP ? XP[g0 + u] : g0 + u, YP[g0 + u]);
+    const int cbits = 32 - __clz(cnt);
+    if (!a.x_small || (a.smax >= 0 && (a.smax - a.smin) + 24 + cbits > 53)) {
+        bucket_mean_exact(XP, YP, g0, g1, mx, my);
+        return;
+    }
+    const double c = (double)cnt;
+    mx = (double)a.sx / c;
+    my = a.sy / c;
 }
 
 // Phase 1 of the segmented chain for chain segment s (buckets

@@ -211,6 +211,19 @@ def everynth(n: int, n_out: int, out=None, device="cuda"):
     return out[: min(n, n_out)]
 
 
+def lttb_means(y, n_out: int, x=None, MX=None, MY=None):
+    """(MX, MY): the next-bucket means LTTB takes over the m = len(y) given
+    points (m > n_out), float64 device tensors of n_out - 2 values."""
+    lib = _lib.load()
+    xk = _as_series(y, x)
+    B = n_out - 2
+    MX = MX if MX is not None else torch.empty(max(B, 1), dtype=torch.float64, device=y.device)
+    MY = MY if MY is not None else torch.empty(max(B, 1), dtype=torch.float64, device=y.device)
+    _lib.check(lib.mmlttb_lttb_means(xk, _lib.ptr(x), y.data_ptr(), y.numel(), n_out, MX.data_ptr(), MY.data_ptr(),
+                                     _lib.stream_ptr()))
+    return MX[:B], MY[:B]
+
+
 def lttb(y, n_out: int, x=None, out=None, ws=None):
     """Plain LTTB over every point (the comparator)."""
     lib = _lib.load()

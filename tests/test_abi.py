@@ -200,3 +200,17 @@ def test_profile_samples_host_checks(lib):
         assert cnt.value == 0
     finally:
         assert lib.mmlttb_profile_enable(0) == 0
+
+
+def test_lttb_means_host_checks(lib):
+    """The means call validates on the host before any launch."""
+    _setup(lib)
+    vp, i64 = ctypes.c_void_p, ctypes.c_int64
+    lib.mmlttb_lttb_means.argtypes = [ctypes.c_int, vp, vp, i64, i64, vp, vp, vp]
+    fake, mx, my = ctypes.c_void_p(0x100000), ctypes.c_void_p(0x200000), ctypes.c_void_p(0x300000)
+    assert lib.mmlttb_lttb_means(0, None, fake, 100, 100, mx, my, None) == -1      # m <= n_out
+    assert lib.mmlttb_lttb_means(0, None, fake, 100, 2, mx, my, None) == -1        # n_out < 3
+    assert lib.mmlttb_lttb_means(0, None, fake, 1000, 100, None, my, None) == -1   # MX NULL
+    assert lib.mmlttb_lttb_means(0, None, fake, 1000, 100, mx, ctypes.c_void_p(0x300004), None) == -1
+    assert lib.mmlttb_lttb_means(1, None, fake, 1000, 100, mx, my, None) == -1     # int64 x missing
+    assert lib.mmlttb_lttb_means(0, fake, fake, 1000, 100, mx, my, None) == -1     # x with implicit
