@@ -278,9 +278,12 @@ __global__ __launch_bounds__(kTileThreads) void k_batch_small(BatchPtrs b)
     }
 }
 
-// One workgroup per series: compaction, then the next-bucket means over P.
-// Identity series (n <= n_out) write their output here.
-__global__ __launch_bounds__(1024) void k_batch_compact(BatchPtrs b)
+// One workgroup per series: compaction (the means follow in k_batch_means).
+// Identity series (n <= n_out) write their output here. The compaction is a
+// chain of dependent steps (keys, scan, x gathers, writes); workgroups of
+// kCompactThreads let four series share a CU instead of one.
+constexpr int kCompactThreads = 256;
+__global__ __launch_bounds__(kCompactThreads) void k_batch_compact(BatchPtrs b)
 {
     __shared__ int wave_tot[17];
     const int tid = threadIdx.x;
@@ -489,7 +492,7 @@ hipError_t launch_batch_small(const BatchPtrs &b, int tile, hipStream_t s)
 
 hipError_t launch_batch_compact(const BatchPtrs &b, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_batch_compact, dim3(cap_grid(b.n_segs, 4096)), dim3(1024), 0, s, b);
+    hipLaunchKernelGGL(k_batch_compact, dim3(cap_grid(b.n_segs, 16384)), dim3(kCompactThreads), 0, s, b);
     return hipGetLastError();
 }
 
