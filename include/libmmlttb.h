@@ -304,7 +304,8 @@ int mmlttb_get_tuning(int *unroll, int64_t *chunk, int *chain, int *tile);
  * system-scope fence) are recorded on the caller's stream around every launch
  * of the named kernels; mmlttb_profile_read
  * synchronises those events and returns the summed milliseconds and the
- * launch count of `kernel` since the last reset. Not thread-safe; off by default. */
+ * launch count of `kernel` since the last reset. Launches on a stream that is
+ * being captured into a graph are not timed. Not thread-safe; off by default. */
 int mmlttb_profile_enable(int on);
 int mmlttb_profile_reset(void);
 int mmlttb_profile_read(const char *kernel, double *total_ms, int64_t *launches);

@@ -105,10 +105,19 @@ hipEvent_t take_event()
     return e;
 }
 
+// Timing events are recorded only on streams that are not being captured
+// into a graph: a captured event would complete only when the graph runs, and
+// reading the profile would wait for it.
+bool capturing(hipStream_t s)
+{
+    hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+    return hipStreamIsCapturing(s, &st) == hipSuccess && st != hipStreamCaptureStatusNone;
+}
+
 template <class F>
 hipError_t timed(const char *name, hipStream_t s, F &&launch)
 {
-    if (!g_prof)
+    if (!g_prof || capturing(s))
         return launch();
     hipEvent_t a = take_event(), b = take_event();
     if (!a || !b)
@@ -130,7 +139,7 @@ struct CallSpan {
     hipEvent_t a = nullptr;
     CallSpan(const char *nm, hipStream_t st) : name(nm), s(st)
     {
-        if (g_prof && (a = take_event()))
+        if (g_prof && !capturing(s) && (a = take_event()))
             (void)hipEventRecord(a, s);
     }
     void close()

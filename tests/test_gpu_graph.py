@@ -1,6 +1,7 @@
 """Batched calls replayed from captured HIP graphs equal eager calls on every
 replay, with the program's own eager work and synchronisations between
-replays, after in-place changes of the input data, and across evictions."""
+replays, after in-place changes of the input data, and across evictions; a
+single-series call captured by the caller replays the same way."""
 from __future__ import annotations
 
 import numpy as np
@@ -106,3 +107,42 @@ def test_eviction_keeps_results_correct():
         assert torch.equal(oa, ra) and torch.equal(ob, rb), f"round {i}"
     entries, hits, captures = ops.graph_cache_stats()
     assert entries == 1 and captures >= 8
+
+
+def test_single_series_call_captured_by_the_caller_with_profiling_on():
+    """A caller captures one MinMaxLTTB call into its own graph while the
+    library's profiling is on: no timing events enter the graph, every replay
+    (with eager work and synchronisations between replays) equals the eager
+    call, and reading the profile afterwards returns."""
+    n, n_out, r_ps = 3_000_001, 1000, 4
+    y = synth.random_walk(n, 12, device="cuda")
+    out = torch.empty(n_out, dtype=torch.int64, device="cuda")
+    ws = torch.empty(ops.workspace_size(n, n_out, r_ps), dtype=torch.uint8, device="cuda")
+    ref = ops.minmaxlttb(y, n_out, r_ps).clone()
+    torch.cuda.synchronize()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):  # warm-up on the capture's kind of stream
+        ops.minmaxlttb(y, n_out, r_ps, out=out, ws=ws)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    ops.profile_enable(True)
+    try:
+        ops.profile_reset()
+        with torch.cuda.graph(g):
+            ops.minmaxlttb(y, n_out, r_ps, out=out, ws=ws)
+        for i in range(4):
+            out.fill_(-1)
+            g.replay()
+            torch.cuda.synchronize()
+            assert torch.equal(out, ref), f"replay {i}"
+            ops.minmaxlttb(y[:10_000], 100, 4)  # eager work between replays
+            torch.cuda.synchronize()
+        tot, cnt = ops.profile_read("minmax_bin_reduce")
+        spans = ops.profile_samples("call_minmaxlttb")
+    finally:
+        ops.profile_enable(False)
+        ops.profile_reset()
+    assert cnt == 4 and len(spans) == 4  # the four eager calls only
+    np.testing.assert_array_equal(ref.cpu().numpy(), oracle.minmaxlttb(y.cpu().numpy(), n_out, r_ps))
