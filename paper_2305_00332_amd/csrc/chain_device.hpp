@@ -260,4 +260,88 @@ __device__ inline int64_t seg_pick(const uint8_t *__restrict__ path, const uint8
     return 1 + split_lo(bk, k) + off;
 }
 
+typedef long long i64x2 __attribute__((ext_vector_type(2)));
+
+// f(p, x, y) with the raw x (int64; the position when X is NULL) and y of
+// every p in [s, e), spread over a workgroup of nthreads
+// threads, each of which sees its points in increasing p. The body comes in
+// groups of 4 points at a 16-byte boundary of Y: one 16-byte load of y and
+// two 16-byte (or, when X is not aligned with Y, four 8-byte) loads of x per
+// group, kDepth groups per thread in flight. The up to 3 points before the
+// boundary go to threads 0-2 first, the up to 3 after the last group to
+// threads 0-2 last.
+template <int kDepth, bool kHasX, class F>
+__device__ inline void scan_groups_x(const int64_t *__restrict__ X, const float *__restrict__ Y, int64_t s,
+                                     int64_t e, int tid, int nthreads, F &&f)
+{
+    const uint64_t ya = (uint64_t)(uintptr_t)(Y + s);
+    int64_t a0 = s + (int64_t)(((16u - (unsigned)(ya & 15u)) & 15u) >> 2);
+    a0 = a0 < e ? a0 : e;
+    if (s + tid < a0)
+        f(s + tid, kHasX ? X[s + tid] : s + tid, Y[s + tid]);
+    const int64_t nq = (e - a0) >> 2;
+    const f32x4 *__restrict__ Y4 = reinterpret_cast<const f32x4 *>(Y + a0);
+    const bool x16 = kHasX && ((((uint64_t)(uintptr_t)(X + a0)) & 15u) == 0);
+    auto load_x = [&](int64_t q, int64_t (&xv)[4]) {
+        const int64_t p0 = a0 + 4 * q;
+        if (!kHasX) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                xv[i] = p0 + i;
+        } else if (x16) {
+            const i64x2 *__restrict__ X2 = reinterpret_cast<const i64x2 *>(X + p0);
+            const i64x2 lo = X2[0], hi = X2[1];
+            xv[0] = lo.x;
+            xv[1] = lo.y;
+            xv[2] = hi.x;
+            xv[3] = hi.y;
+        } else {
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                xv[i] = X[p0 + i];
+        }
+    };
+    int64_t q = tid;
+    for (; q + (int64_t)(kDepth - 1) * nthreads < nq; q += (int64_t)kDepth * nthreads) {
+        f32x4 yv[kDepth];
+        int64_t xv[kDepth][4];
+#pragma unroll
+        for (int u = 0; u < kDepth; ++u) {
+            yv[u] = Y4[q + (int64_t)u * nthreads];
+            load_x(q + (int64_t)u * nthreads, xv[u]);
+        }
+#pragma unroll
+        for (int u = 0; u < kDepth; ++u) {
+            const int64_t p0 = a0 + 4 * (q + (int64_t)u * nthreads);
+            f(p0, xv[u][0], yv[u].x);
+            f(p0 + 1, xv[u][1], yv[u].y);
+            f(p0 + 2, xv[u][2], yv[u].z);
+            f(p0 + 3, xv[u][3], yv[u].w);
+        }
+    }
+    for (; q < nq; q += nthreads) {
+        const f32x4 yv = Y4[q];
+        int64_t xv[4];
+        load_x(q, xv);
+        const int64_t p0 = a0 + 4 * q;
+        f(p0, xv[0], yv.x);
+        f(p0 + 1, xv[1], yv.y);
+        f(p0 + 2, xv[2], yv.z);
+        f(p0 + 3, xv[3], yv.w);
+    }
+    const int64_t t0 = a0 + 4 * nq;
+    if (t0 + tid < e)
+        f(t0 + tid, kHasX ? X[t0 + tid] : t0 + tid, Y[t0 + tid]);
+}
+
+template <int kDepth = 2, class F>
+__device__ inline void scan_groups(const int64_t *__restrict__ X, const float *__restrict__ Y, int64_t s, int64_t e,
+                                   int tid, int nthreads, F &&f)
+{
+    if (X)
+        scan_groups_x<kDepth, true>(X, Y, s, e, tid, nthreads, f);
+    else
+        scan_groups_x<kDepth, false>(X, Y, s, e, tid, nthreads, f);
+}
+
 } // namespace mmlttb

@@ -64,10 +64,10 @@ __global__ __launch_bounds__(256) void k_bucket_mean_small(const int64_t *__rest
 }
 
 // One workgroup (256 threads) per bucket (whole-series LTTB: large buckets).
-// Wide buckets: one workgroup per bucket k sums bucket k+1 (8 loads per
-// thread in flight). With YR != NULL it also records the y range of the
-// bucket it reads (YR[k + 1]; workgroup 0 adds YR[0] by one more pass), which
-// the table form of the chain uses.
+// Wide buckets: one workgroup per bucket k sums bucket k+1 (16-byte loads,
+// 8 points per thread in flight). With YR != NULL it also records the y range
+// of the bucket it reads (YR[k + 1]; workgroup 0 adds YR[0] by one more
+// pass), which the table form of the chain uses.
 __global__ __launch_bounds__(256) void k_bucket_mean_wide(const int64_t *__restrict__ X, const float *__restrict__ Y,
                                                           int64_t m, int64_t B, double *__restrict__ MX,
                                                           double *__restrict__ MY, float2 *__restrict__ YR)
@@ -113,30 +113,12 @@ __global__ __launch_bounds__(256) void k_bucket_mean_wide(const int64_t *__restr
         sx.clear();
         sy.clear();
         float lo = kInf, hi = -kInf;
-        constexpr int kDepth = 8;
-        int64_t i = g0 + tid;
-        for (; i + (kDepth - 1) * 256 < g1; i += kDepth * 256) {
-            int64_t xs[kDepth];
-            float ys[kDepth];
-#pragma unroll
-            for (int u = 0; u < kDepth; ++u) {
-                xs[u] = X ? X[i + u * 256] : i + u * 256;
-                ys[u] = Y[i + u * 256];
-            }
-#pragma unroll
-            for (int u = 0; u < kDepth; ++u) {
-                sx.add(xs[u]);
-                sy.add(ys[u]);
-                lo = fminf(lo, ys[u]);
-                hi = fmaxf(hi, ys[u]);
-            }
-        }
-        for (; i < g1; i += blockDim.x) {
-            sx.add(X ? X[i] : i);
-            sy.add(Y[i]);
-            lo = fminf(lo, Y[i]);
-            hi = fmaxf(hi, Y[i]);
-        }
+        scan_groups<2>(X, Y, g0, g1, tid, (int)blockDim.x, [&](int64_t, int64_t x, float y) {
+            sx.add(x);
+            sy.add(y);
+            lo = fminf(lo, y);
+            hi = fmaxf(hi, y);
+        });
         if (YR && k + 1 < B)
             yrange(lo, hi, &YR[k + 1]);
         sy.normalize();

@@ -356,7 +356,8 @@ __device__ inline void table_group(const int64_t *__restrict__ X, const float *_
         best[c] = -1.0;
         bi[c] = 0x7fffffff;
     }
-    scan_points<4>(X, Y, s + tid, e, blockDim.x, [&](int64_t p, double xj, double yj) {
+    scan_groups<2>(X, Y, s, e, tid, (int)blockDim.x, [&](int64_t p, int64_t xraw, float yraw) {
+        const double xj = (double)xraw, yj = (double)yraw;
 #pragma unroll
         for (int c = 0; c < kTabGroup; ++c) {
             const double ar = lttb_area2(xa[c], ya[c], xj, yj, mx, my);
