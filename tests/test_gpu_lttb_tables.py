@@ -92,3 +92,23 @@ def test_repeated_calls_reuse_the_workspace():
     second = ops.lttb(z, n_out, ws=ws).cpu().numpy()  # tables of the first call must not leak
     np.testing.assert_array_equal(second, oracle.lttb(z.cpu().numpy(), n_out, None))
     np.testing.assert_array_equal(first.cpu().numpy(), oracle.lttb(y.cpu().numpy(), n_out, None))
+
+
+@pytest.mark.parametrize("y_off", [0, 1, 2, 3])
+@pytest.mark.parametrize("x_off", [0, 1])
+def test_group_loads_at_every_alignment(y_off, x_off):
+    """The tables and the wide means read 4-point groups from the first
+    16-byte boundary of y, with x in 16-byte pairs when x shares that
+    alignment and point by point otherwise: every start offset of y and x."""
+    n, n_out = 300_001, 102
+    rng = np.random.default_rng(77 + 4 * x_off + y_off)
+    y_np = (np.cumsum(rng.standard_normal(n)) + 5 * rng.standard_normal(n)).astype(np.float32)
+    x_np = np.cumsum(rng.integers(1, 2000, n)).astype(np.int64)
+    ybuf = torch.empty(n + y_off, dtype=torch.float32, device="cuda")
+    ybuf[y_off:] = torch.from_numpy(y_np).to("cuda")
+    xbuf = torch.empty(n + x_off, dtype=torch.int64, device="cuda")
+    xbuf[x_off:] = torch.from_numpy(x_np).to("cuda")
+    got = ops.lttb(ybuf[y_off:], n_out, x=xbuf[x_off:]).cpu().numpy()
+    np.testing.assert_array_equal(got, oracle.lttb(y_np, n_out, x_np))
+    got_i = ops.lttb(ybuf[y_off:], n_out).cpu().numpy()
+    np.testing.assert_array_equal(got_i, oracle.lttb(y_np, n_out))
