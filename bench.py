@@ -706,7 +706,7 @@ def bench_comparator(args):
             "parity_vs_oracle": bool(np.array_equal(out_m.cpu().numpy(), want_m) and np.array_equal(want_omp, want_m))}
     del x, y, y_np, x_np
     res["paper_context"] = {
-        "serial_speedup_vs_lttb": "about 10x (an order of magnitude)",
+        "serial_speedup_vs_lttb": "about 10x",
         "parallel_speedup_vs_lttb": "30x",
         "source": "section 3.2: CPU implementations (a C LTTB, tsdownsample's MinMaxLTTB); hardware, core "
                   "count, N, n_out and r_ps are not stated",
