@@ -13,8 +13,9 @@
  *
  * Conventions shared by every entry point
  * ---------------------------------------
- * - Buffers named x, y, out_idx, out_count, ws are DEVICE pointers owned by the
- *   caller; segs_host is a HOST pointer. The library never allocates or frees
+ * - Buffers named x, y, out_idx, out_count, ws, MX, MY are DEVICE pointers
+ *   owned by the caller; segs_host (and the ms array of mmlttb_profile_samples)
+ *   is a HOST pointer. The library never allocates or frees
  *   device memory inside these calls: scratch lives in the caller's workspace
  *   `ws` of `ws_bytes` bytes, sized by the matching *_workspace_size call.
  * - `stream` is a hipStream_t (NULL = the default stream). Work is enqueued on
