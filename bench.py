@@ -270,6 +270,7 @@ def bench_headline(args):
 
         log("copying y to the host for the oracle")
         y_np = y.cpu().numpy()
+        result["config"]["y_sha256"] = hashlib.sha256(memoryview(y_np).cast("B")).hexdigest()
         times = []
         want = None
         for _ in range(max(1, args.cpu_reps)):
@@ -651,6 +652,8 @@ def bench_comparator(args):
     x, y = synth.composite_series(n, 2, device="cuda")
     torch.cuda.synchronize()
     y_np, x_np = y.cpu().numpy(), x.cpu().numpy()
+    input_sha256 = {"y": hashlib.sha256(memoryview(y_np).cast("B")).hexdigest(),
+                    "x": hashlib.sha256(memoryview(x_np).cast("B")).hexdigest()}
 
     def gpu_time(fn, reps):
         fn()
@@ -664,7 +667,7 @@ def bench_comparator(args):
     omp = oracle.load_openmp()
     res = {"workload": f"one series, n={n}, float32 random walk + 3 sinusoids + noise + 0.01% spikes (seed 2), "
                        f"int64 irregular x; n_out={n_out}", "n": n, "n_out": n_out,
-           "cpu_openmp_threads": oracle.threads(omp)}
+           "cpu_openmp_threads": oracle.threads(omp), "input_sha256": input_sha256}
     log("comparator: GPU whole-series LTTB")
     t_l, out_l = gpu_time(lambda: ops.lttb(y, n_out, x=x), 3)
     c0 = time.perf_counter()
