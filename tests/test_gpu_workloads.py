@@ -74,3 +74,19 @@ def test_one_billion_points(chain_mode):
     np.testing.assert_array_equal(P.cpu().numpy(), oracle.minmax(y_np, 4000, 4))
     del y
     torch.cuda.empty_cache()
+
+
+def test_large_output_sizes(chain_mode):
+    """n_out of 2^20 and 3*10^5 on 5e7 points: 2M and 1.2M bins, a compaction
+    of several rounds in its one workgroup, chains of 32768 segments; whole-
+    series LTTB with 1e6 buckets of ~50 points."""
+    _say("generating 5e7 composite series on the GPU")
+    x, y = synth.composite_series(50_000_000, 9, device="cuda")
+    y_np, x_np = y.cpu().numpy(), x.cpu().numpy()
+    for n_out, r_ps in [(1 << 20, 4), (300_000, 8)]:
+        _say(f"minmaxlttb n=5e7 n_out={n_out} r_ps={r_ps}")
+        got = ops.minmaxlttb(y, n_out, r_ps, x=x).cpu().numpy()
+        np.testing.assert_array_equal(got, oracle.minmaxlttb(y_np, n_out, r_ps, x_np))
+    _say("lttb n=5e7 n_out=1e6")
+    got_l = ops.lttb(y, 1_000_000, x=x).cpu().numpy()
+    np.testing.assert_array_equal(got_l, oracle.lttb(y_np, 1_000_000, x_np))
