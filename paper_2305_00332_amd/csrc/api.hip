@@ -187,7 +187,7 @@ constexpr size_t kAlign = 256;
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 struct MmLayout {
-    size_t keys, m, P, XP, YP, MX, MY, path, finals, start, total;
+    size_t keys, m, P, XP, YP, MX, MY, path, finals, start, tiles, total;
 };
 
 MmLayout mm_layout(int64_t n_out, int32_t r_ps)
@@ -212,6 +212,7 @@ MmLayout mm_layout(int64_t n_out, int32_t r_ps)
     L.path = take(seg_path_bytes(B));
     L.finals = take(seg_finals_bytes(B));
     L.start = take((size_t)seg_count(B));
+    L.tiles = take(8 * (size_t)compact_tiles(nb)); // first slots of the tiled compaction
     L.total = off;
     return L;
 }
@@ -379,7 +380,12 @@ int enqueue_preselect(const int64_t *x, const float *y, int64_t n, int64_t n_out
     if (keys_need_init(g))
         MMLTTB_LAUNCH("init_keys", s, launch_init_keys(keys, nb, s));
     MMLTTB_LAUNCH("minmax_bin_reduce", s, launch_minmax_bin_reduce(y, g, tuning().unroll, keys, s));
-    MMLTTB_LAUNCH("preselect_compact", s, launch_preselect_compact(keys, g.bins, n, x, y, P, XP, YP, m_out, s));
+    if (nb <= kFusedCompactBins) {
+        MMLTTB_LAUNCH("preselect_compact", s, launch_preselect_compact(keys, g.bins, n, x, y, P, XP, YP, m_out, s));
+    } else {
+        MMLTTB_LAUNCH("preselect_compact", s,
+                      launch_compact_tiled(keys, g.bins, n, x, y, P, XP, YP, m_out, at<int64_t>(ws, L.tiles), s));
+    }
     return MMLTTB_OK;
 }
 
@@ -981,8 +987,14 @@ int mmlttb_minmaxlttb(int xk, const int64_t *x, const float *y, int64_t n, int64
         if (keys_need_init(g))
             MMLTTB_LAUNCH("init_keys", s, launch_init_keys(keys, nb, s));
         MMLTTB_LAUNCH("minmax_bin_reduce", s, launch_minmax_bin_reduce(y, g, tuning().unroll, keys, s));
-        MMLTTB_LAUNCH("preselect_compact_means", s,
-                      launch_preselect_compact_means(keys, g.bins, n, x, y, P, XP, YP, m, B, MX, MY, s));
+        if (nb <= kFusedCompactBins) { // one workgroup: compaction, then the means
+            MMLTTB_LAUNCH("preselect_compact_means", s,
+                          launch_preselect_compact_means(keys, g.bins, n, x, y, P, XP, YP, m, B, MX, MY, s));
+        } else { // many bins: tiled compaction, then the means over many workgroups
+            MMLTTB_LAUNCH("preselect_compact", s,
+                          launch_compact_tiled(keys, g.bins, n, x, y, P, XP, YP, m, at<int64_t>(ws, L.tiles), s));
+            MMLTTB_LAUNCH("bucket_mean", s, launch_bucket_mean_small(XP, YP, m, 0, B, MX, MY, s));
+        }
     }
     // preselected points per bucket: at most ceil((m-2)/B) with m - 2 <= 2*nb
     const int64_t maxb_bound = (2 * nb + B - 1) / B;

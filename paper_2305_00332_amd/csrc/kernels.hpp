@@ -157,6 +157,15 @@ inline size_t seg_finals_bytes(int64_t B) { return (size_t)seg_count(B) * kSegSt
 hipError_t launch_init_keys(unsigned long long *keys, int64_t nb, hipStream_t s);
 hipError_t launch_minmax_bin_reduce(const float *y, const MinMaxGeom &g, int unroll, unsigned long long *keys,
                                     hipStream_t s);
+// Bins per workgroup of the tiled compaction (1024 threads, 4 slabs), and the
+// bin count above which it replaces the one-workgroup compaction: that one
+// walks every bin in rounds of 4096 (nb = 32768: 105 us with the means).
+constexpr int64_t kCompactTileBins = 4096;
+constexpr int64_t kFusedCompactBins = 16384;
+inline int64_t compact_tiles(int64_t nb) { return (nb + kCompactTileBins - 1) / kCompactTileBins; }
+hipError_t launch_compact_tiled(const unsigned long long *keys, const Split &bins, int64_t n, const int64_t *x,
+                                const float *y, int64_t *P, int64_t *XP, float *YP, int64_t *m_out, int64_t *tile_slot,
+                                hipStream_t s);
 hipError_t launch_preselect_compact(const unsigned long long *keys, const Split &bins, int64_t n, const int64_t *x,
                                     const float *y, int64_t *P, int64_t *XP, float *YP, int64_t *m_out, hipStream_t s);
 hipError_t launch_preselect_compact_means(const unsigned long long *keys, const Split &bins, int64_t n,

@@ -99,6 +99,65 @@ __global__ __launch_bounds__(1024) void k_preselect_compact_means(
         bucket_mean_one(XP, YP, bk, m, k, MX[k], MY[k]);
 }
 
+// Tiled compaction, for many bins: tile t is bins [t*kCompactTileBins,
+// (t+1)*kCompactTileBins), one workgroup of 1024 threads (one round of
+// compact_bin_range) each. Three launches: the tiles' point counts; one
+// workgroup turning them into each tile's first slot in P (after the first
+// point) and writing the first and last points and m; the tiles writing P.
+static_assert(kCompactTileBins == 1024 * kCompactBins, "a compaction tile is one round of 1024 threads");
+
+__global__ __launch_bounds__(1024) void k_compact_count(const unsigned long long *__restrict__ keys, Split bins,
+                                                        int64_t *__restrict__ tile_slot)
+{
+    __shared__ int wave_tot[17];
+    const int64_t b0 = (int64_t)blockIdx.x * kCompactTileBins;
+    int c = 0;
+#pragma unroll
+    for (int u = 0; u < kCompactBins; ++u) {
+        const int64_t b = b0 + (int64_t)u * blockDim.x + threadIdx.x;
+        if (b < bins.parts)
+            c += bin_kept(keys, bins, b);
+    }
+    int total;
+    (void)block_exclusive_scan(c, wave_tot, total);
+    if (threadIdx.x == 0)
+        tile_slot[blockIdx.x] = total;
+}
+
+__global__ __launch_bounds__(1024) void k_compact_slots(int64_t *__restrict__ tile_slot, int64_t tiles, int64_t n,
+                                                        const int64_t *__restrict__ x, const float *__restrict__ y,
+                                                        int64_t *__restrict__ P, int64_t *__restrict__ XP,
+                                                        float *__restrict__ YP, int64_t *__restrict__ m_out)
+{
+    __shared__ int wave_tot[17];
+    int64_t running = 1; // slot 0 is the first point
+    for (int64_t base = 0; base < tiles; base += blockDim.x) {
+        const int64_t t = base + threadIdx.x;
+        const int c = t < tiles ? (int)tile_slot[t] : 0; // at most 2 * kCompactTileBins
+        int total;
+        const int off = block_exclusive_scan(c, wave_tot, total);
+        if (t < tiles)
+            tile_slot[t] = running + off;
+        running += total;
+    }
+    if (threadIdx.x == 0) {
+        put_end_point(0, 0, x, y, P, XP, YP);
+        put_end_point(running, n - 1, x, y, P, XP, YP);
+        *m_out = running + 1;
+    }
+}
+
+__global__ __launch_bounds__(1024) void k_compact_tiles(const unsigned long long *__restrict__ keys, Split bins,
+                                                        const int64_t *__restrict__ tile_slot,
+                                                        const int64_t *__restrict__ x, int64_t *__restrict__ P,
+                                                        int64_t *__restrict__ XP, float *__restrict__ YP)
+{
+    __shared__ int wave_tot[17];
+    const int64_t b0 = (int64_t)blockIdx.x * kCompactTileBins;
+    const int64_t b1 = b0 + kCompactTileBins < bins.parts ? b0 + kCompactTileBins : bins.parts;
+    (void)compact_bin_range(keys, bins, b0, b1, tile_slot[blockIdx.x], x, P, XP, YP, wave_tot);
+}
+
 // ---------------------------------------------------------------- launches
 
 hipError_t launch_init_keys(unsigned long long *keys, int64_t nb, hipStream_t s)
@@ -138,6 +197,24 @@ hipError_t launch_preselect_compact_means(const unsigned long long *keys, const 
 {
     hipLaunchKernelGGL(k_preselect_compact_means, dim3(1), dim3(1024), 0, s, keys, bins, n, x, y, P, XP, YP, m_out, B,
                        MX, MY);
+    return hipGetLastError();
+}
+
+hipError_t launch_compact_tiled(const unsigned long long *keys, const Split &bins, int64_t n, const int64_t *x,
+                                const float *y, int64_t *P, int64_t *XP, float *YP, int64_t *m_out, int64_t *tile_slot,
+                                hipStream_t s)
+{
+    const int64_t tiles = compact_tiles(bins.parts);
+    if (tiles > 0x7fffffff)
+        return hipErrorInvalidConfiguration;
+    hipLaunchKernelGGL(k_compact_count, dim3((unsigned)tiles), dim3(1024), 0, s, keys, bins, tile_slot);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        return e;
+    hipLaunchKernelGGL(k_compact_slots, dim3(1), dim3(1024), 0, s, tile_slot, tiles, n, x, y, P, XP, YP, m_out);
+    if ((e = hipGetLastError()) != hipSuccess)
+        return e;
+    hipLaunchKernelGGL(k_compact_tiles, dim3((unsigned)tiles), dim3(1024), 0, s, keys, bins, tile_slot, x, P, XP, YP);
     return hipGetLastError();
 }
 

@@ -429,35 +429,56 @@ __device__ inline int block_exclusive_scan(int c, int *wave_tot, int &total)
     return r;
 }
 
-// Decode the bin keys into the sorted distinct preselection P (section 3: the
-// first and last points join the per-bin extrema). Bins are disjoint and in
-// index order, so emitting each bin's pair in index order yields P sorted.
-// Called by a whole workgroup (blockDim a multiple of 64, at most 1024). A
-// round covers kCompactBins slabs of blockDim consecutive bins, bin
-// base + u*blockDim + tid for thread tid: the keys of all slabs are decoded
-// and scanned slab by slab, then the x gathers of all of them are in flight
-// together. Optionally writes
-// XP (raw x, gathered, or the index for implicit x) and YP (decoded from the
-// keys, so y is not read again). A key offset past its bin (keys no part ever
-// reached, or values that never compare, such as NaN) decodes to the bin's
-// first point, so every index stays inside its bin. wave_tot: 17 ints of LDS.
+// One bin's kept points from its key pair: the lowest index of the minimum and
+// of the maximum (offsets inside the bin), in index order; 1 when they
+// coincide, else 2. A key offset past its bin (keys no part ever reached, or
+// values that never compare, such as NaN) decodes to the bin's first point, so
+// every index stays inside its bin.
+__device__ inline int decode_bin(unsigned long long kmin, unsigned long long kmax, int64_t blo, int64_t len,
+                                 int64_t &i0, int64_t &i1, float &v0, float &v1)
+{
+    int64_t omin = min_key_offset(kmin), omax = max_key_offset(kmax);
+    omin = omin < len ? omin : 0;
+    omax = omax < len ? omax : 0;
+    const int64_t imin = 1 + blo + omin, imax = 1 + blo + omax;
+    const float vmin = key_value(kmin), vmax = key_value(kmax);
+    const bool lo_min = imin < imax;
+    i0 = lo_min ? imin : imax;
+    i1 = lo_min ? imax : imin;
+    v0 = lo_min ? vmin : vmax;
+    v1 = lo_min ? vmax : vmin;
+    return (imin == imax) ? 1 : 2;
+}
+
+// Points of bin b alone (as decode_bin counts them).
+__device__ inline int bin_kept(const unsigned long long *__restrict__ keys, const Split &bins, int64_t b)
+{
+    const int64_t blo = split_lo(bins, b), len = split_lo(bins, b + 1) - blo;
+    int64_t i0, i1;
+    float v0, v1;
+    return decode_bin(keys[2 * b], keys[2 * b + 1], blo, len, i0, i1, v0, v1);
+}
+
+// Decode the keys of bins [b0, b1) into P from slot `first` on (section 3:
+// the per-bin extrema; the first and last points are the caller's). Bins are
+// disjoint and in index order, so emitting each bin's pair in index order
+// yields P sorted. Called by a whole workgroup (blockDim a multiple of 64, at
+// most 1024). A round covers kCompactBins slabs of blockDim consecutive bins,
+// bin base + u*blockDim + tid for thread tid: the keys of all slabs are
+// decoded and scanned slab by slab, then the x gathers of all of them are in
+// flight together. Optionally writes XP (raw x, gathered, or the index for
+// implicit x) and YP (decoded from the keys, so y is not read again).
+// Returns the slot after the last one written (the same in every thread).
+// wave_tot: 17 ints of LDS.
 constexpr int kCompactBins = 4;
-__device__ inline void compact_keys(const unsigned long long *__restrict__ keys, const Split &bins, int64_t n,
-                                    const int64_t *__restrict__ x, const float *__restrict__ y,
-                                    int64_t *__restrict__ P, int64_t *__restrict__ XP, float *__restrict__ YP,
-                                    int64_t *__restrict__ m_out, int *wave_tot)
+__device__ inline int64_t compact_bin_range(const unsigned long long *__restrict__ keys, const Split &bins, int64_t b0,
+                                            int64_t b1, int64_t first, const int64_t *__restrict__ x,
+                                            int64_t *__restrict__ P, int64_t *__restrict__ XP,
+                                            float *__restrict__ YP, int *wave_tot)
 {
     const int tid = threadIdx.x;
-    int64_t running = 1;
-    if (tid == 0) {
-        P[0] = 0;
-        if (XP) {
-            XP[0] = x ? x[0] : 0;
-            YP[0] = y[0];
-        }
-    }
-    const int64_t nb = bins.parts;
-    for (int64_t base = 0; base < nb; base += (int64_t)blockDim.x * kCompactBins) {
+    int64_t running = first;
+    for (int64_t base = b0; base < b1; base += (int64_t)blockDim.x * kCompactBins) {
         int64_t i0[kCompactBins], i1[kCompactBins], off[kCompactBins];
         float v0[kCompactBins], v1[kCompactBins];
         int cnt[kCompactBins];
@@ -465,7 +486,7 @@ __device__ inline void compact_keys(const unsigned long long *__restrict__ keys,
 #pragma unroll
         for (int u = 0; u < kCompactBins; ++u) {
             const int64_t b = base + (int64_t)u * blockDim.x + tid;
-            if (b < nb) {
+            if (b < b1) {
                 kmin[u] = keys[2 * b];
                 kmax[u] = keys[2 * b + 1];
             }
@@ -476,19 +497,9 @@ __device__ inline void compact_keys(const unsigned long long *__restrict__ keys,
             cnt[u] = 0;
             i0[u] = i1[u] = 0;
             v0[u] = v1[u] = 0.0f;
-            if (b < nb) {
+            if (b < b1) {
                 const int64_t blo = split_lo(bins, b), len = split_lo(bins, b + 1) - blo;
-                int64_t omin = min_key_offset(kmin[u]), omax = max_key_offset(kmax[u]);
-                omin = omin < len ? omin : 0;
-                omax = omax < len ? omax : 0;
-                const int64_t imin = 1 + blo + omin, imax = 1 + blo + omax;
-                const float vmin = key_value(kmin[u]), vmax = key_value(kmax[u]);
-                const bool lo_min = imin < imax;
-                i0[u] = lo_min ? imin : imax;
-                i1[u] = lo_min ? imax : imin;
-                v0[u] = lo_min ? vmin : vmax;
-                v1[u] = lo_min ? vmax : vmin;
-                cnt[u] = (imin == imax) ? 1 : 2;
+                cnt[u] = decode_bin(kmin[u], kmax[u], blo, len, i0[u], i1[u], v0[u], v1[u]);
             }
             int total;
             off[u] = running + block_exclusive_scan(cnt[u], wave_tot, total);
@@ -520,12 +531,34 @@ __device__ inline void compact_keys(const unsigned long long *__restrict__ keys,
             }
         }
     }
-    if (tid == 0) {
-        P[running] = n - 1;
-        if (XP) {
-            XP[running] = x ? x[n - 1] : n - 1;
-            YP[running] = y[n - 1];
-        }
+    return running;
+}
+
+// The first point (slot 0) or the last point of the series into P (and XP,
+// YP): one thread.
+__device__ inline void put_end_point(int64_t slot, int64_t i, const int64_t *__restrict__ x,
+                                     const float *__restrict__ y, int64_t *__restrict__ P, int64_t *__restrict__ XP,
+                                     float *__restrict__ YP)
+{
+    P[slot] = i;
+    if (XP) {
+        XP[slot] = x ? x[i] : i;
+        YP[slot] = y[i];
+    }
+}
+
+// The whole preselection P = {0} + every bin's kept points + {n-1} by one
+// workgroup, and its size into *m_out.
+__device__ inline void compact_keys(const unsigned long long *__restrict__ keys, const Split &bins, int64_t n,
+                                    const int64_t *__restrict__ x, const float *__restrict__ y,
+                                    int64_t *__restrict__ P, int64_t *__restrict__ XP, float *__restrict__ YP,
+                                    int64_t *__restrict__ m_out, int *wave_tot)
+{
+    if (threadIdx.x == 0)
+        put_end_point(0, 0, x, y, P, XP, YP);
+    const int64_t running = compact_bin_range(keys, bins, 0, bins.parts, 1, x, P, XP, YP, wave_tot);
+    if (threadIdx.x == 0) {
+        put_end_point(running, n - 1, x, y, P, XP, YP);
         *m_out = running + 1;
     }
 }

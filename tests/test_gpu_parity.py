@@ -261,3 +261,22 @@ def test_waves_looping_over_long_items(unroll, chunk, n_out, r_ps):
         np.testing.assert_array_equal(idx4[: int(m4)].cpu().numpy(), oracle.m4(y_np, 4 * n_out * r_ps // 2))
     finally:
         ops.set_tuning(*old)
+
+
+@pytest.mark.parametrize("n_out,r_ps", [(8192, 4), (16385, 2), (10240, 4), (10241, 4), (20000, 4), (5000, 16)],
+                         ids=lambda v: str(v))
+@pytest.mark.parametrize("xk", [0, 1, 2])
+def test_tiled_compaction_around_its_threshold(n_out, r_ps, xk):
+    """More than 16384 bins take the tiled compaction (tiles of 4096 bins:
+    counts, slots, tiles) and the means over many workgroups; 16384 bins
+    (n_out = 8192, r_ps = 4) the one-workgroup form. Ragged last tiles, bins of
+    a few points, and every x kind."""
+    n = 300_001 + xk
+    seed = 600 + 3 * n_out + xk
+    y_np = _series("ties" if xk == 1 else "walk", n, seed)
+    x_np = _x_for(xk, n)
+    y, x = _dev(y_np, xk), _devx(x_np)
+    got = ops.minmaxlttb(y, n_out, r_ps, x=x).cpu().numpy()
+    np.testing.assert_array_equal(got, oracle.minmaxlttb(y_np, n_out, r_ps, x_np))
+    P, m = ops.minmax(y, n_out, r_ps, x=x)
+    np.testing.assert_array_equal(P[: int(m)].cpu().numpy(), oracle.minmax(y_np, n_out, r_ps))
