@@ -211,7 +211,7 @@ MmLayout mm_layout(int64_t n_out, int32_t r_ps)
     L.MY = take(8 * (size_t)B);
     L.path = take(seg_path_bytes(B));
     L.finals = take(seg_finals_bytes(B));
-    L.start = take((size_t)seg_count(B));
+    L.start = take(seg_start_bytes(B));
     L.tiles = take(8 * (size_t)compact_tiles(nb)); // first slots of the tiled compaction
     L.total = off;
     return L;
@@ -235,7 +235,7 @@ LtLayout lt_layout(int64_t n_out)
     L.MY = take(8 * (size_t)B);
     L.path = take(seg_path_bytes(B));
     L.finals = take(seg_finals_bytes(B));
-    L.start = take((size_t)seg_count(B));
+    L.start = take(seg_start_bytes(B));
     const size_t tb = B <= kTableMaxBuckets ? (size_t)B : 0; // transition tables (wide buckets)
     L.yr = take(8 * tb);
     L.cand_cnt = take(4 * tb);
@@ -473,7 +473,7 @@ TyLayout ty_layout(int64_t n_out, int32_t r_ps)
     L.MY = take(8 * (size_t)B);
     L.path = take(seg_path_bytes(B));
     L.finals = take(seg_finals_bytes(B));
-    L.start = take((size_t)seg_count(B));
+    L.start = take(seg_start_bytes(B));
     L.total = off;
     return L;
 }

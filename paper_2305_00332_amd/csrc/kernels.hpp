@@ -151,6 +151,21 @@ hipError_t launch_batch_link_emit(const BatchPtrs &b, hipStream_t s);
 hipError_t launch_batch_chain_seq(const BatchPtrs &b, hipStream_t s);
 
 inline int64_t seg_count(int64_t B) { return (B + kSegLen - 1) / kSegLen; }
+// Two-level link for long chains (more than kTwoLevelLink segments): the S-1
+// segment-to-segment transitions are cut into chunks of kLinkChunk; each
+// chunk's composed start->exit map is formed in parallel, one chain over the
+// chunk maps gives every chunk's start, and each chunk then fills its own
+// segments' starts. In the workspace region of the S start lanes they are
+// followed, from the next multiple of 64 bytes, by the chunk maps (64 bytes
+// each) and the chunk starts (one byte per chunk, plus one).
+constexpr int kLinkChunk = 64;
+constexpr int64_t kTwoLevelLink = 2 * kChaseWindow;
+inline int64_t seg_chunks(int64_t B) { return (seg_count(B) - 1 + kLinkChunk - 1) / kLinkChunk; }
+inline int64_t seg_maps_offset(int64_t S) { return (S + 63) / 64 * 64; }
+inline size_t seg_start_bytes(int64_t B)
+{
+    return (size_t)seg_maps_offset(seg_count(B)) + (size_t)seg_chunks(B) * kSegStarts + (size_t)seg_chunks(B) + 1;
+}
 inline size_t seg_path_bytes(int64_t B) { return (size_t)seg_count(B) * kSegStarts * kSegLen; }
 inline size_t seg_finals_bytes(int64_t B) { return (size_t)seg_count(B) * kSegStarts; }
 

@@ -308,6 +308,53 @@ __global__ __launch_bounds__(kSegStarts) void k_lttb_chain_seg(Args a)
              a.finals);
 }
 
+// Two-level link, step 1: chunk c's composed map, lane l following start
+// lane l through the chunk's transitions (staged in LDS).
+__global__ __launch_bounds__(kSegStarts) void k_link_chunk_maps(const uint8_t *__restrict__ finals, int64_t S,
+                                                               uint8_t *__restrict__ maps)
+{
+    __shared__ uint8_t F[kLinkChunk * kSegStarts];
+    const int64_t t0 = (int64_t)blockIdx.x * kLinkChunk;
+    const int nt = (int)((t0 + kLinkChunk < S - 1) ? kLinkChunk : S - 1 - t0);
+    for (int q = threadIdx.x; q < nt * kSegStarts; q += blockDim.x)
+        F[q] = finals[t0 * kSegStarts + q];
+    __syncthreads();
+    int cur = threadIdx.x;
+    for (int t = 0; t < nt; ++t)
+        cur = F[t * kSegStarts + cur];
+    maps[(int64_t)blockIdx.x * kSegStarts + threadIdx.x] = (uint8_t)cur;
+}
+
+// Step 2: the chain over the chunk maps from lane 0 (seg_link on them).
+__global__ __launch_bounds__(1024) void k_link_chunk_starts(const uint8_t *__restrict__ maps, int64_t chunks,
+                                                            uint8_t *__restrict__ cstart)
+{
+    __shared__ uint8_t F[kChaseWindow * kSegStarts];
+    seg_link(maps, cstart, chunks + 1, F);
+}
+
+// Step 3: chunk c's segment starts from its known start.
+__global__ __launch_bounds__(kSegStarts) void k_link_chunk_fill(const uint8_t *__restrict__ finals, int64_t S,
+                                                               const uint8_t *__restrict__ cstart,
+                                                               uint8_t *__restrict__ start)
+{
+    __shared__ uint8_t F[kLinkChunk * kSegStarts];
+    const int64_t t0 = (int64_t)blockIdx.x * kLinkChunk;
+    const int nt = (int)((t0 + kLinkChunk < S - 1) ? kLinkChunk : S - 1 - t0);
+    for (int q = threadIdx.x; q < nt * kSegStarts; q += blockDim.x)
+        F[q] = finals[t0 * kSegStarts + q];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int cur = cstart[blockIdx.x];
+        if (blockIdx.x == 0)
+            start[0] = (uint8_t)cur;
+        for (int t = 0; t < nt; ++t) {
+            cur = F[t * kSegStarts + cur];
+            start[t0 + t + 1] = (uint8_t)cur;
+        }
+    }
+}
+
 template <class Args>
 __global__ __launch_bounds__(1024) void k_lttb_chain_link_emit(Args a, const int64_t *__restrict__ Pmap,
                                                                int64_t *__restrict__ out)
@@ -321,6 +368,24 @@ __global__ __launch_bounds__(1024) void k_lttb_chain_link_emit(Args a, const int
         out[k + 1] = Pmap ? Pmap[sel] : sel;
     }
     if (threadIdx.x == 0) {
+        out[0] = Pmap ? Pmap[0] : 0;
+        out[a.B + 1] = Pmap ? Pmap[m - 1] : m - 1;
+    }
+}
+
+// After the two-level link: every pick written by a grid over the buckets.
+template <class Args>
+__global__ __launch_bounds__(256) void k_lttb_chain_emit(Args a, const int64_t *__restrict__ Pmap,
+                                                         int64_t *__restrict__ out)
+{
+    const int64_t m = a.m_ptr ? *a.m_ptr : a.m_const;
+    const Split bk = make_split(m - 2, a.B);
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < a.B) {
+        const int64_t sel = seg_pick(a.path, a.start, bk, k);
+        out[k + 1] = Pmap ? Pmap[sel] : sel;
+    }
+    if (k == 0) {
         out[0] = Pmap ? Pmap[0] : 0;
         out[a.B + 1] = Pmap ? Pmap[m - 1] : m - 1;
     }
@@ -456,7 +521,25 @@ static hipError_t launch_chain_seg_impl(const Args &a, const int64_t *Pmap, int6
     hipError_t e = hipGetLastError();
     if (e != hipSuccess)
         return e;
-    hipLaunchKernelGGL(k_lttb_chain_link_emit<Args>, dim3(1), dim3(1024), 0, s, a, Pmap, out);
+    const bool two_level = a.S > kTwoLevelLink;
+    if (two_level) {
+        const int64_t chunks = (a.S - 1 + kLinkChunk - 1) / kLinkChunk;
+        uint8_t *maps = a.start + seg_maps_offset(a.S), *cstart = maps + chunks * kSegStarts;
+        hipLaunchKernelGGL(k_link_chunk_maps, dim3((unsigned)chunks), dim3(kSegStarts), 0, s, a.finals, a.S, maps);
+        if ((e = hipGetLastError()) != hipSuccess)
+            return e;
+        hipLaunchKernelGGL(k_link_chunk_starts, dim3(1), dim3(1024), 0, s, maps, chunks, cstart);
+        if ((e = hipGetLastError()) != hipSuccess)
+            return e;
+        hipLaunchKernelGGL(k_link_chunk_fill, dim3((unsigned)chunks), dim3(kSegStarts), 0, s, a.finals, a.S, cstart,
+                           a.start);
+        if ((e = hipGetLastError()) != hipSuccess)
+            return e;
+    }
+    if (two_level)
+        hipLaunchKernelGGL(k_lttb_chain_emit<Args>, dim3(grid_for(a.B, 256, 1 << 30)), dim3(256), 0, s, a, Pmap, out);
+    else
+        hipLaunchKernelGGL(k_lttb_chain_link_emit<Args>, dim3(1), dim3(1024), 0, s, a, Pmap, out);
     return hipGetLastError();
 }
 

@@ -280,3 +280,20 @@ def test_tiled_compaction_around_its_threshold(n_out, r_ps, xk):
     np.testing.assert_array_equal(got, oracle.minmaxlttb(y_np, n_out, r_ps, x_np))
     P, m = ops.minmax(y, n_out, r_ps, x=x)
     np.testing.assert_array_equal(P[: int(m)].cpu().numpy(), oracle.minmax(y_np, n_out, r_ps))
+
+
+@pytest.mark.parametrize("n_out", [32770, 32802, 32866, 70002], ids=lambda v: f"o{v}")
+def test_two_level_link_of_long_chains(n_out):
+    """More than 1024 chain segments (32 buckets each) link in two levels:
+    chunk maps of 64 transitions, a chain over the chunks, then each chunk's
+    segment starts. n_out = 32770 keeps 1024 segments (one level); 32802 and
+    32866 give 1025 and 1027 (16 full chunks, then a ragged 17th)."""
+    n = 400_003
+    seed = 31 + n_out
+    y_np = _series("walk", n, seed)
+    x_np = _x_for(1, n)
+    y, x = _dev(y_np), _devx(x_np)
+    got = ops.minmaxlttb(y, n_out, 2, x=x).cpu().numpy()
+    np.testing.assert_array_equal(got, oracle.minmaxlttb(y_np, n_out, 2, x_np))
+    got_l = ops.lttb(y, n_out).cpu().numpy()  # buckets of ~12 points: the segmented pass over all points
+    np.testing.assert_array_equal(got_l, oracle.lttb(y_np, n_out))
