@@ -299,6 +299,13 @@ int check_rps(int64_t n, int64_t n_out, int32_t r_ps, int32_t min_rps = 2)
             return fail(MMLTTB_EDEVICE, "%s launch failed: %s", name, hipGetErrorString(e_));                          \
     } while (0)
 
+#define MMLTTB_TRY(expr)                                                                                               \
+    do {                                                                                                               \
+        const int rc_ = (expr);                                                                                        \
+        if (rc_ != MMLTTB_OK)                                                                                          \
+            return rc_;                                                                                                \
+    } while (0)
+
 // Work items (one wave each) a stream launch should have to keep every CU
 // busy: 8 waves per CU of the 256 on MI355X. Fewer, longer items leave CUs
 // idle; many more add per-item reductions and merges.
@@ -332,6 +339,22 @@ MinMaxGeom minmax_geom(int64_t len, int64_t nb)
     g.chunks_per_bin = (maxbin + g.chunk - 1) / g.chunk;
     g.n_items = nb * g.chunks_per_bin;
     return g;
+}
+
+// The MinMax stream of one float32 series into its bin keys: one work item
+// per bin (or bin piece), or, for short bins, fixed chunks across bin ends.
+int enqueue_minmax_stream(const float *y, const MinMaxGeom &g, unsigned long long *keys, hipStream_t s)
+{
+    const int64_t maxbin = g.bins.q + (g.bins.r ? 1 : 0);
+    if (maxbin < kShortBin && g.bins.len >= kShortBinChunk * kFillItems) { // and at least 2048 chunks
+        MMLTTB_LAUNCH("init_keys", s, launch_init_keys(keys, g.bins.parts, s));
+        MMLTTB_LAUNCH("minmax_bin_reduce", s, launch_minmax_stream_chunks(y, g.bins, tuning().unroll, keys, s));
+        return MMLTTB_OK;
+    }
+    if (keys_need_init(g))
+        MMLTTB_LAUNCH("init_keys", s, launch_init_keys(keys, g.bins.parts, s));
+    MMLTTB_LAUNCH("minmax_bin_reduce", s, launch_minmax_bin_reduce(y, g, tuning().unroll, keys, s));
+    return MMLTTB_OK;
 }
 
 bool use_segmented_chain(int64_t maxb_bound)
@@ -377,9 +400,7 @@ int enqueue_preselect(const int64_t *x, const float *y, int64_t n, int64_t n_out
     }
     unsigned long long *keys = at<unsigned long long>(ws, L.keys);
     const MinMaxGeom g = minmax_geom(n - 2, nb);
-    if (keys_need_init(g))
-        MMLTTB_LAUNCH("init_keys", s, launch_init_keys(keys, nb, s));
-    MMLTTB_LAUNCH("minmax_bin_reduce", s, launch_minmax_bin_reduce(y, g, tuning().unroll, keys, s));
+    MMLTTB_TRY(enqueue_minmax_stream(y, g, keys, s));
     if (nb <= kFusedCompactBins) {
         MMLTTB_LAUNCH("preselect_compact", s, launch_preselect_compact(keys, g.bins, n, x, y, P, XP, YP, m_out, s));
     } else {
@@ -984,9 +1005,7 @@ int mmlttb_minmaxlttb(int xk, const int64_t *x, const float *y, int64_t n, int64
     } else {
         unsigned long long *keys = at<unsigned long long>(ws, L.keys);
         const MinMaxGeom g = minmax_geom(n - 2, nb);
-        if (keys_need_init(g))
-            MMLTTB_LAUNCH("init_keys", s, launch_init_keys(keys, nb, s));
-        MMLTTB_LAUNCH("minmax_bin_reduce", s, launch_minmax_bin_reduce(y, g, tuning().unroll, keys, s));
+        MMLTTB_TRY(enqueue_minmax_stream(y, g, keys, s));
         if (nb <= kFusedCompactBins) { // one workgroup: compaction, then the means
             MMLTTB_LAUNCH("preselect_compact_means", s,
                           launch_preselect_compact_means(keys, g.bins, n, x, y, P, XP, YP, m, B, MX, MY, s));

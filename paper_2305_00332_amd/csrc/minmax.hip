@@ -67,6 +67,24 @@ __global__ __launch_bounds__(256) void k_minmax_bin_reduce(const float *__restri
     }
 }
 
+// Short bins: one wave per fixed chunk of the interior, streaming across bin
+// ends (wave_stream_bins, as the batched large-bin kernel), the parts merged
+// into keys that start at the identities.
+template <int U>
+__global__ __launch_bounds__(256) void k_minmax_stream_chunks(const float *__restrict__ y, Split bins, int64_t chunk,
+                                                              int64_t items, unsigned long long *__restrict__ keys)
+{
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    const int64_t i = (int64_t)blockIdx.x * (blockDim.x / kWave) + wave;
+    if (i >= items)
+        return;
+    const int64_t lo = 1 + i * chunk;
+    const int64_t end = 1 + bins.len;
+    const int64_t hi = (lo + chunk < end) ? lo + chunk : end;
+    wave_stream_bins<U>(y, lo, hi, bins, keys, lane);
+}
+
 // One workgroup of 1024 threads builds P for one series.
 __global__ __launch_bounds__(1024) void k_preselect_compact(const unsigned long long *__restrict__ keys, Split bins,
                                                             int64_t n, const int64_t *__restrict__ x,
@@ -186,6 +204,34 @@ hipError_t launch_minmax_bin_reduce(const float *y, const MinMaxGeom &g, int unr
         break;
     default:
         hipLaunchKernelGGL(k_minmax_bin_reduce<4>, dim3((unsigned)blocks), dim3(256), 0, s, y, g, keys);
+        break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_minmax_stream_chunks(const float *y, const Split &bins, int unroll, unsigned long long *keys,
+                                      hipStream_t s)
+{
+    const int64_t items = (bins.len + kShortBinChunk - 1) / kShortBinChunk;
+    const int64_t blocks = (items + 3) / 4;
+    if (blocks > 0x7fffffff)
+        return hipErrorInvalidConfiguration;
+    switch (unroll) {
+    case 1:
+        hipLaunchKernelGGL(k_minmax_stream_chunks<1>, dim3((unsigned)blocks), dim3(256), 0, s, y, bins,
+                           kShortBinChunk, items, keys);
+        break;
+    case 2:
+        hipLaunchKernelGGL(k_minmax_stream_chunks<2>, dim3((unsigned)blocks), dim3(256), 0, s, y, bins,
+                           kShortBinChunk, items, keys);
+        break;
+    case 8:
+        hipLaunchKernelGGL(k_minmax_stream_chunks<8>, dim3((unsigned)blocks), dim3(256), 0, s, y, bins,
+                           kShortBinChunk, items, keys);
+        break;
+    default:
+        hipLaunchKernelGGL(k_minmax_stream_chunks<4>, dim3((unsigned)blocks), dim3(256), 0, s, y, bins,
+                           kShortBinChunk, items, keys);
         break;
     }
     return hipGetLastError();

@@ -90,3 +90,20 @@ def test_large_output_sizes(chain_mode):
     _say("lttb n=5e7 n_out=1e6")
     got_l = ops.lttb(y, 1_000_000, x=x).cpu().numpy()
     np.testing.assert_array_equal(got_l, oracle.lttb(y_np, 1_000_000, x_np))
+
+
+def test_short_bins_of_a_long_series():
+    """A series of 2e8 points with bins of fewer than 4096 points is streamed
+    in fixed chunks of 65536 points across bin ends (wave_stream_bins) rather
+    than one work item per bin: bins of 763 and 3051 points."""
+    _say("generating 2e8 random walk on the GPU")
+    y = synth.random_walk(200_000_000, 17, device="cuda")
+    torch.cuda.synchronize()
+    y_np = y.cpu().numpy()
+    for n_out, r_ps in [(131072, 4), (65536, 2)]:
+        _say(f"minmaxlttb n=2e8 n_out={n_out} r_ps={r_ps}")
+        got = ops.minmaxlttb(y, n_out, r_ps).cpu().numpy()
+        np.testing.assert_array_equal(got, oracle.minmaxlttb(y_np, n_out, r_ps))
+        P, m = ops.minmax(y, n_out, r_ps)
+        np.testing.assert_array_equal(P[: int(m)].cpu().numpy(), oracle.minmax(y_np, n_out, r_ps))
+    del y
