@@ -287,19 +287,25 @@ int mmlttb_set_graph_cache(int max_graphs);
 int mmlttb_graph_cache_stats(int64_t *entries, int64_t *hits, int64_t *captures);
 
 /* Execution tuning (never changes results): unroll = 16-byte loads in flight
- * per lane of the MinMax stream (1, 2, 4 or 8); chunk = points per MinMax work
- * item (rounded up to a multiple of 256*unroll); chain = LTTB pass form:
- * 1 sequential (one wave walks every bucket in order), 2 segmented (segments
- * walked from every start point in parallel, then linked; used when buckets
- * hold at most 64 points), 3 automatic (the default: segmented when possible);
- * tile = points a workgroup stages in LDS for batched series with small bins
- * (2048, 4096 or 8192; bins of at most tile/4 points take that path).
- * A value of 0 keeps the current setting; mmlttb_get_tuning reports every
- * field as a settable value, so passing its results back restores a saved
- * setting. Returns MMLTTB_EINVAL for other values. Process-wide; not
- * thread-safe with concurrent calls. */
-int mmlttb_set_tuning(int unroll, int64_t chunk, int chain, int tile);
-int mmlttb_get_tuning(int *unroll, int64_t *chunk, int *chain, int *tile);
+ * per lane of the single-series MinMax streams (1, 2, 4 or 8); chunk = points
+ * per single-series MinMax work item (rounded up to a multiple of
+ * 256*unroll); chain = LTTB pass form: 1 sequential (one wave walks every
+ * bucket in order), 2 segmented (segments walked from every start point in
+ * parallel, then linked; used when buckets hold at most 64 points), 3
+ * automatic (segmented when possible); tile = points a workgroup stages in
+ * LDS for batched series with small bins (2048, 4096 or 8192; bins of at most
+ * tile/4 points take that path); batch_unroll and batch_chunk = unroll and
+ * chunk of the batched large-bin stream. The compiled defaults are the best
+ * settings measured on MI355X: unroll 4, chunk 2^20, chain 3, tile 4096,
+ * batch_unroll 4, batch_chunk 65536 (environment variables MMLTTB_UNROLL,
+ * MMLTTB_CHUNK, MMLTTB_CHAIN, MMLTTB_TILE, MMLTTB_BATCH_UNROLL and
+ * MMLTTB_BATCH_CHUNK override them when the library loads). A value of 0
+ * keeps the current setting; mmlttb_get_tuning reports every field as a
+ * settable value, so passing its results back restores a saved setting.
+ * Returns MMLTTB_EINVAL for other values. Process-wide; not thread-safe with
+ * concurrent calls. */
+int mmlttb_set_tuning(int unroll, int64_t chunk, int chain, int tile, int batch_unroll, int64_t batch_chunk);
+int mmlttb_get_tuning(int *unroll, int64_t *chunk, int *chain, int *tile, int *batch_unroll, int64_t *batch_chunk);
 
 /* Kernel timing for measurement. When enabled, timing-only HIP events (no
  * system-scope fence) are recorded on the caller's stream around every launch

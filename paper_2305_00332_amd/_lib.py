@@ -71,13 +71,15 @@ class Segment(ctypes.Structure):
 
 
 _lib = None
+tuning_source = None  # what set the execution tuning when the library loaded (MMLTTB_TUNE)
 _vp = ctypes.c_void_p
 _i64 = ctypes.c_int64
 _i32 = ctypes.c_int32
 
 
 def load(path: str = LIB_PATH):
-    """Load libmmlttb.so (raises if it is not built)."""
+    """Load libmmlttb.so (raises if it is not built) and apply the execution
+    tuning that MMLTTB_TUNE selects (off | use, the default | retune)."""
     global _lib
     if _lib is not None:
         return _lib
@@ -116,9 +118,9 @@ def load(path: str = LIB_PATH):
     lib.mmlttb_everynth.argtypes = [_i64, _i64, _vp, _vp]
     lib.mmlttb_set_graph_cache.argtypes = [ctypes.c_int]
     lib.mmlttb_graph_cache_stats.argtypes = [ctypes.POINTER(_i64)] * 3
-    lib.mmlttb_set_tuning.argtypes = [ctypes.c_int, _i64, ctypes.c_int, ctypes.c_int]
+    lib.mmlttb_set_tuning.argtypes = [ctypes.c_int, _i64, ctypes.c_int, ctypes.c_int, ctypes.c_int, _i64]
     lib.mmlttb_get_tuning.argtypes = [ctypes.POINTER(ctypes.c_int), ctypes.POINTER(_i64), ctypes.POINTER(ctypes.c_int),
-                                      ctypes.POINTER(ctypes.c_int)]
+                                      ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int), ctypes.POINTER(_i64)]
     lib.mmlttb_lttb_means.argtypes = [ctypes.c_int, _vp, _vp, _i64, _i64, _vp, _vp, _vp]
     lib.mmlttb_profile_enable.argtypes = [ctypes.c_int]
     lib.mmlttb_profile_read.argtypes = [ctypes.c_char_p, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_i64)]
@@ -133,6 +135,10 @@ def load(path: str = LIB_PATH):
               "mmlttb_profile_samples"):
         getattr(lib, f).restype = ctypes.c_int
     _lib = lib
+    from . import autotune
+
+    global tuning_source
+    tuning_source = autotune.on_load()
     return lib
 
 

@@ -11,8 +11,11 @@ tune_single() sweeps unroll x chunk on one resident series, timing the stream
 kernel with the library's HIP events; tune_typed() does the same for the
 stream of the other value types (classes "typed_f64", "typed_i32");
 tune_batched() sweeps tile x chunk x unroll on a batch, timing whole batched
-calls. Results are cached as JSON, keyed by GPU architecture, HIP runtime and
-library version and the workload class; apply(kind) sets the cached choice.
+calls (the batched class sets the batched stream's own unroll and chunk).
+Results are cached as JSON, keyed by GPU architecture, HIP runtime and
+library version and the workload class; apply(kind) sets the cached choice,
+and the binding applies the single-series and batched entries when it loads
+the library (on_load, under MMLTTB_TUNE=off|use|retune).
 
     python -m paper_2305_00332_amd.autotune --out tune_cache.json
 """
@@ -57,17 +60,83 @@ def save_entry(kind: str, entry: dict, path: str = CACHE):
     os.replace(tmp, path)
 
 
+# Cache fields of each workload class -> mmlttb_set_tuning arguments. The
+# typed streams ("typed_f64", "typed_i32") share the single-series settings.
+_FIELDS = {
+    "single": {"unroll": "unroll", "chunk": "chunk"},
+    "typed_f64": {"unroll": "unroll", "chunk": "chunk"},
+    "typed_i32": {"unroll": "unroll", "chunk": "chunk"},
+    "batched": {"unroll": "batch_unroll", "chunk": "batch_chunk", "tile": "tile"},
+}
+LOAD_CLASSES = ("single", "batched")
+
+
+def select(cache: dict, key: str, kind: str):
+    """set_tuning keyword arguments of the cached best entry for (device key,
+    workload class), or None when the cache holds no such entry."""
+    entry = cache.get(key, {}).get(kind)
+    if not entry:
+        return None
+    best = entry["best"]
+    return {arg: int(best[f]) for f, arg in _FIELDS[kind].items() if f in best}
+
+
 def apply(kind: str, path: str = CACHE):
     """Set the cached tuning for this device and workload class; returns the
     applied parameters, or None when the cache has no entry."""
     from . import ops
 
-    entry = load_cache(path).get(device_key(), {}).get(kind)
-    if not entry:
+    args = select(load_cache(path), device_key(), kind)
+    if args is None:
         return None
-    best = entry["best"]
-    ops.set_tuning(unroll=best.get("unroll", 0), chunk=best.get("chunk", 0), tile=best.get("tile", 0))
-    return best
+    ops.set_tuning(**args)
+    return args
+
+
+def on_load(path: str = CACHE) -> str:
+    """Tuning policy applied when the library loads, from MMLTTB_TUNE:
+    "off" keeps the compiled defaults (the settings measured best on MI355X);
+    "use" (the default) applies the cached entries of this device for the
+    single-series and batched classes, warning when there is none;
+    "retune" measures both classes again on synthetic inputs on this device,
+    stores them in the cache and applies them. Returns what was done."""
+    import torch
+
+    mode = os.environ.get("MMLTTB_TUNE", "use").strip().lower()
+    if mode not in ("off", "use", "retune"):
+        raise ValueError(f"MMLTTB_TUNE must be off, use or retune, not {mode!r}")
+    if mode == "off" or not torch.cuda.is_available():
+        return "compiled defaults"
+    if mode == "retune":
+        retune(path)
+    applied = [k for k in LOAD_CLASSES if apply(k, path) is not None]
+    if not applied:
+        import warnings
+
+        warnings.warn(f"libmmlttb: the tuning cache {path} has no entry for {device_key()}; the compiled defaults "
+                      "are in use (MMLTTB_TUNE=retune measures this device)", RuntimeWarning, stacklevel=3)
+        return "compiled defaults (no cache entry)"
+    return "cache: " + ", ".join(applied)
+
+
+def retune(path: str = CACHE, n: int = 250_000_000, batch_series: int = 1024, log=None):
+    """Measure the single-series and batched classes on this device (a
+    random-walk series of n points; a batch of the batched workload's recipe
+    with batch_series series) and store the results in the cache."""
+    import torch
+
+    from . import synth
+
+    y = synth.random_walk(n, 3, device="cuda")
+    torch.cuda.synchronize()
+    save_entry("single", tune_single(y, 1000, 4, log=log), path)
+    del y
+    lengths = synth.batch_lengths(batch_series, 1e3, 1e7, 4)
+    n_outs = synth.choice([200, 500, 1000, 2000], batch_series, 40)
+    x, yb, offsets = synth.batch_series(lengths, 4, device="cuda")
+    torch.cuda.synchronize()
+    segs = [(int(o), int(m), int(no), 4) for o, m, no in zip(offsets, lengths, n_outs)]
+    save_entry("batched", tune_batched(yb, segs, x, log=log), path)
 
 
 def _median_ms(fn, reps: int) -> float:
@@ -169,9 +238,9 @@ def tune_batched(y, segs, x=None, tiles=(2048, 4096, 8192), chunks=(16384, 65536
     results = []
     try:
         for t, c, u in itertools.product(tiles, chunks, unrolls):
-            ops.set_tuning(unroll=u, chunk=c, tile=t)
+            ops.set_tuning(batch_unroll=u, batch_chunk=c, tile=t)
             ms = _median_ms(lambda: ops.minmaxlttb_batched(y, segs, x_base=x, out=out, ws=ws, table=table), reps)
-            results.append({"tile": t, "chunk": ops.get_tuning()[1], "unroll": u, "call_ms": round(ms, 4)})
+            results.append({"tile": t, "chunk": ops.get_tuning().batch_chunk, "unroll": u, "call_ms": round(ms, 4)})
             if log:
                 log(f"  tile={t} chunk={c} unroll={u}: {ms:.3f} ms")
     finally:

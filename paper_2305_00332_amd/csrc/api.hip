@@ -34,26 +34,40 @@ int ok()
     return MMLTTB_OK;
 }
 
+
 // ---------------------------------------------------------------- tuning
 
 // Chain forms; 0 is reserved for "keep the current setting" in mmlttb_set_tuning.
 enum ChainMode { kChainSequential = 1, kChainSegmented = 2, kChainAuto = 3 };
 
 struct Tuning {
-    int unroll = 4;        // float4 loads per lane per batch in minmax_bin_reduce
-    int64_t chunk = 16384; // points per minmax work item (multiple of 256 * unroll)
+    // Defaults: the best settings the autotuner measured on MI355X (one
+    // 1e9-point series; the 4096-series batch).
+    int unroll = 4;              // float4 loads per lane per batch in the single-series MinMax streams
+    int64_t chunk = 1 << 20;     // points per single-series MinMax work item (multiple of 256 * unroll)
     int chain = kChainAuto;
-    int tile = 4096;       // batched small-bin tile points (bins of <= tile/4 points)
+    int tile = 4096;             // batched small-bin tile points (bins of <= tile/4 points)
+    int batch_unroll = 4;        // as unroll, for the batched large-bin stream
+    int64_t batch_chunk = 65536; // points per batched large-bin work item (multiple of 256 * batch_unroll)
 };
+
+int64_t round_chunk(int64_t chunk, int unroll)
+{
+    const int64_t q = 256 * (int64_t)unroll;
+    return ((chunk + q - 1) / q) * q;
+}
+
+bool valid_unroll(int u) { return u == 1 || u == 2 || u == 4 || u == 8; }
+
+bool valid_tile(int t) { return t == 2048 || t == 4096 || t == 8192; }
 
 Tuning &tuning()
 {
     static Tuning t = [] {
         Tuning r;
         if (const char *e = getenv("MMLTTB_UNROLL")) {
-            int u = atoi(e);
-            if (u == 1 || u == 2 || u == 4 || u == 8)
-                r.unroll = u;
+            if (valid_unroll(atoi(e)))
+                r.unroll = atoi(e);
         }
         if (const char *e = getenv("MMLTTB_CHUNK")) {
             long long c = atoll(e);
@@ -61,17 +75,25 @@ Tuning &tuning()
                 r.chunk = c;
         }
         if (const char *e = getenv("MMLTTB_TILE")) {
-            int t = atoi(e);
-            if (t == 2048 || t == 4096 || t == 8192)
-                r.tile = t;
+            if (valid_tile(atoi(e)))
+                r.tile = atoi(e);
         }
         if (const char *e = getenv("MMLTTB_CHAIN")) {
             int c = atoi(e);
             if (c >= 1 && c <= 3)
                 r.chain = c;
         }
-        int64_t q = 256 * (int64_t)r.unroll;
-        r.chunk = ((r.chunk + q - 1) / q) * q;
+        if (const char *e = getenv("MMLTTB_BATCH_UNROLL")) {
+            if (valid_unroll(atoi(e)))
+                r.batch_unroll = atoi(e);
+        }
+        if (const char *e = getenv("MMLTTB_BATCH_CHUNK")) {
+            long long c = atoll(e);
+            if (c >= 256)
+                r.batch_chunk = c;
+        }
+        r.chunk = round_chunk(r.chunk, r.unroll);
+        r.batch_chunk = round_chunk(r.batch_chunk, r.batch_unroll);
         return r;
     }();
     return t;
@@ -641,7 +663,7 @@ int plan_batch(int xk, const mmlttb_segment_t *in, int64_t n_segs, BatchPlan &pl
                 g.tn = (nb + G - 1) / G;
                 tiles += g.tn;
             } else {
-                g.chunk = tn.chunk < kMaxStreamChunk ? tn.chunk : kMaxStreamChunk;
+                g.chunk = tn.batch_chunk < kMaxStreamChunk ? tn.batch_chunk : kMaxStreamChunk;
                 g.ln = (q.n - 2 + g.chunk - 1) / g.chunk;
                 large += g.ln;
             }
@@ -739,7 +761,7 @@ int enqueue_batch(const BatchPlan &plan, int xk, const int64_t *x_base, const fl
     b.stage_cap_max = (int)(h.max_stage_cap > 0 ? h.max_stage_cap : kSegLen);
     if (h.n_large_items > 0) {
         MMLTTB_LAUNCH("batch_init", s, launch_batch_init(b, s));
-        MMLTTB_LAUNCH("batch_minmax_large", s, launch_batch_large(b, tuning().unroll, s));
+        MMLTTB_LAUNCH("batch_minmax_large", s, launch_batch_large(b, tuning().batch_unroll, s));
     }
     if (h.n_small_tiles > 0) {
         MMLTTB_LAUNCH("batch_minmax_small", s, launch_batch_small(b, tuning().tile, s));
@@ -794,7 +816,7 @@ std::vector<char> graph_key(int xk, const int64_t *x_base, const float *y_base, 
         int64_t chunk, n_segs;
         const void *x, *y, *out, *ws, *stream;
         size_t ws_bytes;
-    } head{xk, t.unroll, t.chain, t.tile, t.chunk, n_segs, x_base, y_base, out, ws, (const void *)s, ws_bytes};
+    } head{xk, t.batch_unroll, t.chain, t.tile, t.batch_chunk, n_segs, x_base, y_base, out, ws, (const void *)s, ws_bytes};
     std::vector<char> k(sizeof(head) + (size_t)n_segs * sizeof(mmlttb_segment_t));
     memcpy(k.data(), &head, sizeof(head));
     memcpy(k.data() + sizeof(head), segs, (size_t)n_segs * sizeof(mmlttb_segment_t));
@@ -1423,15 +1445,15 @@ int mmlttb_graph_cache_stats(int64_t *entries, int64_t *hits, int64_t *captures)
     return ok();
 }
 
-int mmlttb_set_tuning(int unroll, int64_t chunk, int chain, int tile)
+int mmlttb_set_tuning(int unroll, int64_t chunk, int chain, int tile, int batch_unroll, int64_t batch_chunk)
 {
     Tuning &t = tuning();
-    if (tile != 0 && tile != 2048 && tile != 4096 && tile != 8192)
+    if (tile != 0 && !valid_tile(tile))
         return fail(MMLTTB_EINVAL, "tile must be 2048, 4096 or 8192");
-    if (unroll != 0 && unroll != 1 && unroll != 2 && unroll != 4 && unroll != 8)
-        return fail(MMLTTB_EINVAL, "unroll must be 1, 2, 4 or 8");
-    if (chunk != 0 && chunk < 256)
-        return fail(MMLTTB_EINVAL, "chunk must be >= 256");
+    if ((unroll != 0 && !valid_unroll(unroll)) || (batch_unroll != 0 && !valid_unroll(batch_unroll)))
+        return fail(MMLTTB_EINVAL, "unroll and batch_unroll must be 1, 2, 4 or 8");
+    if ((chunk != 0 && chunk < 256) || (batch_chunk != 0 && batch_chunk < 256))
+        return fail(MMLTTB_EINVAL, "chunk and batch_chunk must be >= 256");
     if (chain < 0 || chain > 3)
         return fail(MMLTTB_EINVAL, "chain must be 0 (keep), 1 (sequential), 2 (segmented) or 3 (automatic)");
     if (unroll)
@@ -1442,19 +1464,26 @@ int mmlttb_set_tuning(int unroll, int64_t chunk, int chain, int tile)
         t.chain = chain;
     if (tile)
         t.tile = tile;
-    const int64_t q = 256 * (int64_t)t.unroll;
-    t.chunk = ((t.chunk + q - 1) / q) * q;
+    if (batch_unroll)
+        t.batch_unroll = batch_unroll;
+    if (batch_chunk)
+        t.batch_chunk = batch_chunk;
+    t.chunk = round_chunk(t.chunk, t.unroll);
+    t.batch_chunk = round_chunk(t.batch_chunk, t.batch_unroll);
     return ok();
 }
 
-int mmlttb_get_tuning(int *unroll, int64_t *chunk, int *chain, int *tile)
+int mmlttb_get_tuning(int *unroll, int64_t *chunk, int *chain, int *tile, int *batch_unroll, int64_t *batch_chunk)
 {
-    if (!unroll || !chunk || !chain || !tile)
+    if (!unroll || !chunk || !chain || !tile || !batch_unroll || !batch_chunk)
         return fail(MMLTTB_EINVAL, "NULL argument");
-    *unroll = tuning().unroll;
-    *chunk = tuning().chunk;
-    *chain = tuning().chain;
-    *tile = tuning().tile;
+    const Tuning &t = tuning();
+    *unroll = t.unroll;
+    *chunk = t.chunk;
+    *chain = t.chain;
+    *tile = t.tile;
+    *batch_unroll = t.batch_unroll;
+    *batch_chunk = t.batch_chunk;
     return ok();
 }
 

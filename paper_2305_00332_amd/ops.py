@@ -14,6 +14,8 @@ stream. Results are int64 device tensors of indices into the series.
 """
 from __future__ import annotations
 
+from typing import NamedTuple
+
 import torch
 
 from . import _lib
@@ -309,24 +311,35 @@ def graph_cache_stats():
 CHAIN_SEQUENTIAL, CHAIN_SEGMENTED, CHAIN_AUTO = 1, 2, 3
 
 
-def set_tuning(unroll: int = 0, chunk: int = 0, chain: int = 0, tile: int = 0):
-    """Execution tuning (results never depend on it): MinMax loads in flight per
-    lane, points per MinMax work item, LTTB pass form (1 sequential, 2 segmented,
-    3 automatic), batched small-bin tile points. Zero keeps the current value, so
+class Tuning(NamedTuple):
+    unroll: int
+    chunk: int
+    chain: int
+    tile: int
+    batch_unroll: int
+    batch_chunk: int
+
+
+def set_tuning(unroll: int = 0, chunk: int = 0, chain: int = 0, tile: int = 0, batch_unroll: int = 0,
+               batch_chunk: int = 0):
+    """Execution tuning (results never depend on it): single-series MinMax loads
+    in flight per lane and points per work item, LTTB pass form (1 sequential,
+    2 segmented, 3 automatic), batched small-bin tile points, batched large-bin
+    loads in flight and points per work item. Zero keeps the current value, so
     set_tuning(*get_tuning()) restores a saved setting exactly."""
-    _lib.check(_lib.load().mmlttb_set_tuning(unroll, chunk, chain, tile))
+    _lib.check(_lib.load().mmlttb_set_tuning(unroll, chunk, chain, tile, batch_unroll, batch_chunk))
 
 
-def get_tuning():
-    """(unroll, chunk, chain, tile)"""
+def get_tuning() -> Tuning:
     import ctypes
 
-    u = ctypes.c_int(0)
-    c = ctypes.c_int64(0)
-    ch = ctypes.c_int(0)
-    t = ctypes.c_int(0)
-    _lib.check(_lib.load().mmlttb_get_tuning(ctypes.byref(u), ctypes.byref(c), ctypes.byref(ch), ctypes.byref(t)))
-    return u.value, c.value, ch.value, t.value
+    ints = [ctypes.c_int(0) for _ in range(4)]
+    longs = [ctypes.c_int64(0) for _ in range(2)]
+    u, ch, t, bu = ints
+    c, bc = longs
+    _lib.check(_lib.load().mmlttb_get_tuning(ctypes.byref(u), ctypes.byref(c), ctypes.byref(ch), ctypes.byref(t),
+                                             ctypes.byref(bu), ctypes.byref(bc)))
+    return Tuning(u.value, c.value, ch.value, t.value, bu.value, bc.value)
 
 
 def profile_enable(on: bool = True):

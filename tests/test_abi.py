@@ -7,6 +7,7 @@ import ctypes
 import os
 import re
 import subprocess
+import sys
 
 import pytest
 
@@ -128,27 +129,59 @@ def test_oracle_shares_no_code_with_gpu_path():
 
 
 def test_tuning_round_trips_including_automatic_chain(lib):
-    lib.mmlttb_set_tuning.argtypes = [ctypes.c_int, ctypes.c_int64, ctypes.c_int, ctypes.c_int]
-    lib.mmlttb_get_tuning.argtypes = [ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int64),
-                                      ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]
+    i32p, i64p = ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int64)
+    lib.mmlttb_set_tuning.argtypes = [ctypes.c_int, ctypes.c_int64, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                      ctypes.c_int64]
+    lib.mmlttb_get_tuning.argtypes = [i32p, i64p, i32p, i32p, i32p, i64p]
 
     def get():
-        u, c, ch, t = ctypes.c_int(), ctypes.c_int64(), ctypes.c_int(), ctypes.c_int()
-        assert lib.mmlttb_get_tuning(ctypes.byref(u), ctypes.byref(c), ctypes.byref(ch), ctypes.byref(t)) == 0
-        return u.value, c.value, ch.value, t.value
+        u, c, ch, t, bu, bc = (ctypes.c_int(), ctypes.c_int64(), ctypes.c_int(), ctypes.c_int(), ctypes.c_int(),
+                               ctypes.c_int64())
+        assert lib.mmlttb_get_tuning(*(ctypes.byref(v) for v in (u, c, ch, t, bu, bc))) == 0
+        return u.value, c.value, ch.value, t.value, bu.value, bc.value
 
     saved = get()
     assert saved[2] in (1, 2, 3) and saved[0] in (1, 2, 4, 8) and saved[3] in (2048, 4096, 8192)
+    assert saved[4] in (1, 2, 4, 8) and saved[5] >= 256
     try:
-        assert lib.mmlttb_set_tuning(8, 2048, 1, 8192) == 0
-        assert get() == (8, 2048, 1, 8192)
-        assert lib.mmlttb_set_tuning(0, 0, 3, 0) == 0  # automatic again, the rest kept
-        assert get() == (8, 2048, 3, 8192)
-        assert lib.mmlttb_set_tuning(0, 0, 4, 0) == -1
-        assert lib.mmlttb_set_tuning(3, 0, 0, 0) == -1
+        assert lib.mmlttb_set_tuning(8, 2048, 1, 8192, 2, 1000) == 0
+        assert get() == (8, 2048, 1, 8192, 2, 1024)  # chunks rounded up to 256 * unroll
+        assert lib.mmlttb_set_tuning(0, 0, 3, 0, 0, 0) == 0  # automatic again, the rest kept
+        assert get() == (8, 2048, 3, 8192, 2, 1024)
+        assert lib.mmlttb_set_tuning(0, 0, 4, 0, 0, 0) == -1
+        assert lib.mmlttb_set_tuning(3, 0, 0, 0, 0, 0) == -1
+        assert lib.mmlttb_set_tuning(0, 0, 0, 0, 5, 0) == -1
+        assert lib.mmlttb_set_tuning(0, 0, 0, 0, 0, 100) == -1
     finally:
         assert lib.mmlttb_set_tuning(*saved) == 0
     assert get() == saved
+
+
+def test_compiled_tuning_defaults_are_the_measured_best(lib):
+    """Without MMLTTB_* overrides the library starts from the settings the
+    committed tuning cache holds as best for MI355X (single-series stream and
+    batched stream), so callers that never apply the cache run them too."""
+    import json
+
+    if any(k.startswith("MMLTTB_") and k != "MMLTTB_TUNE" for k in os.environ):
+        pytest.skip("MMLTTB_* overrides are set")
+    out = subprocess.run(
+        [sys.executable, "-c",
+         "import ctypes,sys; l=ctypes.CDLL(sys.argv[1]); P=ctypes.POINTER;"
+         "l.mmlttb_get_tuning.argtypes=[P(ctypes.c_int),P(ctypes.c_int64),P(ctypes.c_int),P(ctypes.c_int),"
+         "P(ctypes.c_int),P(ctypes.c_int64)];"
+         "v=[ctypes.c_int(),ctypes.c_int64(),ctypes.c_int(),ctypes.c_int(),ctypes.c_int(),ctypes.c_int64()];"
+         "assert l.mmlttb_get_tuning(*[ctypes.byref(a) for a in v])==0; print(*[a.value for a in v])", LIB],
+        capture_output=True, text=True, check=True).stdout.split()
+    unroll, chunk, chain, tile, bunroll, bchunk = map(int, out)
+    cache = json.load(open(os.path.join(ROOT, "paper_2305_00332_amd", "tune_cache.json")))
+    mi355x = [v for k, v in cache.items() if k.startswith("gfx950")]
+    assert mi355x
+    for entry in mi355x:
+        assert (entry["single"]["best"]["unroll"], entry["single"]["best"]["chunk"]) == (unroll, chunk)
+        b = entry["batched"]["best"]
+        assert (b["unroll"], b["chunk"], b["tile"]) == (bunroll, bchunk, tile)
+    assert chain == 3
 
 
 def test_new_calls_reject_invalid_arguments_on_host(lib):

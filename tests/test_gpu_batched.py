@@ -133,7 +133,7 @@ def test_tuning_does_not_change_batched_results(tile, chunk, unroll):
     ref, _ = ops.minmaxlttb_batched(y, segs, x_base=x)
     old = ops.get_tuning()
     try:
-        ops.set_tuning(unroll=unroll, chunk=chunk, tile=tile)
+        ops.set_tuning(batch_unroll=unroll, batch_chunk=chunk, tile=tile)
         got, outoff = ops.minmaxlttb_batched(y, segs, x_base=x)
     finally:
         ops.set_tuning(*old)
