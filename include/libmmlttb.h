@@ -151,6 +151,29 @@ int mmlttb_lttb_means(int xk, const int64_t *x, const float *y, int64_t m, int64
 int mmlttb_minmaxlttb(int xk, const int64_t *x, const float *y, int64_t n, int64_t n_out, int32_t r_ps,
                       int64_t *out_idx, void *ws, size_t ws_bytes, void *stream);
 
+/* Bytes of the fixed device array that mmlttb_minmaxlttb_noalloc uses as its
+ * workspace (4 MiB: enough for n_out * r_ps up to about 87000, e.g.
+ * n_out = 16384 at r_ps = 4). */
+#define MMLTTB_NOALLOC_SCRATCH_BYTES (4u << 20)
+
+/* For callers that cannot allocate device memory (code under graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): mmlttb_minmaxlttb
+ * with the same arguments, meaning and result, minus ws and ws_bytes. Its
+ * workspace is a fixed array of MMLTTB_NOALLOC_SCRATCH_BYTES bytes inside the
+ * library, one per device, held from the first call on that device until the
+ * process ends; its address is looked up on that first call, with the device
+ * current, and kept. The call never allocates or frees memory. x, y and
+ * out_idx are caller-owned device buffers on the current device, and stream
+ * must belong to the current device. Errors: those of mmlttb_minmaxlttb, plus
+ * MMLTTB_EINVAL (nothing enqueued) when mmlttb_workspace_size(n, n_out, r_ps)
+ * exceeds MMLTTB_NOALLOC_SCRATCH_BYTES, and MMLTTB_EDEVICE if the array's
+ * address cannot be looked up. Every call on one device shares that device's
+ * array and leaves its contents behind (no part of the path needs it zeroed):
+ * calls that overlap on one device -- on two streams, or from two threads
+ * without ordering -- race on it and give undefined results. */
+int mmlttb_minmaxlttb_noalloc(int xk, const int64_t *x, const float *y, int64_t n, int64_t n_out, int32_t r_ps,
+                              int64_t *out_idx, void *stream);
+
 /* Workspace bytes for mmlttb_minmaxlttb_batched over these segments (host
  * array). Independent of the segment lengths. Returns 0 on invalid input. */
 size_t mmlttb_batched_workspace_size(const mmlttb_segment_t *segs_host, int64_t n_segs);

@@ -16,6 +16,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libmmlttb.so")
 
 OK, EINVAL, ENOMEM, EDEVICE, ENOTSUP = 0, -1, -2, -3, -4
+NOALLOC_SCRATCH_BYTES = 4 << 20  # MMLTTB_NOALLOC_SCRATCH_BYTES
 X_IMPLICIT, X_INT64, X_F64 = 0, 1, 2
 Y_F32, Y_F64, Y_I32 = 0, 1, 2
 
@@ -28,6 +29,7 @@ EXPORTS = (
     "mmlttb_minmax",
     "mmlttb_lttb",
     "mmlttb_minmaxlttb",
+    "mmlttb_minmaxlttb_noalloc",
     "mmlttb_lttb_means",
     "mmlttb_batched_workspace_size",
     "mmlttb_minmaxlttb_batched",
@@ -95,6 +97,7 @@ def load(path: str = LIB_PATH):
     lib.mmlttb_minmax.argtypes = [ctypes.c_int, _vp, _vp, _i64, _i64, _i32, _vp, _vp, _vp, ctypes.c_size_t, _vp]
     lib.mmlttb_lttb.argtypes = [ctypes.c_int, _vp, _vp, _i64, _i64, _vp, _vp, ctypes.c_size_t, _vp]
     lib.mmlttb_minmaxlttb.argtypes = [ctypes.c_int, _vp, _vp, _i64, _i64, _i32, _vp, _vp, ctypes.c_size_t, _vp]
+    lib.mmlttb_minmaxlttb_noalloc.argtypes = [ctypes.c_int, _vp, _vp, _i64, _i64, _i32, _vp, _vp]
     lib.mmlttb_batched_workspace_size.argtypes = [ctypes.POINTER(Segment), _i64]
     lib.mmlttb_batched_workspace_size.restype = ctypes.c_size_t
     lib.mmlttb_minmaxlttb_batched.argtypes = [ctypes.c_int, _vp, _vp, ctypes.POINTER(Segment), _i64, _vp, _vp,
@@ -126,7 +129,7 @@ def load(path: str = LIB_PATH):
     lib.mmlttb_profile_read.argtypes = [ctypes.c_char_p, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_i64)]
     lib.mmlttb_profile_samples.argtypes = [ctypes.c_char_p, ctypes.POINTER(ctypes.c_float), _i64,
                                            ctypes.POINTER(_i64)]
-    for f in ("mmlttb_minmax", "mmlttb_lttb", "mmlttb_minmaxlttb", "mmlttb_lttb_means", "mmlttb_minmaxlttb_batched",
+    for f in ("mmlttb_minmax", "mmlttb_lttb", "mmlttb_minmaxlttb", "mmlttb_minmaxlttb_noalloc", "mmlttb_lttb_means", "mmlttb_minmaxlttb_batched",
               "mmlttb_m4",
               "mmlttb_minmax_xbins", "mmlttb_minmaxlttb_xbins", "mmlttb_minmax_typed", "mmlttb_minmaxlttb_typed",
               "mmlttb_minmax_simplify",

@@ -8,6 +8,7 @@
 #include <string>
 #include <vector>
 
+#include "errors.hpp"
 #include "kernels.hpp"
 #include "libmmlttb.h"
 
@@ -34,6 +35,24 @@ int ok()
     return MMLTTB_OK;
 }
 
+} // namespace
+
+namespace mmlttb {
+
+int set_error(int code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+} // namespace mmlttb
+
+namespace {
 
 // ---------------------------------------------------------------- tuning
 

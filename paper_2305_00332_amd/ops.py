@@ -250,6 +250,19 @@ def minmaxlttb(y, n_out: int, r_ps: int, x=None, out=None, ws=None):
     return out[: min(n, n_out)]
 
 
+def minmaxlttb_noalloc(y, n_out: int, r_ps: int, x=None, out=None):
+    """MinMaxLTTB with the library's fixed device scratch as its workspace:
+    the call allocates nothing in the library (pass `out` to allocate nothing
+    at all). Calls that overlap on one device race on that scratch."""
+    lib = _lib.load()
+    xk = _as_series(y, x)
+    n = y.numel()
+    out = out if out is not None else torch.empty(max(min(n, n_out), 1), dtype=torch.int64, device=y.device)
+    _lib.check(lib.mmlttb_minmaxlttb_noalloc(xk, _lib.ptr(x), y.data_ptr(), n, n_out, r_ps, out.data_ptr(),
+                                             _lib.stream_ptr()))
+    return out[: min(n, n_out)]
+
+
 def segment_table(segs):
     """Build the C segment array from (offset, n, n_out, r_ps) tuples; output
     slots are packed in order. Returns (ctypes array, out_offsets, total_out)."""

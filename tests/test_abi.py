@@ -208,6 +208,23 @@ def test_new_calls_reject_invalid_arguments_on_host(lib):
     assert lib.mmlttb_minmaxlttb_xbins(fake, fake, 10 ** 6, 1000, 4, fake, fake, ws, 16, None) == -2
 
 
+def test_noalloc_rejects_sizes_beyond_its_array_on_host(lib):
+    """The fixed-scratch call refuses a workspace larger than its array (and
+    invalid n_out / r_ps) before any HIP call."""
+    _setup(lib)
+    i64 = ctypes.c_int64
+    lib.mmlttb_minmaxlttb_noalloc.argtypes = [ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, i64, i64,
+                                              ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p]
+    fake = ctypes.c_void_p(0x100000)
+    limit = 4 << 20
+    assert "(4u << 20)" in open(HEADER).read()
+    assert lib.mmlttb_workspace_size(10 ** 8, 65536, 4) > limit >= lib.mmlttb_workspace_size(10 ** 8, 16384, 4)
+    assert lib.mmlttb_minmaxlttb_noalloc(0, None, fake, 10 ** 8, 65536, 4, fake, None) == -1
+    assert b"fixed scratch" in lib.mmlttb_last_error()
+    assert lib.mmlttb_minmaxlttb_noalloc(0, None, fake, 10 ** 8, 2, 4, fake, None) == -1   # n_out < 3
+    assert lib.mmlttb_minmaxlttb_noalloc(0, None, fake, 10 ** 8, 100, 0, fake, None) == -1  # r_ps < 1
+
+
 def test_profile_samples_host_checks(lib):
     """Per-launch samples: argument checks, and nothing recorded for calls the
     host rejects (no HIP call is made on this path)."""
