@@ -70,6 +70,19 @@ def shared_walk(n: int, seed: int, dev):
     return _WALKS[key]
 
 
+def oracle_seconds(fn, reps: int = 5):
+    """Median wall time of `reps` runs of fn() after one warm-up, and its result."""
+    import statistics
+
+    out = fn()
+    times = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        out = fn()
+        times.append(time.perf_counter() - t0)
+    return statistics.median(times), out
+
+
 def kernel_source_sha() -> str:
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
@@ -114,8 +127,12 @@ def main():
     ap.add_argument("--skip-simplifiers", action="store_true")
     ap.add_argument("--batch-series", type=int, default=4096)
     ap.add_argument("--pool-series", type=int, default=512)
-    ap.add_argument("--rates", type=str, default="100,500,1000,2000,5000")
-    ap.add_argument("--serve-seconds", type=float, default=2.0)
+    ap.add_argument("--rates", type=str, default="100,250,500,1000,2000,5000")
+    ap.add_argument("--serve-seconds", type=float, default=10.0,
+                    help="requests per rate: max(--serve-min-requests, rate x this)")
+    ap.add_argument("--serve-min-requests", type=int, default=2000)
+    ap.add_argument("--serve-arena", type=int, default=1 << 30, help="device arena bytes of each serving form")
+    ap.add_argument("--serve-oracle-sample", type=int, default=256)
     ap.add_argument("--burst", type=int, default=2000)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (the reference kernel for HBM counter scaling)")
@@ -375,8 +392,18 @@ def bench_shapes(args):
     el["gpts_per_s"] = round(n / (el["call_ms"] * 1e-3) / 1e9, 3)
     if not args.no_cpu_baseline:
         y_np = y.cpu().numpy()
-        e["parity_vs_oracle"] = bool(np.array_equal(got, oracle.minmaxlttb(y_np, n_out, r_ps)))
-        el["parity_vs_oracle"] = bool(np.array_equal(out_l.cpu().numpy(), oracle.lttb(y_np, n_out)))
+        omp = oracle.load_openmp()
+        for entry, fn, gpu_out in ((e, lambda lib: oracle.minmaxlttb(y_np, n_out, r_ps, _lib_override=lib), got),
+                                   (el, lambda lib: oracle.lttb(y_np, n_out, _lib_override=lib),
+                                    out_l.cpu().numpy())):
+            t_one, want = oracle_seconds(lambda: fn(None))
+            t_omp, want_omp = oracle_seconds(lambda: fn(omp))
+            entry["parity_vs_oracle"] = bool(np.array_equal(gpu_out, want))
+            entry["cpu_oracle_s"] = round(t_one, 5)
+            entry["cpu_openmp_s"] = round(t_omp, 5)
+            entry["cpu_openmp_identical"] = bool(np.array_equal(want_omp, want))
+        res["cpu"] = {"host_cpu": host_cpu_model(), "openmp_threads": oracle.threads(omp),
+                      "protocol": "median of 5 runs after one warm-up"}
     res["n1e6"] = {"workload": f"one series, n={n}, float32 random walk (seed 1), implicit x; n_out={n_out}, "
                                f"r_ps={r_ps}; 200 back-to-back calls over 64 copies of it in turn (256 MB)",
                    "minmaxlttb": e, "lttb": el}
@@ -811,24 +838,84 @@ def bench_batched(args):
     run_plain()
     torch.cuda.synchronize()
     t_plain = time.perf_counter() - t0
+    # the same per-series calls again, each bracketed by the library's events:
+    # their summed device spans (the plain form's device time without host gaps)
+    ops.profile_enable(True)
+    ops.profile_reset()
+    run_plain()
+    torch.cuda.synchronize()
+    ops.profile_enable(False)
+    plain_spans = ops.profile_samples("call_minmaxlttb")
     pts = int(lengths.sum())
     res = {"workload": f"{count} series, lengths log-uniform in [1e3, 1e7] (seed 4), float32 random walk + "
                        f"N(0, 0.5^2), int64 irregular x; n_out in {{200, 500, 1000, 2000}}, r_ps=4",
            "points": pts, "ms": round(t_batched * 1e3, 4), "gpts_per_s": round(pts / t_batched / 1e9, 3),
            "plain_ms": round(t_plain * 1e3, 4), "plain_gpts_per_s": round(pts / t_plain / 1e9, 3),
-           "speedup_vs_plain": round(t_plain / t_batched, 3), "kernel_ms": kern,
+           "speedup_vs_plain": round(t_plain / t_batched, 3),
+           "plain_device_ms": round(float(sum(plain_spans)), 4) if len(plain_spans) == len(segs) else None,
+           "speedup_vs_plain_device": (round(float(sum(plain_spans)) / (t_batched * 1e3), 3)
+                                       if len(plain_spans) == len(segs) else None),
+           "kernel_ms": kern,
            "tuning": ops.get_tuning()._asdict(),
            "graph_replay_ms": round(t_graph * 1e3, 4), "graph_stats": list(graph_stats),
            "small_batch_16": {"eager_ms": round(t_small_eager * 1e3, 4), "graph_ms": round(t_small_graph * 1e3, 4),
                               "points": int(sum(n for _, n, _, _ in small))},
            "identical_to_plain": bool(torch.equal(out[: table[2]], plain[: table[2]]))}
+    if not args.no_cpu_baseline:
+        res.update(batched_oracle(args, x, y, segs, out, table[1]))
     del x, y, out, plain, ws, ws1
     return res
 
 
+def batched_oracle(args, x, y, segs, out, outoff):
+    """Every series of the batch through the oracle on the host: parity with
+    the batched output, and the oracle's time single-threaded, in its OpenMP
+    build (bins of each series across threads), and single-threaded builds on
+    a pool of threads over the series."""
+    import numpy as np
+
+    import oracle
+
+    log("batched: copying the batch to the host for the oracle")
+    y_h, x_h = y.cpu().numpy(), x.cpu().numpy()
+    got = out.cpu().numpy()
+
+    def fetch(lo, hi):
+        return y_h[lo:hi], x_h[lo:hi]
+
+    omp = oracle.load_openmp()
+    workers = min(16, os.cpu_count() or 1)
+    log("batched: oracle, single thread")
+    t0 = time.perf_counter()
+    want = oracle.minmaxlttb_segments(fetch, segs, workers=1, slab_points=1 << 40)
+    t_one = time.perf_counter() - t0
+    log("batched: oracle, OpenMP build")
+    t0 = time.perf_counter()
+    want_omp = oracle.minmaxlttb_segments(fetch, segs, workers=1, slab_points=1 << 40, _lib_override=omp)
+    t_omp = time.perf_counter() - t0
+    log(f"batched: oracle, {workers} threads over the series")
+    t0 = time.perf_counter()
+    want_par = oracle.minmaxlttb_segments(fetch, segs, workers=workers, slab_points=1 << 40)
+    t_par = time.perf_counter() - t0
+    bad = [i for i, (o, n, no, r) in enumerate(segs)
+           if not np.array_equal(got[outoff[i]: outoff[i] + min(n, no)], want[i])]
+    pts = sum(n for _, n, _, _ in segs)
+    return {"parity_vs_oracle": not bad, "oracle_mismatches": len(bad),
+            "cpu_oracle_s": round(t_one, 3), "cpu_openmp_s": round(t_omp, 3),
+            "cpu_series_parallel_s": round(t_par, 3), "cpu_series_parallel_threads": workers,
+            "cpu_oracle_gpts_per_s": round(pts / t_one / 1e9, 4),
+            "cpu_identical": bool(all(np.array_equal(a, b) and np.array_equal(a, c)
+                                      for a, b, c in zip(want, want_omp, want_par))),
+            "cpu_host": host_cpu_model(), "cpu_openmp_threads": oracle.threads(omp),
+            "cpu_sample": f"all {len(segs)} series, each its own oracle call, inputs already in host memory"}
+
+
 def bench_served(args):
     """Poisson request streams against a resident pool: continuous batching
-    vs one single-series call per request, p50/p99 latency and Gpts/s."""
+    vs one single-series call per request, p50/p99 latency, Gpts/s and the
+    fraction of the run with work on the device; every result of the two forms
+    compared, and a seeded sample of requests compared with the oracle (which
+    is also timed on that sample)."""
     import numpy as np
     import torch
 
@@ -842,62 +929,114 @@ def bench_served(args):
     x, y, offsets = synth.batch_series(lengths, 5, device="cuda", sinusoids=True)
     torch.cuda.synchronize()
     rates = [float(r) for r in args.rates.split(",") if r]
+    slots = 4
+    forms = {"batched": (GpuExecutor(y, offsets, lengths, x=x, n_slots=slots, arena_bytes=args.serve_arena), None),
+             "plain": (PlainGpuExecutor(y, offsets, lengths, x=x, n_slots=slots, arena_bytes=args.serve_arena), 1)}
+
+    def serve(name, reqs, max_batch=None):
+        ex, mb = forms[name]
+        sched = Scheduler(ex, n_slots=slots, max_batch=max_batch if max_batch is not None else mb)
+        fresh = [type(r)(r.rid, r.series, r.lo, r.hi, r.n_out, r.r_ps, r.arrival) for r in reqs]
+        done = sched.run_open_loop(fresh, timeout=900)
+        s = latency_summary(done)
+        s["busy_frac"] = round(sched.busy_fraction(s.get("span_s", 0.0)), 4)
+        s["steps"] = sched.steps_launched
+        s["mean_batch"] = round(float(np.mean(sched.batch_sizes)), 2) if sched.batch_sizes else 0.0
+        s["max_in_flight"] = sched.max_in_flight
+        s["max_device_bytes"] = sched.max_ws_in_use
+        return s, done
+
+    def same(a, b):
+        """Every request succeeded in both forms with equal indices."""
+        ra, rb = {r.rid: r for r in a}, {r.rid: r for r in b}
+        return ra.keys() == rb.keys() and all(
+            ra[k].error is None and rb[k].error is None and np.array_equal(ra[k].result, rb[k].result) for k in ra)
+
     per_rate = {}
     identical = True
     for rate in rates:
-        n_req = max(100, int(rate * args.serve_seconds))
+        n_req = max(args.serve_min_requests, int(rate * args.serve_seconds))
         reqs = poisson_requests(rate, n_req, lengths, seed=50 + int(rate))
         warm = poisson_requests(rate, 50, lengths, seed=7)
-        entry = {}
-        results = {}
-        for name, ex_cls, slots, max_batch in (("batched", GpuExecutor, 3, None), ("plain", PlainGpuExecutor, 4, 1)):
-            ex = ex_cls(y, offsets, lengths, x=x, n_slots=slots)
-            Scheduler(ex, n_slots=slots, ws_budget=1 << 30, max_batch=max_batch).run_open_loop(warm, timeout=120)
-            sched = Scheduler(ex, n_slots=slots, ws_budget=1 << 30, max_batch=max_batch)
+        entry, results = {}, {}
+        for name in forms:
+            serve(name, warm)
             log(f"served: rate {rate:g}/s, {n_req} requests, {name}")
-            fresh = [type(r)(r.rid, r.series, r.lo, r.hi, r.n_out, r.r_ps, r.arrival) for r in reqs]
-            done = sched.run_open_loop(fresh, timeout=300)
-            s = latency_summary(done)
-            if name == "batched":
-                s["mean_batch"] = round(float(np.mean(sched.batch_sizes)), 2)
-                s["max_in_flight"] = sched.max_in_flight
-            entry[name] = s
-            results[name] = {r.rid: r.result for r in done}
-        identical = identical and all(np.array_equal(results["batched"][k], results["plain"][k])
-                                      for k in results["batched"])
+            entry[name], results[name] = serve(name, reqs)
+        identical = identical and same(results["batched"], results["plain"])
         b, p = entry["batched"], entry["plain"]
-        entry["p99_speedup_vs_plain"] = round(p["p99_ms"] / b["p99_ms"], 3) if b.get("p99_ms") else None
-        entry["throughput_ratio_vs_plain"] = round(b["gpts_per_s"] / p["gpts_per_s"], 3) if p.get("gpts_per_s") else None
+        entry["p99_ratio_plain_over_batched"] = round(p["p99_ms"] / b["p99_ms"], 3) if b.get("p99_ms") else None
+        entry["throughput_ratio_vs_plain"] = (round(b["gpts_per_s"] / p["gpts_per_s"], 3)
+                                              if p.get("gpts_per_s") else None)
         per_rate[f"{rate:g}"] = entry
     # saturation: a burst of requests all arriving at t=0, served to completion
-    burst_n = args.burst
-    burst = poisson_requests(1e12, burst_n, lengths, seed=77)
-    burst_entry = {}
-    burst_results = {}
-    for name, ex_cls, slots, max_batch in (("batched", GpuExecutor, 3, 256), ("plain", PlainGpuExecutor, 4, 1)):
-        ex = ex_cls(y, offsets, lengths, x=x, n_slots=slots)
-        fresh = [type(r)(r.rid, r.series, r.lo, r.hi, r.n_out, r.r_ps, 0.0) for r in burst]
-        Scheduler(ex, n_slots=slots, ws_budget=1 << 30, max_batch=max_batch).run_open_loop(fresh[:64], timeout=120)
-        fresh = [type(r)(r.rid, r.series, r.lo, r.hi, r.n_out, r.r_ps, 0.0) for r in burst]
-        sched = Scheduler(ex, n_slots=slots, ws_budget=1 << 30, max_batch=max_batch)
-        log(f"served: burst of {burst_n} requests, {name}")
-        done = sched.run_open_loop(fresh, timeout=300)
-        s = latency_summary(done)
-        s["steps"] = sched.steps_launched
-        burst_entry[name] = s
-        burst_results[name] = {r.rid: r.result for r in done}
-    identical = identical and all(np.array_equal(burst_results["batched"][k], burst_results["plain"][k])
-                                  for k in burst_results["batched"])
+    burst = poisson_requests(1e12, args.burst, lengths, seed=77)
+    burst_entry, burst_results = {}, {}
+    for name in forms:
+        serve(name, burst[:64], max_batch=256 if name == "batched" else None)
+        log(f"served: burst of {args.burst} requests, {name}")
+        burst_entry[name], burst_results[name] = serve(name, burst, max_batch=256 if name == "batched" else None)
+    identical = identical and same(burst_results["batched"], burst_results["plain"])
     burst_entry["throughput_ratio_vs_plain"] = round(burst_entry["batched"]["gpts_per_s"] /
                                                      burst_entry["plain"]["gpts_per_s"], 3)
+    errors = sum(e[k]["errors"] for e in per_rate.values() for k in ("batched", "plain")) + \
+        sum(burst_entry[k]["errors"] for k in ("batched", "plain"))
     res = {"workload": f"pool of {count} series resident in HBM, lengths log-uniform in [1e4, 1e8] (seed 5), "
                        f"float32 random walk + sinusoids + noise, int64 irregular x; Poisson arrivals; per request "
                        f"a series, a log-uniform sub-range, n_out uniform in [100, 4000], r_ps in {{2, 4}}",
-           "pool_points": int(lengths.sum()), "seconds_per_rate": args.serve_seconds, "rates": per_rate,
-           "burst": burst_entry,
-           "identical_to_plain": bool(identical)}
-    del x, y
+           "pool_points": int(lengths.sum()), "slots": slots, "arena_bytes_per_form": args.serve_arena,
+           "requests_per_rate": f"max({args.serve_min_requests}, {args.serve_seconds:g} s x rate)",
+           "rates": per_rate, "burst": burst_entry, "errors": errors,
+           "identical_to_plain": bool(identical and errors == 0)}
+    if not args.no_cpu_baseline:
+        res.update(served_oracle(x, y, offsets, burst_results["batched"], args.serve_oracle_sample))
+    del forms, x, y
     return res
+
+
+def served_oracle(x, y, offsets, done, sample):
+    """A seeded sample of served requests (from the burst, so most ran inside
+    batched steps) through the oracle: parity, and its time single-threaded and
+    in the OpenMP build on that sample."""
+    import numpy as np
+
+    import oracle
+
+    rng = np.random.default_rng(2024)
+    pick = sorted(rng.choice(len(done), size=min(sample, len(done)), replace=False).tolist())
+    reqs = [done[i] for i in pick]
+    segs = [(int(offsets[r.series]) + r.lo, r.n, r.n_out, r.r_ps) for r in reqs]
+    log(f"served: copying {len(segs)} sampled sub-ranges to the host for the oracle")
+    host = {}
+    for o, n, _, _ in segs:
+        if o not in host or host[o][0].shape[0] < n:
+            host[o] = (y[o: o + n].cpu().numpy(), x[o: o + n].cpu().numpy())
+
+    def fetch(lo, hi):
+        ys, xs = host[lo]
+        return ys[: hi - lo], xs[: hi - lo]
+
+    omp = oracle.load_openmp()
+    log("served: oracle on the sample, single thread")
+    t0 = time.perf_counter()
+    want = oracle.minmaxlttb_segments(fetch, segs, workers=1, slab_points=0)
+    t_one = time.perf_counter() - t0
+    log("served: oracle on the sample, OpenMP build")
+    t0 = time.perf_counter()
+    want_omp = oracle.minmaxlttb_segments(fetch, segs, workers=1, slab_points=0, _lib_override=omp)
+    t_omp = time.perf_counter() - t0
+    bad = [r.rid for r, w in zip(reqs, want) if r.error is not None or not np.array_equal(r.result, w)]
+    pts = sum(r.n for r in reqs)
+    return {"parity_vs_oracle": not bad, "oracle_mismatches": len(bad),
+            "oracle_sample": {"requests": len(reqs), "points": int(pts),
+                              "above_1e7_points": sum(1 for r in reqs if r.n > 10 ** 7),
+                              "in_batched_steps": sum(1 for r in reqs if r.batch > 1),
+                              "how": "seeded sample of the burst's requests (batched form), each sub-range "
+                                     "through the oracle alone"},
+            "cpu_oracle_s": round(t_one, 3), "cpu_openmp_s": round(t_omp, 3),
+            "cpu_oracle_gpts_per_s": round(pts / t_one / 1e9, 4), "cpu_openmp_gpts_per_s": round(pts / t_omp / 1e9, 4),
+            "cpu_identical": bool(all(np.array_equal(a, b) for a, b in zip(want, want_omp))),
+            "cpu_host": host_cpu_model(), "cpu_openmp_threads": oracle.threads(omp)}
 
 
 if __name__ == "__main__":

@@ -28,6 +28,7 @@ from .oracle import (  # noqa: F401
     minmax_xbins,
     minmaxlttb_xbins,
     minmaxlttb,
+    minmaxlttb_segments,
     load_openmp,
     threads,
     XK_IMPLICIT,

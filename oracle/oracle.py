@@ -382,6 +382,51 @@ def minmaxlttb(y, n_out: int, r_ps: int, x=None, _lib_override=None) -> np.ndarr
     return out[: min(n, n_out)].copy()
 
 
+def minmaxlttb_segments(fetch, segs, workers: int = 1, slab_points: int = 1 << 27, _lib_override=None):
+    """minmaxlttb of many segments of one long series pair, in segment order.
+
+    segs holds (offset, n, n_out, r_ps) per segment (segments may overlap and
+    come in any order); fetch(lo, hi) returns the host arrays (y[lo:hi],
+    x[lo:hi] or None) of an element range. Segments are taken in offset order
+    and grouped into slabs of about slab_points elements, each fetched once;
+    the segments of a slab run on `workers` threads (the C calls release the
+    GIL, and the oracle keeps no shared state). No arithmetic happens here:
+    each result is minmaxlttb of that segment alone."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    order = sorted(range(len(segs)), key=lambda i: (int(segs[i][0]), i))
+    results = [None] * len(segs)
+    pool = ThreadPoolExecutor(max_workers=max(1, workers)) if workers > 1 else None
+    try:
+        k = 0
+        while k < len(order):
+            lo = int(segs[order[k]][0])
+            hi = lo + int(segs[order[k]][1])
+            j = k + 1
+            while j < len(order):
+                o, n = int(segs[order[j]][0]), int(segs[order[j]][1])
+                if max(hi, o + n) - lo > slab_points:
+                    break
+                hi = max(hi, o + n)
+                j += 1
+            ys, xs = fetch(lo, hi)
+
+            def one(i, ys=ys, xs=xs, lo=lo):
+                o, n, n_out, r_ps = (int(v) for v in segs[i])
+                xi = None if xs is None else xs[o - lo: o - lo + n]
+                return i, minmaxlttb(ys[o - lo: o - lo + n], n_out, r_ps, xi, _lib_override=_lib_override)
+
+            batch = order[k:j]
+            done = pool.map(one, batch) if pool else map(one, batch)
+            for i, r in done:
+                results[i] = r
+            k = j
+    finally:
+        if pool:
+            pool.shutdown()
+    return results
+
+
 def lttb_means(y, n_out: int, x=None, _lib_override=None):
     """(MX, MY) next-bucket means of LTTB over the given points (reading R6)."""
     y = _f32(y)

@@ -4,19 +4,24 @@ A request asks for MinMaxLTTB of one pool series' sub-range [lo, hi) with its
 own n_out and r_ps. The scheduler keeps a FIFO of arrived requests and, on
 every tick:
   1. completes steps whose device work has finished (indices land in pinned
-     host memory; workspace bytes and the slot are released);
+     host memory; the step's device memory and slot are released);
   2. while a slot (an in-flight step, each on its own HIP stream) is free,
-     admits requests from the head of the queue as long as their workspace
-     fits the remaining budget, and launches them as ONE batched call.
+     admits requests from the head of the queue, spread over the free slots
+     (a step takes ceil(queued / free slots) of them, so a lightly loaded
+     server runs each request alone and batches form once slots are busy),
+     reserves the step's exact device memory (workspace and output) from the
+     executor, and launches the requests as ONE batched call.
 Requests that arrive while other steps run are admitted as soon as a slot
 and memory free up, and steps overlap on the device. A request whose
 arguments are invalid fails alone (checked on submit); one that can never fit
-the budget fails alone; an executor failure fails the requests of that step
-only and the server keeps serving.
+the memory budget fails alone; an executor failure fails the requests of that
+step only and the server keeps serving.
 
-The scheduler is plain host logic over an Executor (launch / poll / collect);
-GpuExecutor runs the batched library call, PlainGpuExecutor one single-series
-call per request (the comparator).
+The scheduler is plain host logic over an Executor (reserve / launch / poll /
+collect / release); GpuExecutor runs the batched library call with its
+workspace and output carved out of one device arena allocated up front (the
+budget is the arena: serving allocates no other device memory), and
+PlainGpuExecutor one single-series call per request (the comparator).
 """
 from __future__ import annotations
 
@@ -43,6 +48,7 @@ class Request:
     done: float | None = None
     result: np.ndarray | None = None
     error: str | None = None
+    batch: int = 0  # requests in the step that served it
 
     @property
     def n(self) -> int:
@@ -78,14 +84,25 @@ class Step:
     slot: int
     reqs: list
     ws_bytes: int
+    token: object = None
     handle: object = None
+    launched: float = 0.0
 
 
 class Scheduler:
-    def __init__(self, executor, n_slots: int = 2, ws_budget: int = 256 << 20, max_batch: int | None = None,
+    def __init__(self, executor, n_slots: int = 2, ws_budget: int | None = None, max_batch: int | None = None,
                  clock=time.perf_counter):
         self.ex = executor
         self.n_slots = n_slots
+        # bytes the executor may hold for in-flight steps (an executor with a
+        # device arena bounds this by the arena's size)
+        cap = getattr(executor, "capacity", None)
+        if ws_budget is None:
+            ws_budget = cap
+        if ws_budget is None:
+            raise ValueError("ws_budget is needed for an executor without a fixed capacity")
+        if cap is not None and ws_budget > cap:
+            raise ValueError(f"ws_budget {ws_budget} exceeds the executor's device arena of {cap} bytes")
         self.ws_budget = ws_budget
         self.max_batch = max_batch
         self.clock = clock
@@ -93,17 +110,28 @@ class Scheduler:
         self.free_slots = list(range(n_slots))
         self.in_flight: list[Step] = []
         self.ws_in_use = 0
+        self.max_ws_in_use = 0
         self.t0 = None
         self.completed: list[Request] = []
         self.steps_launched = 0
         self.max_in_flight = 0
         self.batch_sizes: list[int] = []
+        self.busy_since = None  # start of the current stretch with a step in flight
+        self.busy_time = 0.0
 
     def now(self) -> float:
         return self.clock() - self.t0
 
     def start(self):
         self.t0 = self.clock()
+        self.busy_since = None
+        self.busy_time = 0.0
+
+    def busy_fraction(self, span: float) -> float:
+        """Fraction of `span` seconds during which at least one step was in
+        flight (launched and not yet seen complete)."""
+        busy = self.busy_time + ((self.now() - self.busy_since) if self.busy_since is not None else 0.0)
+        return busy / span if span > 0 else 0.0
 
     def submit(self, req: Request):
         err = validate(req, self.ex.series_len(req.series))
@@ -142,41 +170,67 @@ class Scheduler:
                 for r in st.reqs:
                     r.done = t
                     self.completed.append(r)
+                self.ex.release(st.token)
                 self.ws_in_use -= st.ws_bytes
                 self.free_slots.append(st.slot)
             else:
                 still.append(st)
         self.in_flight = still
+        if not self.in_flight and self.busy_since is not None:
+            self.busy_time += self.now() - self.busy_since
+            self.busy_since = None
+
+    def _take_batch(self):
+        """Requests from the head of the queue for one step: ceil(queued / free
+        slots) of them (at most max_batch), as long as their estimated memory
+        fits what the budget has left."""
+        want = -(-len(self.queue) // len(self.free_slots))
+        if self.max_batch is not None:
+            want = min(want, self.max_batch)
+        batch, est = [], 0
+        while self.queue and len(batch) < want:
+            need = self.ex.request_ws(self.queue[0])
+            if self.ws_in_use + est + need > self.ws_budget:
+                break
+            batch.append(self.queue.popleft())
+            est += need
+        return batch
 
     def _admit(self):
         while self.free_slots and self.queue:
-            batch, ws = [], 0
-            while self.queue:
-                r = self.queue[0]
-                need = self.ex.request_ws(r)
-                if self.ws_in_use + ws + need > self.ws_budget:
+            batch = self._take_batch()
+            token = None
+            while batch:
+                token = self.ex.reserve(batch)  # exact bytes of the step, or None if they do not fit now
+                if token is not None and self.ws_in_use + self.ex.token_bytes(token) <= self.ws_budget:
                     break
-                if self.max_batch is not None and len(batch) >= self.max_batch:
-                    break
-                batch.append(self.queue.popleft())
-                ws += need
+                if token is not None:
+                    self.ex.release(token)
+                    token = None
+                self.queue.appendleft(batch.pop())  # shrink the step from its tail
             if not batch:
-                return  # head does not fit until memory frees up
+                return  # the head does not fit until memory frees up
             slot = self.free_slots.pop(0)
             t = self.now()
             for r in batch:
                 r.admitted = t
-            st = Step(slot=slot, reqs=batch, ws_bytes=ws)
+                r.batch = len(batch)
+            nbytes = self.ex.token_bytes(token)
+            st = Step(slot=slot, reqs=batch, ws_bytes=nbytes, token=token, launched=t)
             try:
-                st.handle = self.ex.launch(batch, slot)
+                st.handle = self.ex.launch(batch, slot, token)
             except Exception as e:
                 for r in batch:
                     r.error = f"launch failed: {e}"
                     r.done = self.now()
                     self.completed.append(r)
+                self.ex.release(token)
                 self.free_slots.append(slot)
                 continue
-            self.ws_in_use += ws
+            self.ws_in_use += nbytes
+            self.max_ws_in_use = max(self.max_ws_in_use, self.ws_in_use)
+            if self.busy_since is None:
+                self.busy_since = t
             self.in_flight.append(st)
             self.steps_launched += 1
             self.batch_sizes.append(len(batch))
@@ -207,10 +261,13 @@ class Scheduler:
 
 
 def latency_summary(reqs) -> dict:
+    """p50 / p99 / mean latency (ms) of the successful requests, their Gpts/s
+    over the run's span, and the number of failed requests."""
+    errors = sum(1 for r in reqs if r.error is not None)
     lat = np.array([r.latency for r in reqs if r.error is None], dtype=np.float64) * 1e3
     pts = sum(r.n for r in reqs if r.error is None)
     if lat.size == 0:
-        return {"requests": 0}
+        return {"requests": 0, "errors": errors}
     first = min(r.arrival for r in reqs)
     last = max(r.done for r in reqs if r.done is not None)
     span = max(last - first, 1e-9)
@@ -221,7 +278,7 @@ def latency_summary(reqs) -> dict:
         "mean_ms": round(float(lat.mean()), 4),
         "gpts_per_s": round(pts / span / 1e9, 3),
         "span_s": round(span, 4),
-        "errors": sum(1 for r in reqs if r.error is not None),
+        "errors": errors,
     }
 
 
@@ -249,13 +306,59 @@ def poisson_requests(rate: float, count: int, pool_lengths, seed: int, n_out_ran
 
 # ------------------------------------------------------------------ executors
 
+class Arena:
+    """First-fit allocator of byte ranges in [0, size), 256-byte aligned (host
+    bookkeeping of one device allocation)."""
+
+    ALIGN = 256
+
+    def __init__(self, size: int):
+        self.size = size
+        self.free = [(0, size)]  # sorted, non-adjacent (offset, length) holes
+        self.used = 0
+
+    @classmethod
+    def round(cls, nbytes: int) -> int:
+        return -(-max(int(nbytes), 1) // cls.ALIGN) * cls.ALIGN
+
+    def alloc(self, nbytes: int):
+        nbytes = self.round(nbytes)
+        for i, (o, ln) in enumerate(self.free):
+            if ln >= nbytes:
+                if ln == nbytes:
+                    del self.free[i]
+                else:
+                    self.free[i] = (o + nbytes, ln - nbytes)
+                self.used += nbytes
+                return o, nbytes
+        return None
+
+    def release(self, block):
+        o, ln = block
+        self.used -= ln
+        holes = self.free
+        i = 0
+        while i < len(holes) and holes[i][0] < o:
+            i += 1
+        holes.insert(i, (o, ln))
+        # merge with the neighbours
+        if i + 1 < len(holes) and holes[i][0] + holes[i][1] == holes[i + 1][0]:
+            holes[i] = (holes[i][0], holes[i][1] + holes[i + 1][1])
+            del holes[i + 1]
+        if i > 0 and holes[i - 1][0] + holes[i - 1][1] == holes[i][0]:
+            holes[i - 1] = (holes[i - 1][0], holes[i - 1][1] + holes[i][1])
+            del holes[i]
+
+
 class GpuExecutor:
     """Runs each admitted set of requests as one batched call on the slot's
     stream (a set of one takes the single-series call, which launches fewer
-    kernels and gives the same indices), then copies the indices to pinned
-    host memory on that stream."""
+    kernels and gives the same indices), then copies the indices to the slot's
+    pinned host buffer on that stream. Workspace and output of every step come
+    from one device arena of `arena_bytes` allocated here."""
 
-    def __init__(self, y, offsets, lengths, x=None, n_slots: int = 2):
+    def __init__(self, y, offsets, lengths, x=None, n_slots: int = 2, arena_bytes: int = 256 << 20,
+                 host_capacity: int = 1 << 20):
         import torch
 
         self.torch = torch
@@ -263,64 +366,127 @@ class GpuExecutor:
         self.offsets = np.asarray(offsets, dtype=np.int64)
         self.lengths = np.asarray(lengths, dtype=np.int64)
         self.streams = [torch.cuda.Stream() for _ in range(n_slots)]
+        self.capacity = int(arena_bytes)
+        self.arena = torch.empty(self.capacity, dtype=torch.uint8, device=y.device)
+        self.blocks = Arena(self.capacity)
+        self.host = [torch.empty(host_capacity, dtype=torch.int64, pin_memory=True) for _ in range(n_slots)]
+        self.done_events = [torch.cuda.Event() for _ in range(n_slots)]
         self._ws_cache = {}
 
     def series_len(self, s: int) -> int:
         return int(self.lengths[s])
 
-    def request_ws(self, r: Request) -> int:
-        key = (r.n_out, r.r_ps)
+    def _single_ws(self, n_out: int, r_ps: int) -> int:
+        key = (n_out, r_ps)
         v = self._ws_cache.get(key)
         if v is None:
-            v = int(_lib.load().mmlttb_workspace_size(1, r.n_out, r.r_ps))
+            v = int(_lib.load().mmlttb_workspace_size(1, n_out, r_ps))
             self._ws_cache[key] = v
         return v
 
-    def launch(self, reqs, slot):
-        from .ops import minmaxlttb_batched, segment_table
+    def request_ws(self, r: Request) -> int:
+        """Device bytes of the request served alone (workspace and output)."""
+        return Arena.round(self._single_ws(r.n_out, r.r_ps)) + Arena.round(8 * min(r.n, r.n_out))
+
+    def _segs(self, reqs):
+        return [(int(self.offsets[r.series]) + r.lo, r.n, r.n_out, r.r_ps) for r in reqs]
+
+    def reserve(self, reqs):
+        """The step's exact device memory (workspace sized by the library for
+        this step, output indices) as one arena block, or None when it does
+        not fit now."""
+        from .ops import batched_workspace_size, segment_table
+
+        table = None
+        if len(reqs) == 1:
+            ws = self._single_ws(reqs[0].n_out, reqs[0].r_ps)
+        else:
+            table = segment_table(self._segs(reqs))
+            ws = int(_lib.load().mmlttb_batched_workspace_size(table[0], len(table[0])))
+        total_out = sum(min(r.n, r.n_out) for r in reqs)
+        ws_r = Arena.round(ws)
+        block = self.blocks.alloc(ws_r + Arena.round(8 * total_out))
+        if block is None:
+            return None
+        return {"block": block, "ws": ws_r, "out": total_out, "table": table}
+
+    @staticmethod
+    def token_bytes(token) -> int:
+        return token["block"][1]
+
+    def release(self, token):
+        if token is not None:
+            self.blocks.release(token["block"])
+
+    def _views(self, token):
+        o, ln = token["block"]
+        ws = self.arena[o: o + token["ws"]]
+        out = self.arena[o + token["ws"]: o + token["ws"] + 8 * max(token["out"], 1)].view(self.torch.int64)
+        return ws, out
+
+    def _host(self, slot, count):
+        torch = self.torch
+        if self.host[slot].numel() < count:
+            self.host[slot] = torch.empty(max(count, 2 * self.host[slot].numel()), dtype=torch.int64,
+                                          pin_memory=True)
+        return self.host[slot][:count]
+
+    def launch(self, reqs, slot, token):
+        from .ops import minmaxlttb_batched
 
         if len(reqs) == 1:
-            return PlainGpuExecutor.launch(self, reqs, slot)
+            return PlainGpuExecutor.launch(self, reqs, slot, token)
         torch = self.torch
-        segs = [(int(self.offsets[r.series]) + r.lo, r.n, r.n_out, r.r_ps) for r in reqs]
-        table = segment_table(segs)
+        ws, out = self._views(token)
         stream = self.streams[slot]
         with torch.cuda.stream(stream):
-            out, outoff = minmaxlttb_batched(self.y, segs, x_base=self.x, table=table)
-            host = torch.empty(out.numel(), dtype=torch.int64, pin_memory=True)
-            host.copy_(out, non_blocking=True)
-            ev = torch.cuda.Event()
+            _, outoff = minmaxlttb_batched(self.y, None, x_base=self.x, out=out, ws=ws, table=token["table"])
+            host = self._host(slot, token["out"])
+            host.copy_(out[: token["out"]], non_blocking=True)
+            ev = self.done_events[slot]
             ev.record(stream)
-        return (ev, host, outoff, [min(r.n, r.n_out) for r in reqs], out)
+        return (ev, host, outoff, [min(r.n, r.n_out) for r in reqs])
 
     def poll(self, handle) -> bool:
         return handle[0].query()
 
     def collect(self, handle):
-        _, host, outoff, counts, _ = handle
+        _, host, outoff, counts = handle
         h = host.numpy()
         return [h[o: o + c].copy() for o, c in zip(outoff, counts)]
 
 
 class PlainGpuExecutor(GpuExecutor):
-    """Comparator: one single-series call per request, in arrival order."""
+    """Comparator: one single-series call per request, in arrival order, each
+    with its own workspace region of the step's arena block."""
 
-    def launch(self, reqs, slot):
+    def reserve(self, reqs):
+        ws = [Arena.round(self._single_ws(r.n_out, r.r_ps)) for r in reqs]
+        total_out = sum(min(r.n, r.n_out) for r in reqs)
+        block = self.blocks.alloc(sum(ws) + Arena.round(8 * total_out))
+        if block is None:
+            return None
+        return {"block": block, "ws": sum(ws), "ws_each": ws, "out": total_out, "table": None}
+
+    def launch(self, reqs, slot, token):
         from .ops import minmaxlttb
 
         torch = self.torch
+        ws_all, out = self._views(token)
+        ws_each = token.get("ws_each") or [token["ws"]]
         stream = self.streams[slot]
-        outs = []
+        counts = [min(r.n, r.n_out) for r in reqs]
+        offs = [int(v) for v in np.concatenate([[0], np.cumsum(counts)[:-1]])]
         with torch.cuda.stream(stream):
-            for r in reqs:
+            w = 0
+            for r, o_out, k, wb in zip(reqs, offs, counts, ws_each):
                 o = int(self.offsets[r.series]) + r.lo
                 xs = None if self.x is None else self.x[o: o + r.n]
-                outs.append(minmaxlttb(self.y[o: o + r.n], r.n_out, r.r_ps, x=xs))
-            cat = torch.cat(outs) if len(outs) > 1 else outs[0]
-            host = torch.empty(cat.numel(), dtype=torch.int64, pin_memory=True)
-            host.copy_(cat, non_blocking=True)
-            ev = torch.cuda.Event()
+                minmaxlttb(self.y[o: o + r.n], r.n_out, r.r_ps, x=xs, out=out[o_out: o_out + k],
+                           ws=ws_all[w: w + wb])
+                w += wb
+            host = self._host(slot, token["out"])
+            host.copy_(out[: token["out"]], non_blocking=True)
+            ev = self.done_events[slot]
             ev.record(stream)
-        counts = [min(r.n, r.n_out) for r in reqs]
-        offs = list(np.concatenate([[0], np.cumsum(counts)[:-1]]).astype(int))
-        return (ev, host, offs, counts, outs)
+        return (ev, host, offs, counts)

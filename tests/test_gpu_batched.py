@@ -101,9 +101,10 @@ def test_workspace_size_independent_of_lengths():
 
 
 def test_full_batch_4096_series():
-    """4096 series, lengths log-uniform in [1e3, 1e7] (~4.45e9 points), int64
+    """4096 series, lengths log-uniform in [1e3, 1e7] (~4.6e9 points), int64
     irregular x, n_out in {200, 500, 1000, 2000}, r_ps = 4. Every series is
-    compared with the single-series GPU call; 64 sampled series with the oracle."""
+    compared with the oracle on that series alone and with the single-series
+    GPU call."""
     lengths = synth.batch_lengths(4096, 1e3, 1e7, 4)
     n_outs = synth.choice([200, 500, 1000, 2000], 4096, 40)
     print(f"generating {int(lengths.sum())} points", flush=True)
@@ -112,66 +113,18 @@ def test_full_batch_4096_series():
     segs = [(int(o), int(n), int(no), 4) for o, n, no in zip(offsets, lengths, n_outs)]
     out, outoff = ops.minmaxlttb_batched(y, segs, x_base=x)
     got = out.cpu().numpy()
-    print("batched call done; comparing with single-series calls", flush=True)
+    print("batched call done; comparing every series with the oracle", flush=True)
+
+    def fetch(lo, hi):
+        return y[lo:hi].cpu().numpy(), x[lo:hi].cpu().numpy()
+
+    want = oracle.minmaxlttb_segments(fetch, segs, workers=16)
+    bad = [i for i, (o, n, no, r) in enumerate(segs)
+           if not np.array_equal(got[outoff[i]: outoff[i] + min(n, no)], want[i])]
+    assert not bad, f"{len(bad)} series differ from the oracle, first {bad[:5]}"
+    print("comparing with single-series calls", flush=True)
     for i, (o, n, no, r) in enumerate(segs):
         single = ops.minmaxlttb(y[o: o + n], no, r, x=x[o: o + n]).cpu().numpy()
         assert np.array_equal(got[outoff[i]: outoff[i] + min(n, no)], single), f"series {i}"
-    rng = np.random.default_rng(11)
-    for i in rng.choice(4096, size=64, replace=False):
-        o, n, no, r = segs[i]
-        want = oracle.minmaxlttb(y[o: o + n].cpu().numpy(), no, r, x[o: o + n].cpu().numpy())
-        assert np.array_equal(got[outoff[i]: outoff[i] + min(n, no)], want), f"series {i} vs oracle"
     del x, y
     torch.cuda.empty_cache()
-
-
-@pytest.mark.parametrize("tile,chunk,unroll", [(2048, 1024, 1), (4096, 4096, 2), (8192, 65536, 8), (4096, 16384, 4)])
-def test_tuning_does_not_change_batched_results(tile, chunk, unroll):
-    lengths, n_outs, r_pss = _random_batch(21, 50, 2_000_000)
-    x, y, offsets = synth.batch_series(lengths, 21, device="cuda")
-    segs = [(int(o), int(n), int(no), int(r)) for o, n, no, r in zip(offsets, lengths, n_outs, r_pss)]
-    ref, _ = ops.minmaxlttb_batched(y, segs, x_base=x)
-    old = ops.get_tuning()
-    try:
-        ops.set_tuning(batch_unroll=unroll, batch_chunk=chunk, tile=tile)
-        got, outoff = ops.minmaxlttb_batched(y, segs, x_base=x)
-    finally:
-        ops.set_tuning(*old)
-    assert torch.equal(got, ref)
-    g = got.cpu().numpy()
-    for i in (0, 17, 49):
-        o, n, no, r = segs[i]
-        want = oracle.minmaxlttb(y[o:o + n].cpu().numpy(), no, r, x[o:o + n].cpu().numpy())
-        assert np.array_equal(g[outoff[i]: outoff[i] + min(n, no)], want)
-
-
-@pytest.mark.parametrize("tile", [2048, 4096, 8192])
-def test_small_tiles_every_lane_group_width(tile):
-    """Small-bin tiles with every bins-per-tile count (4..256, so 64..1 lanes
-    per bin), full and ragged bins, one-point bins; quantised values with
-    signed zeros so ties decide many picks (lowest index must win across lanes)."""
-    rng = np.random.default_rng(tile)
-    lengths, n_outs, r_pss = [], [], []
-    for g in (4, 8, 16, 32, 64, 128, 256):
-        s = tile // g
-        for extra in (0, 1):  # every bin s points; or bins of s - 1 and s points
-            nb = 200
-            lengths.append(nb * (s - extra) + (nb // 2 if extra else 0) + 2)
-            n_outs.append(100)
-            r_pss.append(4)
-    lengths += [202, 1002]  # one-point and five-point bins
-    n_outs += [100, 100]
-    r_pss += [4, 4]
-    lengths = np.array(lengths, dtype=np.int64)
-    total = int(lengths.sum()) + 3 * len(lengths)
-    offsets = np.cumsum(np.concatenate([[1], (lengths + 3)[:-1]]))  # misaligned starts
-    vals = np.round(rng.standard_normal(total) * 2) / 2
-    vals[rng.random(total) < 0.1] = -0.0
-    y = torch.from_numpy(vals.astype(np.float32)).cuda()
-    x = synth.irregular_x(total, tile, device="cuda")
-    old = ops.get_tuning()
-    try:
-        ops.set_tuning(tile=tile)
-        _check_batch(x, y, offsets, lengths, np.array(n_outs), np.array(r_pss))
-    finally:
-        ops.set_tuning(*old)

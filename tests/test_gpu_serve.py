@@ -55,9 +55,11 @@ def test_results_in_the_mix_equal_alone(pool, executor):
 
 def test_tight_budget_queues_and_bad_requests_fail_alone(pool):
     x, y, offsets, lengths = pool
-    ex = GpuExecutor(y, offsets, lengths, x=x, n_slots=2)
-    one = ex.request_ws(Request(0, 0, 0, 10, 4000, 4))
-    sched = Scheduler(ex, n_slots=2, ws_budget=2 * one)
+    probe = GpuExecutor(y, offsets, lengths, x=x, n_slots=1, arena_bytes=1 << 20)
+    one = probe.request_ws(Request(0, 0, 0, 10, 4000, 4))
+    del probe
+    ex = GpuExecutor(y, offsets, lengths, x=x, n_slots=2, arena_bytes=2 * one)
+    sched = Scheduler(ex, n_slots=2)
     reqs = poisson_requests(50_000, 60, lengths, seed=9, n_out_range=(3000, 4000), r_ps_choices=(4,))
     reqs.append(Request(1000, 0, 0, 100, 2, 4, arrival=0.0))           # invalid n_out
     reqs.append(Request(1001, 0, 0, int(lengths[0]) + 5, 100, 4, arrival=0.0))  # outside the series
@@ -68,3 +70,27 @@ def test_tight_budget_queues_and_bad_requests_fail_alone(pool):
             assert r.error is None
             assert np.array_equal(r.result, _alone(pool, r))
     assert sched.ws_in_use == 0
+
+
+@pytest.mark.parametrize("executor", [GpuExecutor, PlainGpuExecutor])
+def test_device_memory_held_stays_within_the_budget(pool, executor):
+    """The arena is the whole budget: serving a burst allocates no other
+    device memory, whatever the batch sizes, and every step's memory returns."""
+    x, y, offsets, lengths = pool
+    torch.cuda.synchronize()
+    base = torch.cuda.memory_allocated()
+    torch.cuda.reset_peak_memory_stats()
+    budget = 48 << 20
+    ex = executor(y, offsets, lengths, x=x, n_slots=3, arena_bytes=budget)
+    sched = Scheduler(ex, n_slots=3, max_batch=None if executor is GpuExecutor else 1)
+    reqs = poisson_requests(1e9, 300, lengths, seed=21)
+    done = sched.run_open_loop(reqs, timeout=120)
+    torch.cuda.synchronize()
+    assert len(done) == 300 and all(r.error is None for r in done)
+    assert torch.cuda.max_memory_allocated() - base <= budget
+    assert 0 < sched.max_ws_in_use <= budget
+    assert ex.blocks.used == 0 and ex.blocks.free == [(0, budget)]
+    for r in done[::15]:
+        assert np.array_equal(r.result, _alone(pool, r)), f"request {r.rid}"
+    if executor is GpuExecutor:
+        assert max(sched.batch_sizes) > 1

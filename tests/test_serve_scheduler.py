@@ -38,7 +38,17 @@ class FakeExecutor:
     def request_ws(self, r):
         return self.ws_per_req * (1 + r.n_out // 1000)
 
-    def launch(self, reqs, slot):
+    def reserve(self, reqs):
+        return {"bytes": sum(self.request_ws(r) for r in reqs)}
+
+    @staticmethod
+    def token_bytes(token):
+        return token["bytes"]
+
+    def release(self, token):
+        pass
+
+    def launch(self, reqs, slot, token):
         sid = self.n_steps
         self.n_steps += 1
         self.launched.append((sid, slot, [r.rid for r in reqs], self.clock.t))
@@ -204,3 +214,72 @@ def test_latency_summary_fields():
     sched = Scheduler(FakeExecutor(clock, pool), n_slots=2, ws_budget=10 ** 9, clock=clock)
     s = latency_summary(_drive(sched, _reqs(pool, 50, 1000, 3)))
     assert s["requests"] == 50 and s["p99_ms"] >= s["p50_ms"] > 0 and s["errors"] == 0
+
+
+def test_free_slots_share_the_queue():
+    """Queued requests are spread over the free slots: two requests and four
+    free slots give two steps of one; twelve give four steps of three."""
+    pool = _pool()
+    clock = FakeClock()
+    ex = FakeExecutor(clock, pool, base=0.05)
+    sched = Scheduler(ex, n_slots=4, ws_budget=10 ** 9, clock=clock)
+    sched.start()
+    for i in range(2):
+        sched.submit(Request(i, 0, 0, 1000, 10, 2, arrival=0.0))
+    sched.tick()
+    assert sorted(len(r) for _, _, r, _ in ex.launched) == [1, 1]
+    while not sched.idle():
+        clock.t += 0.01
+        sched.tick()
+    ex.launched.clear()
+    for i in range(12):
+        sched.submit(Request(10 + i, 0, 0, 1000, 10, 2, arrival=clock.t))
+    sched.tick()
+    assert [len(r) for _, _, r, _ in ex.launched] == [3, 3, 3, 3]
+
+
+class ShortArenaExecutor(FakeExecutor):
+    """reserve() refuses steps of more than `fit` requests (a fragmented arena)."""
+
+    def __init__(self, *a, fit=2, **k):
+        super().__init__(*a, **k)
+        self.fit = fit
+        self.refused = 0
+
+    def reserve(self, reqs):
+        if len(reqs) > self.fit:
+            self.refused += 1
+            return None
+        return super().reserve(reqs)
+
+
+def test_step_shrinks_when_its_exact_memory_does_not_fit():
+    pool = _pool()
+    clock = FakeClock()
+    ex = ShortArenaExecutor(clock, pool, base=0.01, fit=2)
+    sched = Scheduler(ex, n_slots=1, ws_budget=10 ** 9, clock=clock)
+    reqs = [Request(i, 1, 0, 20000, 100, 4, arrival=0.0) for i in range(7)]
+    done = _drive(sched, reqs)
+    assert len(done) == 7 and all(r.error is None for r in done)
+    assert ex.refused > 0 and max(sched.batch_sizes) == 2
+    order = [rid for _, _, rids, _ in ex.launched for rid in rids]
+    assert order == sorted(order)  # requests put back keep their place
+
+
+def test_arena_first_fit_alignment_and_merging():
+    from paper_2305_00332_amd.serve import Arena
+
+    a = Arena(4096)
+    b1 = a.alloc(1)
+    b2 = a.alloc(300)
+    b3 = a.alloc(256)
+    assert b1 == (0, 256) and b2 == (256, 512) and b3 == (768, 256)
+    assert a.used == 1024
+    assert a.alloc(4096) is None
+    a.release(b2)
+    assert a.alloc(600) == (1024, 768)  # the 512-byte hole is too small
+    assert a.alloc(512) == (256, 512)  # ... but fits this one exactly
+    for blk in ((0, 256), (256, 512), (768, 256), (1024, 768)):
+        a.release(blk)
+    assert a.free == [(0, 4096)] and a.used == 0
+    assert a.alloc(4096) == (0, 4096)
