@@ -358,7 +358,7 @@ def bench_shapes(args):
         spans = ops.profile_samples(span) if span else []
         kern = {}
         for k in ("minmax_bin_reduce", "preselect_compact_means", "lttb_chain_seg", "lttb_chain",
-                  "bucket_mean", "bucket_mean_wide", "lttb_hull", "lttb_tables", "lttb_table_walk",
+                  "bucket_mean", "bucket_mean_wide", "lttb_scan", "lttb_hull", "lttb_tables", "lttb_table_walk",
                   "lttb_chain_wide"):
             tot, c = ops.profile_read(k)
             if c:
@@ -707,7 +707,7 @@ def bench_comparator(args):
     torch.cuda.synchronize()
     ops.profile_enable(False)
     k_l = {}
-    for k in ("bucket_mean_wide", "lttb_hull", "lttb_tables", "lttb_table_walk"):
+    for k in ("lttb_scan", "bucket_mean_wide", "lttb_hull", "lttb_tables", "lttb_table_walk"):
         tot, cnt = ops.profile_read(k)
         if cnt:
             k_l[k] = round(tot / cnt, 4)

@@ -98,9 +98,9 @@ const char *mmlttb_last_error(void);
 size_t mmlttb_workspace_size(int64_t n, int64_t n_out, int32_t r_ps);
 
 /* Workspace bytes for mmlttb_lttb (next-bucket means and chain scratch:
- * about 850 bytes per bucket for n_out - 2 <= 2^24 buckets, which includes the
- * candidate lists and transition tables of wide buckets); independent of n.
- * Returns 0 on invalid arguments. */
+ * about 2.9 KB per bucket for n_out - 2 <= 2^24 buckets, which includes the
+ * per-slab highs and lows, candidate lists and transition tables of wide
+ * buckets); independent of n. Returns 0 on invalid arguments. */
 size_t mmlttb_lttb_workspace_size(int64_t n, int64_t n_out);
 
 /* MinMax preselection alone (section 2.2.1 MinMax; section 3 step (i)).

@@ -259,7 +259,7 @@ MmLayout mm_layout(int64_t n_out, int32_t r_ps)
 }
 
 struct LtLayout {
-    size_t MX, MY, path, finals, start, yr, cand_cnt, cand, tab, total;
+    size_t MX, MY, path, finals, start, yr, cand_cnt, cand, tab, slab_hi, slab_lo, delta, brk, total;
 };
 
 LtLayout lt_layout(int64_t n_out)
@@ -282,6 +282,10 @@ LtLayout lt_layout(int64_t n_out)
     L.cand_cnt = take(4 * tb);
     L.cand = take(4 * tb * kCandMax);
     L.tab = take(8 * tb * kCandMax);
+    L.slab_hi = take(8 * tb * kSlabsHost);
+    L.slab_lo = take(8 * tb * kSlabsHost);
+    L.delta = take(8 * tb);
+    L.brk = take(16 * tb);
     L.total = off;
     return L;
 }
@@ -964,12 +968,12 @@ int mmlttb_lttb(int xk, const int64_t *x, const float *y, int64_t n, int64_t n_o
     const int64_t maxb = bk.q + (bk.r ? 1 : 0);
     const bool seg = use_segmented_chain(maxb);
     // wide buckets: transition tables unless the sequential pass is asked for
-    const bool tables = !seg && maxb > 64 && tuning().chain != kChainSequential && B <= kTableMaxBuckets;
+    const bool tables = !seg && maxb > 64 && tuning().chain != kChainSequential && B <= kTableMaxBuckets &&
+                        maxb < kTableMaxBucket;
     if (maxb <= 64) {
         MMLTTB_LAUNCH("bucket_mean", s, launch_bucket_mean_small(x, y, nullptr, n, B, MX, MY, s));
-    } else {
-        float2 *yr = tables ? at<float2>(ws, L.yr) : nullptr; // bucket y ranges, for the tables
-        MMLTTB_LAUNCH("bucket_mean_wide", s, launch_bucket_mean_wide(x, y, n, B, MX, MY, yr, s));
+    } else if (!tables) {
+        MMLTTB_LAUNCH("bucket_mean_wide", s, launch_bucket_mean_wide(x, y, n, B, MX, MY, nullptr, s));
     }
     if (seg) {
         const SegChainArgs a = seg_args(ws, L.path, L.finals, L.start, x, y, nullptr, n, B, MX, MY, maxb);
@@ -977,8 +981,14 @@ int mmlttb_lttb(int xk, const int64_t *x, const float *y, int64_t n, int64_t n_o
     } else if (tables) {
         int32_t *cnt = at<int32_t>(ws, L.cand_cnt), *cand = at<int32_t>(ws, L.cand);
         int2 *tab = at<int2>(ws, L.tab);
-        MMLTTB_LAUNCH("lttb_hull", s, launch_lttb_hull(x, y, n, B, MX, MY, at<float2>(ws, L.yr), cnt, cand, s));
-        MMLTTB_LAUNCH("lttb_tables", s, launch_lttb_tables(x, y, n, B, MX, MY, cnt, cand, tab, s));
+        float2 *yr = at<float2>(ws, L.yr);
+        unsigned long long *shi = at<unsigned long long>(ws, L.slab_hi), *slo = at<unsigned long long>(ws, L.slab_lo);
+        double *delta = at<double>(ws, L.delta);
+        double2 *brk = at<double2>(ws, L.brk);
+        // pass 1: means, y ranges, slab highs and lows; pass 2: candidates; then the tables
+        MMLTTB_LAUNCH("lttb_scan", s, launch_lttb_scan(x, y, n, B, MX, MY, yr, shi, slo, s));
+        MMLTTB_LAUNCH("lttb_hull", s, launch_lttb_hull(x, y, n, B, MX, MY, yr, shi, slo, cnt, cand, delta, brk, s));
+        MMLTTB_LAUNCH("lttb_tables", s, launch_lttb_tables(x, y, n, B, MX, MY, yr, cnt, cand, delta, brk, tab, s));
         MMLTTB_LAUNCH("lttb_table_walk", s, launch_lttb_table_walk(x, y, n, B, MX, MY, cnt, cand, tab, out_idx, s));
     } else if (maxb <= kChainStage) {
         MMLTTB_LAUNCH("lttb_chain", s, launch_lttb_chain(x, y, nullptr, n, B, MX, MY, nullptr, out_idx, s));

@@ -111,6 +111,55 @@ __device__ inline void bucket_mean_one(const int64_t *__restrict__ XP, const flo
     my = a.sy / c;
 }
 
+// Block-wide exact mean: every thread of a workgroup of 256 holds partial
+// exact sums of x and y over its points; thread 0 writes the sums, each
+// rounded once to binary64, divided by `count`. Ends with a barrier.
+struct BlockMeanLds {
+    int64_t limb[4][9];
+    int64_t xlo[4], xhi[4];
+};
+
+__device__ inline void block_store_mean(I64ExactSum &sx, F32ExactSum &sy, int64_t count, BlockMeanLds &sm,
+                                        double *mx, double *my)
+{
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    sy.normalize();
+    // wave sums: normalized limbs are < 2^32 (limb 8 small), 64 of them fit
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+#pragma unroll
+        for (int q = 0; q < 9; ++q)
+            sy.limb[q] += __shfl_xor(sy.limb[q], off);
+        int64_t lo64 = (int64_t)(uint64_t)sx.s, hi64 = (int64_t)(sx.s >> 64);
+        int64_t olo = __shfl_xor(lo64, off), ohi = __shfl_xor(hi64, off);
+        sx.s += (__int128)(((unsigned __int128)(uint64_t)ohi << 64) | (uint64_t)olo);
+    }
+    if (lane == 0) {
+#pragma unroll
+        for (int q = 0; q < 9; ++q)
+            sm.limb[wid][q] = sy.limb[q];
+        sm.xlo[wid] = (int64_t)(uint64_t)sx.s;
+        sm.xhi[wid] = (int64_t)(sx.s >> 64);
+    }
+    __syncthreads();
+    if (tid == 0) {
+        F32ExactSum ty;
+        ty.clear();
+        I64ExactSum tx;
+        tx.clear();
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
+#pragma unroll
+            for (int q = 0; q < 9; ++q)
+                ty.limb[q] += sm.limb[w][q];
+            tx.s += (__int128)(((unsigned __int128)(uint64_t)sm.xhi[w] << 64) | (uint64_t)sm.xlo[w]);
+        }
+        const double c = (double)count;
+        *mx = tx.round() / c;
+        *my = ty.round() / c;
+    }
+    __syncthreads();
+}
+
 // Phase 1 of the segmented chain for chain segment s (buckets
 // [s*kSegLen, min(B, (s+1)*kSegLen))), one wave of kSegStarts lanes.
 // A segment's walk depends only on its start point, which lies in the bucket
@@ -332,6 +381,61 @@ __device__ inline void scan_groups_x(const int64_t *__restrict__ X, const float 
     const int64_t t0 = a0 + 4 * nq;
     if (t0 + tid < e)
         f(t0 + tid, kHasX ? X[t0 + tid] : t0 + tid, Y[t0 + tid]);
+}
+
+// Points [s, e) in chunks of 64 groups of 4 (256 points at a 16-byte
+// boundary of Y), one chunk per wave at a time (wave w takes chunks w, w+4, ...
+// of a workgroup of 256), three chunks of loads in flight per wave
+// (nontemporal: each point is read once). For each group a lane holds,
+// fg(p0, xl, xh, y4) with p0 its first point and xl, xh the raw x of its
+// points 0-1 and 2-3 (the positions when kHasX is false); after each chunk,
+// fc(c) on every lane of the wave (uniform). The up to 3 points before the
+// first group and after the last are left to the caller: returns a0 (the
+// first group's first point) and sets *t0 (the point after the last group).
+template <bool kHasX, class FG, class FC>
+__device__ __forceinline__ int64_t scan_chunks(const int64_t *__restrict__ X, const float *__restrict__ Y, int64_t s,
+                                               int64_t e, int64_t *t0, FG &&fg, FC &&fc)
+{
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const uint64_t ya = (uint64_t)(uintptr_t)(Y + s);
+    int64_t a0 = s + (int64_t)(((16u - (unsigned)(ya & 15u)) & 15u) >> 2);
+    a0 = a0 < e ? a0 : e;
+    const int64_t nq = (e - a0) >> 2;
+    *t0 = a0 + 4 * nq;
+    const f32x4 *__restrict__ Y4 = reinterpret_cast<const f32x4 *>(Y + a0);
+    const bool x16 = kHasX && ((((uint64_t)(uintptr_t)(X + a0)) & 15u) == 0);
+    const f32x4 zy = {0.0f, 0.0f, 0.0f, 0.0f};
+    const i64x2 zx = {0, 0};
+    auto ly = [&](int64_t q) { return q < nq ? __builtin_nontemporal_load(Y4 + q) : zy; };
+    auto lx = [&](int64_t q, int half) -> i64x2 {
+        const int64_t p = a0 + 4 * q + 2 * half;
+        if (q >= nq)
+            return zx;
+        if (!kHasX)
+            return i64x2{p, p + 1};
+        if (x16)
+            return __builtin_nontemporal_load(reinterpret_cast<const i64x2 *>(X + p));
+        return i64x2{__builtin_nontemporal_load(X + p), __builtin_nontemporal_load(X + p + 1)};
+    };
+    int64_t base = 64 * (int64_t)wid;
+    f32x4 y0 = ly(base + lane), y1 = ly(base + 256 + lane);
+    i64x2 a0l = lx(base + lane, 0), a0h = lx(base + lane, 1);
+    i64x2 a1l = lx(base + 256 + lane, 0), a1h = lx(base + 256 + lane, 1);
+    for (; base < nq; base += 256) {
+        const int64_t q2 = base + 512 + lane;
+        const f32x4 y2 = ly(q2);
+        const i64x2 a2l = lx(q2, 0), a2h = lx(q2, 1);
+        if (base + lane < nq)
+            fg(a0 + 4 * (base + lane), a0l, a0h, y0);
+        fc(base >> 6);
+        y0 = y1;
+        a0l = a1l;
+        a0h = a1h;
+        y1 = y2;
+        a1l = a2l;
+        a1h = a2h;
+    }
+    return a0;
 }
 
 template <int kDepth = 2, class F>

@@ -323,6 +323,38 @@ struct F32ExactSum {
             normalize();
     }
 
+    // Adds a binary64 value that is an exact sum of float32 values (so a
+    // multiple of 2^-149 below 2^129 in magnitude): its 53-bit significand,
+    // placed at its bit position, spans at most three limbs.
+    __device__ void add_exact_f64(double d)
+    {
+        if (d == 0.0)
+            return;
+        const uint64_t u = (uint64_t)__double_as_longlong(d);
+        const int be = (int)((u >> 52) & 0x7ffu);
+        uint64_t m = (u & 0xfffffffffffffull) | (be ? (1ull << 52) : 0ull);
+        int shift = (be ? be : 1) - 1075 + 149; // bit position of m's lowest bit above 2^-149
+        if (shift < 0) { // the bits below 2^-149 are zero (d is a multiple of it)
+            m >>= -shift;
+            shift = 0;
+        }
+        const int k = shift >> 5, r = shift & 31;
+        const unsigned __int128 w = (unsigned __int128)m << r;
+        const int64_t t[3] = {(int64_t)(uint64_t)(w & 0xffffffffu), (int64_t)(uint64_t)((w >> 32) & 0xffffffffu),
+                              (int64_t)(uint64_t)(w >> 64)};
+        const bool neg = (u >> 63) != 0;
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            const int64_t v = neg ? -t[j] : t[j];
+#pragma unroll
+            for (int i = 0; i < 8; ++i)
+                limb[i] += (k + j == i) ? v : 0;
+            limb[8] += (k + j == 8) ? v : ((k + j == 9) ? (int64_t)((uint64_t)v << 32) : 0);
+        }
+        if (++pending == 255)
+            normalize();
+    }
+
     // Merge a normalized accumulator into a normalized one.
     __device__ void merge_normalized(const F32ExactSum &o)
     {

@@ -258,18 +258,27 @@ hipError_t launch_lttb_chain_seg(const SegChainArgs &a, const int64_t *Pmap, int
 hipError_t launch_lttb_chain_seg(const SegChainArgsD &a, const int64_t *Pmap, int64_t *out, hipStream_t s);
 hipError_t launch_lttb_chain(const double *XP, const double *YP, const int64_t *m_ptr, int64_t m_const, int64_t B,
                              const double *MX, const double *MY, const int64_t *Pmap, int64_t *out, hipStream_t s);
-// Whole-series LTTB by transition tables: candidate picks per bucket (hull
-// vertices and near-hull points, at most kCandMax, count -1 when more), the
-// pick in each bucket for every candidate of the bucket before, and a walk
-// that scans a bucket in full where its predecessor is not a candidate.
+// Whole-series LTTB by transition tables: a first pass (next-bucket means, y
+// ranges, the highest and lowest point of each of kSlabsHost slabs), candidate
+// picks per bucket (hull points of the arc the predecessors' slopes can touch,
+// at most kCandMax, count -1 when more), the pick in each bucket for every
+// candidate of the bucket before (over the candidates where a rounding
+// certificate holds, else over the whole bucket), and a walk that scans a
+// bucket in full where its predecessor is not a candidate.
 constexpr int kCandMax = 64;
-// Largest bucket count the table form runs (its grids and tables grow with B).
+constexpr int kSlabsHost = 128; // slabs per bucket (pass 1)
+// Largest bucket count the table form runs (its grids and tables grow with B),
+// and largest bucket (offsets in 32-bit keys).
 constexpr int64_t kTableMaxBuckets = (int64_t)1 << 24;
+constexpr int64_t kTableMaxBucket = (int64_t)1 << 31;
+hipError_t launch_lttb_scan(const int64_t *X, const float *Y, int64_t n, int64_t B, double *MX, double *MY, float2 *YR,
+                            unsigned long long *slab_hi, unsigned long long *slab_lo, hipStream_t s);
 hipError_t launch_lttb_hull(const int64_t *X, const float *Y, int64_t n, int64_t B, const double *MX, const double *MY,
-                            const float2 *YR, int32_t *cand_cnt, int32_t *cand, hipStream_t s);
+                            const float2 *YR, const unsigned long long *slab_hi, const unsigned long long *slab_lo,
+                            int32_t *cand_cnt, int32_t *cand, double *delta, double2 *brk, hipStream_t s);
 hipError_t launch_lttb_tables(const int64_t *X, const float *Y, int64_t n, int64_t B, const double *MX,
-                              const double *MY, const int32_t *cand_cnt, const int32_t *cand, int2 *tab,
-                              hipStream_t s);
+                              const double *MY, const float2 *YR, const int32_t *cand_cnt, const int32_t *cand,
+                              const double *delta, const double2 *brk, int2 *tab, hipStream_t s);
 hipError_t launch_lttb_table_walk(const int64_t *X, const float *Y, int64_t n, int64_t B, const double *MX,
                                   const double *MY, const int32_t *cand_cnt, const int32_t *cand, const int2 *tab,
                                   int64_t *out, hipStream_t s);

@@ -72,8 +72,7 @@ __global__ __launch_bounds__(256) void k_bucket_mean_wide(const int64_t *__restr
                                                           int64_t m, int64_t B, double *__restrict__ MX,
                                                           double *__restrict__ MY, float2 *__restrict__ YR)
 {
-    __shared__ int64_t s_limb[4][9];
-    __shared__ int64_t s_xlo[4], s_xhi[4];
+    __shared__ BlockMeanLds sm;
     __shared__ float s_lo[4], s_hi[4];
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     const Split bk = make_split(m - 2, B);
@@ -121,41 +120,7 @@ __global__ __launch_bounds__(256) void k_bucket_mean_wide(const int64_t *__restr
         });
         if (YR && k + 1 < B)
             yrange(lo, hi, &YR[k + 1]);
-        sy.normalize();
-        // wave sums: normalized limbs are < 2^32 (limb 8 small), 64 of them fit
-#pragma unroll
-        for (int off = 32; off >= 1; off >>= 1) {
-#pragma unroll
-            for (int q = 0; q < 9; ++q)
-                sy.limb[q] += __shfl_xor(sy.limb[q], off);
-            int64_t lo64 = (int64_t)(uint64_t)sx.s, hi64 = (int64_t)(sx.s >> 64);
-            int64_t olo = __shfl_xor(lo64, off), ohi = __shfl_xor(hi64, off);
-            sx.s += (__int128)(((unsigned __int128)(uint64_t)ohi << 64) | (uint64_t)olo);
-        }
-        if (lane == 0) {
-#pragma unroll
-            for (int q = 0; q < 9; ++q)
-                s_limb[wid][q] = sy.limb[q];
-            s_xlo[wid] = (int64_t)(uint64_t)sx.s;
-            s_xhi[wid] = (int64_t)(sx.s >> 64);
-        }
-        __syncthreads();
-        if (tid == 0) {
-            F32ExactSum ty;
-            ty.clear();
-            I64ExactSum tx;
-            tx.clear();
-            for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
-#pragma unroll
-                for (int q = 0; q < 9; ++q)
-                    ty.limb[q] += s_limb[w][q];
-                tx.s += (__int128)(((unsigned __int128)(uint64_t)s_xhi[w] << 64) | (uint64_t)s_xlo[w]);
-            }
-            const double c = (double)(g1 - g0);
-            MX[k] = tx.round() / c;
-            MY[k] = ty.round() / c;
-        }
-        __syncthreads();
+        block_store_mean(sx, sy, g1 - g0, sm, &MX[k], &MY[k]);
     }
 }
 
