@@ -69,11 +69,15 @@ constexpr int kSlabs = kSlabsHost;
 constexpr double kErr = 0x1p-49;
 // Candidates per full-scan group of the table pass.
 constexpr int kTabGroup = 4;
-// The walk stages the first kWalkSlots entries of kWalkWindow buckets in LDS
-// (entries past them, rare, are read from global memory).
-constexpr int kWalkWindow = 128;
+// The walk stages, for the first kWalkSlots entries of up to kWalkWindow
+// buckets, the slot each leads to (entries past them, rare, are read from
+// global memory); segments of kWalkSeg buckets are followed from every entry
+// slot, then groups of kWalkGroup segments.
+constexpr int kWalkWindow = 2048;
 constexpr int kWalkSlots = 16;
-constexpr int kWalkSeg = 16; // buckets per segment followed by one thread
+constexpr int kWalkSeg = 16;
+constexpr int kWalkGroup = 16;
+constexpr uint8_t kWalkOut = 0xff; // a slot outside [0, kWalkSlots)
 
 __device__ inline double xval(const int64_t *__restrict__ X, int64_t p) { return X ? (double)X[p] : (double)p; }
 
@@ -304,7 +308,8 @@ __global__ __launch_bounds__(256) void k_lttb_scan(const int64_t *__restrict__ X
 // One side's arc: vertices (x relative to the bucket's first point, y) in
 // increasing x, the float32 slopes of its edges, and the slopes of the lines
 // that stand for it left of its first and right of its last vertex.
-constexpr int kArcSlopes = 16; // touching points that make an arc
+constexpr int kArcSlopes = 8; // touching points that make an arc
+constexpr int kScanU = 8;     // points in flight per thread in the survivor scan
 struct Arc {
     double x[kArcSlopes], y[kArcSlopes];
     float xf[kArcSlopes], yf[kArcSlopes], sf[kArcSlopes];
@@ -449,6 +454,7 @@ struct SlabMap {
 //     at the vertices inside) and its lowest y likewise above the lower arc;
 //  4. the points of the other slabs through the exact tests: the survivors;
 //  5. two monotone chains over the survivors: the candidates.
+static_assert(kSlabs == 128, "k_lttb_hull tests slab i on thread i of its two waves");
 __global__ __launch_bounds__(128) void k_lttb_hull(const int64_t *__restrict__ X, const float *__restrict__ Y,
                                                    int64_t n, int64_t B, const double *__restrict__ MX,
                                                    const double *__restrict__ MY, const float2 *__restrict__ YR,
@@ -460,7 +466,8 @@ __global__ __launch_bounds__(128) void k_lttb_hull(const int64_t *__restrict__ X
     __shared__ double gx[2 * kSlabs], gy[2 * kSlabs], ex_[2], ey_[4];
     __shared__ int32_t go[2 * kSlabs];
     __shared__ Arc arc[2];
-    __shared__ uint8_t scan_slab[kSlabs];
+    __shared__ int64_t fl_lo[kSlabs];
+    __shared__ int32_t fl_at[kSlabs + 1], s_wcnt[2], s_wlen[2];
     __shared__ double sx[kSurvMax], sy[kSurvMax], tx[kSurvMax], ty[kSurvMax];
     __shared__ int32_t si[kSurvMax], ti[kSurvMax];
     __shared__ double cxs[2][kChainMax], cys[2][kChainMax];
@@ -513,19 +520,36 @@ __global__ __launch_bounds__(128) void k_lttb_hull(const int64_t *__restrict__ X
         ey_[2] = (double)YR[b].y;
         ey_[3] = (double)YR[b].x;
     }
-    // the slab highs and lows, gathered in parallel
-    for (int i = tid; i < 2 * kSlabs; i += blockDim.x) {
-        const bool upper = i < kSlabs;
-        const unsigned long long kk = upper ? slab_hi[b * kSlabs + i] : slab_lo[b * kSlabs + i - kSlabs];
-        int32_t o = -1;
-        if (kk != (upper ? 0ull : ~0ull)) {
-            const uint32_t lw = (uint32_t)kk;
-            o = (int32_t)(upper ? 0xffffffffu - lw : lw);
-            o = o < 0 ? 0 : (o >= cnt ? cnt - 1 : o);
+    // the slab highs and lows (thread i: slab i): y from the keys, x
+    // interpolated by position between the slab's first and last x (the
+    // arcs' choice of vertices only; a vertex's own x is read exactly), and
+    // the slab's x range for its test
+    SlabMap sm;
+    sm.init(Y, s, e);
+    int64_t lo, hi;
+    sm.range(tid, lo, hi);
+    double xl = 0.0, xh = 0.0;
+    {
+        const unsigned long long ku = slab_hi[b * kSlabs + tid], kd = slab_lo[b * kSlabs + tid];
+        if (hi > lo) {
+            xl = xval(X, lo) - x0;
+            xh = xval(X, hi - 1) - x0;
         }
-        gx[i] = o >= 0 ? xval(X, s + o) - x0 : 0.0;
-        gy[i] = o >= 0 ? (double)Y[s + o] : 0.0;
-        go[i] = o;
+        const double span = hi - 1 > lo ? (double)(hi - 1 - lo) : 1.0;
+#pragma unroll
+        for (int w = 0; w < 2; ++w) {
+            const unsigned long long kk = w == 0 ? ku : kd;
+            int32_t o = -1;
+            if (kk != (w == 0 ? 0ull : ~0ull)) {
+                const uint32_t lw = (uint32_t)kk;
+                o = (int32_t)(w == 0 ? 0xffffffffu - lw : lw);
+                o = o < 0 ? 0 : (o >= cnt ? cnt - 1 : o);
+            }
+            const double f = o >= 0 ? fmin(fmax((double)(s + o - lo) / span, 0.0), 1.0) : 0.0;
+            gx[w * kSlabs + tid] = xl + (xh - xl) * f;
+            gy[w * kSlabs + tid] = o >= 0 ? (double)f32_from_order_key((uint32_t)(kk >> 32)) : 0.0;
+            go[w * kSlabs + tid] = o;
+        }
     }
     __syncthreads();
     const double delta = s_delta;
@@ -549,14 +573,34 @@ __global__ __launch_bounds__(128) void k_lttb_hull(const int64_t *__restrict__ X
             y = gy[q];
             return go[q] >= 0;
         };
-        float gs[kArcSlopes];
+        // kArcSlopes slopes from gL to gR: the unit directions (1, g r) of the
+        // two ends ((0, +-1) for an infinite slope), r = x span / y span,
+        // mixed linearly. Any slopes in the bracket make a valid arc; these
+        // spread its vertices along the hull.
+        double gs[kArcSlopes];
         {
-            const float ys = fmaxf(ey_[2] - ey_[3], 1e-30f), xs = fmaxf((float)ex_[1], 1.0f);
-            const float r = xs / ys;
-            const float aL = atanf((float)gL * r), aR = atanf((float)gR * r); // +-pi/2 when infinite
+            const double ys = fmax(ey_[2] - ey_[3], 1e-300), xs = fmax(ex_[1], 1.0);
+            const double r = xs / ys;
+            double dxL, dyL, dxR, dyR;
+            auto dir = [&](double g, double &dx, double &dy) {
+                const double t = g * r;
+                if (!(fabs(t) < 1e150)) {
+                    dx = 0.0;
+                    dy = t > 0.0 ? 1.0 : -1.0;
+                } else {
+                    const double h = 1.0 / sqrt(1.0 + t * t);
+                    dx = h;
+                    dy = t * h;
+                }
+            };
+            dir(gL, dxL, dyL);
+            dir(gR, dxR, dyR);
 #pragma unroll
-            for (int i = 0; i < kArcSlopes; ++i)
-                gs[i] = tanf(aL + (aR - aL) * i / (kArcSlopes - 1)) / r;
+            for (int i = 0; i < kArcSlopes; ++i) {
+                const double w = (double)i / (kArcSlopes - 1);
+                const double dx = (1.0 - w) * dxL + w * dxR, dy = (1.0 - w) * dyL + w * dyR;
+                gs[i] = dy / fmax(dx, 1e-150) / r;
+            }
         }
         double best[kArcSlopes];
         int bi[kArcSlopes];
@@ -571,7 +615,7 @@ __global__ __launch_bounds__(128) void k_lttb_hull(const int64_t *__restrict__ X
                 continue;
 #pragma unroll
             for (int i = 0; i < kArcSlopes; ++i) {
-                const double v = sign * (y - (double)gs[i] * x);
+                const double v = sign * (y - gs[i] * x);
                 if (v > best[i]) { // increasing j per lane: the lowest keeps a tie
                     best[i] = v;
                     bi[i] = j;
@@ -595,82 +639,135 @@ __global__ __launch_bounds__(128) void k_lttb_hull(const int64_t *__restrict__ X
             bi[0] = 0;
         if (!(fabs(gR) < inf))
             bi[kArcSlopes - 1] = kPts - 1;
-        if (lane == 0) {
-            int m = 0, last = -1;
-            for (int i = 0; i < kArcSlopes; ++i) { // increasing x along a concave (upper) or convex (lower) hull
-                const int j = bi[i] == 0x7fffffff ? (i == 0 ? 0 : kPts - 1) : bi[i];
-                double x, y;
-                if (!pt(j, x, y) || j <= last)
-                    continue; // a repeat, or out of order after rounding: dropped
-                A.x[m] = x;
-                A.y[m] = y;
+        // the vertices: slope i's touching point when it lies after every
+        // earlier one (x increasing); lane i places slope i's
+        int run = -1, m = 0, mine = -1, at = 0, next = -1;
+#pragma unroll
+        for (int i = 0; i < kArcSlopes; ++i) {
+            const int j = bi[i] == 0x7fffffff ? (i == 0 ? 0 : kPts - 1) : bi[i];
+            const bool keep = j > run;
+            if (keep) {
+                if (i == lane) {
+                    mine = j;
+                    at = m;
+                } else if (i > lane && next < 0) {
+                    next = j;
+                }
+                run = j;
                 ++m;
-                last = j;
             }
-            for (int i = 0; i < m; ++i) {
-                A.xf[i] = (float)A.x[i];
-                A.yf[i] = (float)A.y[i];
-                A.sf[i] = i + 1 < m ? (float)((A.y[i + 1] - A.y[i]) / (A.x[i + 1] - A.x[i])) : 0.0f;
-            }
+        }
+        double vx = 0.0, vy = 0.0;
+        if (mine >= 0) { // the vertex itself, x read exactly
+            pt(mine, vx, vy);
+            if (mine != 0 && mine != kPts - 1)
+                vx = xval(X, s + go[(upper ? 0 : kSlabs) + mine - 1]) - x0;
+            A.x[at] = vx;
+            A.y[at] = vy;
+            A.xf[at] = (float)vx;
+            A.yf[at] = (float)vy;
+        }
+        if (lane == 0) {
             A.n = m;
             A.gl = gL;
             A.gr = gR;
             A.glf = (float)gL;
             A.grf = (float)gR;
         }
+        __syncthreads();
+        if (mine >= 0)
+            A.sf[at] = next >= 0 ? (float)((A.y[at + 1] - vy) / (A.x[at + 1] - vx)) : 0.0f;
     }
     __syncthreads();
 
-    // 3. the slabs that can hold a survivor
-    SlabMap sm;
-    sm.init(Y, s, e);
-    for (int i = tid; i < kSlabs; i += blockDim.x) {
-        int64_t lo, hi;
-        sm.range(i, lo, hi);
-        bool need = false;
-        if (hi > lo) {
-            const double xl = xval(X, lo) - x0, xh = xval(X, hi - 1) - x0;
-            for (int w = 0; w < 2 && !need; ++w) {
-                const Arc &A = arc[w];
-                const double sign = w == 0 ? 1.0 : -1.0;
-                if (A.n < 1 || go[w * kSlabs + i] < 0) {
-                    need = true;
-                    break;
-                }
-                // the least (upper) or greatest (lower) arc value over [xl, xh]
-                double ea, eb;
-                double v = sign * fmin(sign * arc_value(A, xl, ea), sign * arc_value(A, xh, eb));
-                double err = fmax(ea, eb);
-                for (int k = 0; k < A.n; ++k)
-                    if (A.x[k] > xl && A.x[k] < xh)
-                        v = sign > 0 ? fmin(v, A.y[k]) : fmax(v, A.y[k]);
-                const double ext = gy[w * kSlabs + i]; // the slab's highest (upper) or lowest (lower) y
-                const double gap = sign * (v - ext);    // > 0 when the slab lies inside
-                need = !(gap - err - 0x1p-50 * (fabs(v) + fabs(ext)) > 2.0 * delta);
+    // 3. the slabs that can hold a survivor (thread i tests slab i), listed
+    // in order with their first point and their place in the list's points
+    bool need = false;
+    if (hi > lo) {
+        for (int w = 0; w < 2 && !need; ++w) {
+            const Arc &A = arc[w];
+            const double sign = w == 0 ? 1.0 : -1.0;
+            if (A.n < 1 || go[w * kSlabs + tid] < 0) {
+                need = true;
+                break;
             }
+            // the least (upper) or greatest (lower) arc value over [xl, xh]
+            double ea, eb;
+            double v = sign * fmin(sign * arc_value(A, xl, ea), sign * arc_value(A, xh, eb));
+            const double err = fmax(ea, eb);
+            for (int q = 0; q < A.n; ++q)
+                if (A.x[q] > xl && A.x[q] < xh)
+                    v = sign > 0 ? fmin(v, A.y[q]) : fmax(v, A.y[q]);
+            const double ext = gy[w * kSlabs + tid]; // the slab's highest (upper) or lowest (lower) y
+            const double gap = sign * (v - ext);      // > 0 when the slab lies inside
+            need = !(gap - err - 0x1p-50 * (fabs(v) + fabs(ext)) > 2.0 * delta);
         }
-        scan_slab[i] = need ? 1 : 0;
+    }
+    {
+        const int len = need ? (int)(hi - lo) : 0;
+        const unsigned long long bal = __ballot(need);
+        int v = len; // inclusive prefix over the wave
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const int t = __shfl_up(v, off);
+            v += lane >= off ? t : 0;
+        }
+        if (lane == 63) {
+            s_wcnt[wid] = __popcll(bal);
+            s_wlen[wid] = v;
+        }
+        __syncthreads();
+        if (need) {
+            const int q = (wid ? s_wcnt[0] : 0) + __popcll(bal & ((1ull << lane) - 1ull));
+            fl_lo[q] = lo;
+            fl_at[q] = (wid ? s_wlen[0] : 0) + v - len;
+        }
+        if (tid == 0)
+            fl_at[s_wcnt[0] + s_wcnt[1]] = s_wlen[0] + s_wlen[1];
     }
     __syncthreads();
 
-    // 4. survivors: the points of those slabs not inside both arcs
-    for (int i = 0; i < kSlabs; ++i) {
-        if (!scan_slab[i])
-            continue;
-        int64_t lo, hi;
-        sm.range(i, lo, hi);
-        int iu = 0, il = 0;
-        for (int64_t p = lo + tid; p < hi; p += blockDim.x) {
-            const double x = xval(X, p) - x0, y = (double)Y[p];
-            const float xf = (float)x, yf = (float)y;
-            const bool inside = arc_inside(arc[0], 1.0, delta, d2f, x, y, xf, yf, iu) &&
-                                arc_inside(arc[1], -1.0, delta, d2f, x, y, xf, yf, il);
-            if (!inside) {
-                const int q = atomicAdd(&nsurv, 1);
-                if (q < kSurvMax) {
-                    sx[q] = x;
-                    sy[q] = y;
-                    si[q] = (int32_t)(p - s);
+    // 4. survivors: the points of those slabs not inside both arcs, kScanU
+    // loads in flight per thread
+    {
+        const int F = s_wlen[0] + s_wlen[1];
+        int iu = 0, il = 0, j = 0;
+        for (int f0 = 0; f0 < F; f0 += kScanU * kSlabs) {
+            int64_t p[kScanU];
+#pragma unroll
+            for (int u = 0; u < kScanU; ++u) {
+                const int f = f0 + u * kSlabs + tid;
+                if (f < F) {
+                    while (fl_at[j + 1] <= f)
+                        ++j;
+                    p[u] = fl_lo[j] + (f - fl_at[j]);
+                } else {
+                    p[u] = -1;
+                }
+            }
+            double xv[kScanU];
+            float yv[kScanU];
+#pragma unroll
+            for (int u = 0; u < kScanU; ++u) {
+                const int64_t q = p[u] >= 0 ? p[u] : s;
+                xv[u] = xval(X, q);
+                yv[u] = Y[q];
+            }
+#pragma unroll
+            for (int u = 0; u < kScanU; ++u) {
+                if (p[u] < 0)
+                    continue;
+                const double x = xv[u] - x0, y = (double)yv[u];
+                const float xf = (float)x, yf = (float)y;
+                const bool inside = arc_inside(arc[0], 1.0, delta, d2f, x, y, xf, yf, iu) &&
+                                    arc_inside(arc[1], -1.0, delta, d2f, x, y, xf, yf, il);
+                if (!inside) {
+                    const int q = atomicAdd(&nsurv, 1);
+                    if (q < kSurvMax) {
+                        sx[q] = x;
+                        sy[q] = y;
+                        si[q] = (int32_t)(p[u] - s);
+                    }
                 }
             }
         }
@@ -689,25 +786,41 @@ __global__ __launch_bounds__(128) void k_lttb_hull(const int64_t *__restrict__ X
     }
     __syncthreads();
 
-    // 5. chains: thread 0 the upper, thread 1 the lower
-    if (tid < 2 && total <= kSurvMax) {
-        const double sign = tid == 0 ? 1.0 : -1.0;
+    // 5. chains: thread 0 the upper, thread 64 the lower (the two top
+    // entries of the stack kept in registers)
+    if ((tid & 63) == 0 && total <= kSurvMax) {
+        const int c = tid >> 6;
+        const double sign = c == 0 ? 1.0 : -1.0;
         int m = 0;
+        double ax = 0.0, ay = 0.0, bx = 0.0, by = 0.0; // entries m-2 and m-1
+        double x = ns > 0 ? tx[0] : 0.0, y = ns > 0 ? ty[0] : 0.0;
         for (int q = 0; q < ns; ++q) {
-            const double x = tx[q], y = ty[q];
-            while (m >= 2 &&
-                   chain_drop(cxs[tid][m - 2], cys[tid][m - 2], cxs[tid][m - 1], cys[tid][m - 1], x, y, sign, delta))
+            const double nx = q + 1 < ns ? tx[q + 1] : 0.0, ny = q + 1 < ns ? ty[q + 1] : 0.0;
+            while (m >= 2 && chain_drop(ax, ay, bx, by, x, y, sign, delta)) {
                 --m;
+                bx = ax;
+                by = ay;
+                if (m >= 2) {
+                    ax = cxs[c][m - 2];
+                    ay = cys[c][m - 2];
+                }
+            }
             if (m < kChainMax) {
-                cxs[tid][m] = x;
-                cys[tid][m] = y;
-                ci[tid][m] = ti[q];
+                cxs[c][m] = x;
+                cys[c][m] = y;
+                ci[c][m] = ti[q];
+                ax = bx;
+                ay = by;
+                bx = x;
+                by = y;
                 ++m;
             } else {
                 ovf = 1;
             }
+            x = nx;
+            y = ny;
         }
-        cn[tid] = m;
+        cn[c] = m;
     }
     __syncthreads();
 
@@ -887,13 +1000,15 @@ __global__ __launch_bounds__(kTableThreads) void k_lttb_tables(const int64_t *__
     }
 }
 
-// One workgroup of 1024 threads. Windows of kWalkWindow buckets: their first
-// kWalkSlots table entries are staged in LDS, every segment of kWalkSeg
-// buckets is followed from every entry slot at once (one thread each), thread
-// 0 links the segments from the true entry slot, and the picks of the window
-// are written in parallel. The window ends early where a slot is -1 (the
-// predecessor is not a candidate: the whole workgroup then scans that bucket
-// for its pick) or past the staged entries (one step from global memory).
+// One workgroup of 1024 threads. A window of up to kWalkWindow buckets from
+// bucket k, entered at slot `slot`: every segment of kWalkSeg buckets is
+// followed from every entry slot at once (one thread each), then every group
+// of kWalkGroup segments from every entry slot (one thread each); thread 0
+// links the groups from the true entry slot, and the picks of the window are
+// written in parallel. The window ends early at the first bucket whose entry
+// slot is not staged: -1 (the predecessor is not a candidate: the whole
+// workgroup then scans that bucket for its pick) or past the staged ones (one
+// step from global memory).
 __global__ __launch_bounds__(1024) void k_lttb_table_walk(const int64_t *__restrict__ X, const float *__restrict__ Y,
                                                           int64_t n, int64_t B, const double *__restrict__ MX,
                                                           const double *__restrict__ MY,
@@ -901,10 +1016,13 @@ __global__ __launch_bounds__(1024) void k_lttb_table_walk(const int64_t *__restr
                                                           const int32_t *__restrict__ cand,
                                                           const int2 *__restrict__ tab, int64_t *__restrict__ out)
 {
-    constexpr int kSegs = kWalkWindow / kWalkSeg;
-    __shared__ int2 sT[kWalkWindow * kWalkSlots];
-    __shared__ uint8_t spath[kSegs][kWalkSlots][kWalkSeg]; // slot used at each bucket of the segment
-    __shared__ int32_t sdone[kSegs][kWalkSlots], sexit[kSegs][kWalkSlots], sent[kSegs];
+    constexpr int kSegs = kWalkWindow / kWalkSeg, kGroups = kSegs / kWalkGroup;
+    __shared__ uint8_t sN[kWalkWindow * kWalkSlots];        // next slot (kWalkOut: not staged)
+    __shared__ uint8_t spath[kSegs][kWalkSlots][kWalkSeg];  // slot at each bucket of a segment, per entry
+    __shared__ uint8_t sdone[kSegs][kWalkSlots], sexit[kSegs][kWalkSlots];
+    __shared__ uint8_t gpath[kGroups][kWalkSlots][kWalkGroup]; // entry slot of each segment of a group, per entry
+    __shared__ int16_t gdone[kGroups][kWalkSlots];          // buckets of the group walked from the tables
+    __shared__ uint8_t gexit[kGroups][kWalkSlots], gent[kGroups];
     __shared__ double s_area[16];
     __shared__ int64_t s_idx[16];
     __shared__ int64_t s_k, s_a;
@@ -918,50 +1036,66 @@ __global__ __launch_bounds__(1024) void k_lttb_table_walk(const int64_t *__restr
         if (slot >= 0 && slot < kWalkSlots) {
             const int64_t k1 = k + kWalkWindow < B ? k + kWalkWindow : B;
             const int W = (int)(k1 - k), nseg = (W + kWalkSeg - 1) / kWalkSeg;
-            for (int q = tid; q < W * kWalkSlots; q += blockDim.x)
-                sT[q] = tab[(k + q / kWalkSlots) * kCandMax + q % kWalkSlots];
+            const int ngrp = (nseg + kWalkGroup - 1) / kWalkGroup;
+            for (int q = tid; q < W * kWalkSlots; q += blockDim.x) {
+                const int32_t nx = tab[(k + q / kWalkSlots) * kCandMax + q % kWalkSlots].y;
+                sN[q] = nx >= 0 && nx < kWalkSlots ? (uint8_t)nx : kWalkOut;
+            }
             __syncthreads();
-            if (tid < nseg * kWalkSlots) { // segment g from entry slot e
-                const int g = tid / kWalkSlots, e = tid % kWalkSlots;
+            for (int q = tid; q < nseg * kWalkSlots; q += blockDim.x) { // segment g from entry slot e
+                const int g = q / kWalkSlots, e = q % kWalkSlots;
                 const int len = W - g * kWalkSeg < kWalkSeg ? W - g * kWalkSeg : kWalkSeg;
                 int sl = e, i = 0;
-                for (; i < len && sl >= 0 && sl < kWalkSlots; ++i) {
+                for (; i < len && sl != kWalkOut; ++i) {
                     spath[g][e][i] = (uint8_t)sl;
-                    sl = sT[(g * kWalkSeg + i) * kWalkSlots + sl].y;
+                    sl = sN[(g * kWalkSeg + i) * kWalkSlots + sl];
                 }
-                sdone[g][e] = i; // steps taken from the tables
-                sexit[g][e] = sl; // the slot after them
+                sdone[g][e] = (uint8_t)i; // buckets picked from the tables
+                sexit[g][e] = (uint8_t)sl; // the entry slot of the next segment
+            }
+            __syncthreads();
+            if (tid < ngrp * kWalkSlots) { // group G from entry slot e
+                const int G = tid / kWalkSlots, e = tid % kWalkSlots;
+                const int g0 = G * kWalkGroup, g1 = g0 + kWalkGroup < nseg ? g0 + kWalkGroup : nseg;
+                int cur = e, done = 0;
+                for (int g = g0; g < g1 && cur != kWalkOut; ++g) {
+                    const int len = W - g * kWalkSeg < kWalkSeg ? W - g * kWalkSeg : kWalkSeg;
+                    gpath[G][e][g - g0] = (uint8_t)cur;
+                    const int d = sdone[g][cur];
+                    done += d;
+                    cur = d < len ? kWalkOut : sexit[g][cur];
+                }
+                gdone[G][e] = (int16_t)done;
+                gexit[G][e] = (uint8_t)cur;
             }
             __syncthreads();
             if (tid == 0) {
                 int cur = slot;
                 int64_t stop = k1;
-                for (int g = 0; g < nseg; ++g) {
-                    sent[g] = cur;
-                    const int len = W - g * kWalkSeg < kWalkSeg ? W - g * kWalkSeg : kWalkSeg;
-                    const int done = sdone[g][cur];
-                    cur = sexit[g][cur];
-                    if (done < len) {
-                        stop = k + g * kWalkSeg + done;
-                        break;
-                    }
-                    if (cur < 0 || cur >= kWalkSlots) { // the next segment cannot start from the tables
-                        stop = k + (int64_t)g * kWalkSeg + len; // <= k1: the last segment may be short
+                for (int G = 0; G < ngrp; ++G) {
+                    gent[G] = (uint8_t)cur;
+                    const int glen = (G + 1) * kWalkGroup * kWalkSeg < W ? kWalkGroup * kWalkSeg : W - G * kWalkGroup * kWalkSeg;
+                    const int d = gdone[G][cur];
+                    cur = gexit[G][cur];
+                    if (d < glen || cur == kWalkOut) { // the tables end inside or right after this group
+                        stop = k + (int64_t)G * kWalkGroup * kWalkSeg + d;
                         break;
                     }
                 }
                 s_k = stop;
-                s_slot = cur;
             }
             __syncthreads();
             const int64_t stop = s_k; // k < stop <= k1 <= B
             for (int t = tid; t < (int)(stop - k); t += blockDim.x) { // the picks of buckets k .. stop-1
-                const int g = t / kWalkSeg, i = t % kWalkSeg;
-                const int sl = spath[g][sent[g]][i];
-                const int64_t pick = 1 + split_lo(bk, k + t) + sT[t * kWalkSlots + sl].x;
+                const int g = t / kWalkSeg, i = t % kWalkSeg, G = g / kWalkGroup;
+                const int sl = spath[g][gpath[G][gent[G]][g - G * kWalkGroup]][i];
+                const int2 te = tab[(k + t) * kCandMax + sl];
+                const int64_t pick = 1 + split_lo(bk, k + t) + te.x;
                 out[k + t + 1] = pick;
-                if (k + t + 1 == stop)
+                if (k + t + 1 == stop) { // the last pick of the window and the slot it leads to
                     s_a = pick;
+                    s_slot = te.y;
+                }
             }
             __syncthreads();
             k = stop;
