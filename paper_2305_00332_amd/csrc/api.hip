@@ -388,17 +388,19 @@ MinMaxGeom minmax_geom(int64_t len, int64_t nb)
 
 // The MinMax stream of one float32 series into its bin keys: one work item
 // per bin (or bin piece), or, for short bins, fixed chunks across bin ends.
-int enqueue_minmax_stream(const float *y, const MinMaxGeom &g, unsigned long long *keys, hipStream_t s)
+// `ticket` (optional): cleared on the way for a k_preselect_tail launch.
+int enqueue_minmax_stream(const float *y, const MinMaxGeom &g, unsigned long long *keys, hipStream_t s,
+                          unsigned int *ticket = nullptr)
 {
     const int64_t maxbin = g.bins.q + (g.bins.r ? 1 : 0);
     if (maxbin < kShortBin && g.bins.len >= kShortBinChunk * kFillItems) { // and at least 2048 chunks
-        MMLTTB_LAUNCH("init_keys", s, launch_init_keys(keys, g.bins.parts, s));
+        MMLTTB_LAUNCH("init_keys", s, launch_init_keys(keys, g.bins.parts, s, ticket));
         MMLTTB_LAUNCH("minmax_bin_reduce", s, launch_minmax_stream_chunks(y, g.bins, tuning().unroll, keys, s));
         return MMLTTB_OK;
     }
     if (keys_need_init(g))
-        MMLTTB_LAUNCH("init_keys", s, launch_init_keys(keys, g.bins.parts, s));
-    MMLTTB_LAUNCH("minmax_bin_reduce", s, launch_minmax_bin_reduce(y, g, tuning().unroll, keys, s));
+        MMLTTB_LAUNCH("init_keys", s, launch_init_keys(keys, g.bins.parts, s, ticket));
+    MMLTTB_LAUNCH("minmax_bin_reduce", s, launch_minmax_bin_reduce(y, g, tuning().unroll, keys, s, ticket));
     return MMLTTB_OK;
 }
 
@@ -1056,6 +1058,18 @@ int mmlttb_minmaxlttb(int xk, const int64_t *x, const float *y, int64_t n, int64
     } else {
         unsigned long long *keys = at<unsigned long long>(ws, L.keys);
         const MinMaxGeom g = minmax_geom(n - 2, nb);
+        const int64_t maxb_bound = (2 * nb + B - 1) / B;
+        if (use_segmented_chain(maxb_bound) && preselect_tail_fits(nb, maxb_bound)) {
+            // two launches: the stream (clearing the tail's ticket, kept in the slot of m) and the fused tail
+            unsigned int *ticket = at<unsigned int>(ws, L.m);
+            MMLTTB_TRY(enqueue_minmax_stream(y, g, keys, s, ticket));
+            const SegChainArgs a = seg_args(ws, L.path, L.finals, L.start, XP, YP, m, 0, B, MX, MY, maxb_bound);
+            MMLTTB_LAUNCH("preselect_tail", s,
+                          launch_preselect_tail(keys, g.bins, n, x, y, B, a.stage_cap, P, a.path, a.finals, a.start,
+                                                ticket, out_idx, s));
+            span.close();
+            return ok();
+        }
         MMLTTB_TRY(enqueue_minmax_stream(y, g, keys, s));
         if (nb <= kFusedCompactBins) { // one workgroup: compaction, then the means
             MMLTTB_LAUNCH("preselect_compact_means", s,

@@ -347,7 +347,7 @@ __global__ __launch_bounds__(kSegStarts) void k_batch_chain(BatchPtrs b)
     const Split bk = make_split(m - 2, g.B);
     seg_walk(b.XP + g.p0, b.YP + g.p0, bk, b.MX + g.b0, b.MY + g.b0, u - g.cw0, g.stage_cap,
              reinterpret_cast<unsigned char *>(lds),
-             b.path + (size_t)g.c0 * kSegStarts * kSegLen, b.finals + (size_t)g.c0 * kSegStarts);
+             b.path + (size_t)g.c0 * kSegStarts * kSegLen, b.finals + (size_t)g.c0 * kSegStarts, (int)threadIdx.x);
 }
 
 // Segmented chain, phases 2 and 3: one workgroup per series links its

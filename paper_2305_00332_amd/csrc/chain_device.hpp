@@ -178,43 +178,43 @@ template <class XT, class YT>
 __device__ inline void seg_walk(const XT *__restrict__ XP, const YT *__restrict__ YP, const Split &bk,
                                 const double *__restrict__ MX, const double *__restrict__ MY, int64_t s,
                                 int stage_cap, unsigned char *lds, uint8_t *__restrict__ path,
-                                uint8_t *__restrict__ finals)
+                                uint8_t *__restrict__ finals, int lane, bool active = true)
 {
-    const int lane = threadIdx.x;
+    // A wave with `active` false walks nothing but meets the same two
+    // workgroup barriers, so several waves of one workgroup can walk
+    // segments side by side in rounds.
     const int64_t B = bk.parts;
     const int64_t k0 = s * kSegLen, k1 = (k0 + kSegLen < B) ? k0 + kSegLen : B;
     const int nk = (int)(k1 - k0);
     SplitWalker w;
     w.init(bk, k0);
     const int64_t p0 = 1 + w.lo;
-    const int64_t p1 = 1 + split_lo(bk, k1);
     double *sx = reinterpret_cast<double *>(lds), *sy = sx + stage_cap, *smx = sy + stage_cap, *smy = smx + kSegLen;
     int32_t *sb = reinterpret_cast<int32_t *>(smy + kSegLen); // bucket starts relative to p0, nk + 1 of them
     uint8_t *T = reinterpret_cast<uint8_t *>(sb + kSegLen + 1); // point -> offset of its pick in the next bucket
-    for (int64_t p = p0 + lane; p < p1; p += kSegStarts) {
-        sx[p - p0] = (double)(XP ? XP[p] : p);
-        sy[p - p0] = (double)YP[p];
-    }
-    for (int64_t k = k0 + lane; k < k1; k += kSegStarts) {
-        smx[k - k0] = MX[k];
-        smy[k - k0] = MY[k];
-    }
-    if (lane == 0) {
-        SplitWalker v = w;
-        for (int i = 0; i <= nk; ++i) {
-            sb[i] = (int32_t)(1 + v.lo - p0);
-            v.advance(bk);
+    double ax0 = 0.0, ay0 = 0.0;
+    if (active) {
+        const int64_t p1 = 1 + split_lo(bk, k1);
+        for (int64_t p = p0 + lane; p < p1; p += kSegStarts) {
+            sx[p - p0] = (double)(XP ? XP[p] : p);
+            sy[p - p0] = (double)YP[p];
         }
+        for (int64_t k = k0 + lane; k < k1; k += kSegStarts) {
+            smx[k - k0] = MX[k];
+            smy[k - k0] = MY[k];
+        }
+        for (int i = lane; i <= nk; i += kSegStarts) // bucket starts, one per lane
+            sb[i] = (int32_t)(1 + split_lo(bk, k0 + i) - p0);
+        // start l: the l-th point of bucket k0 - 1 (the last one for lanes
+        // past its end), whose size is q, plus one when the step into k0 carried
+        int64_t apos = 0;
+        if (s > 0) {
+            const int64_t ca = bk.q + (w.rem < bk.r ? 1 : 0);
+            apos = p0 - ca + (lane < ca ? lane : ca - 1);
+        }
+        ax0 = (double)(XP ? XP[apos] : apos);
+        ay0 = (double)YP[apos];
     }
-    // start l: the l-th point of bucket k0 - 1 (the last one for lanes past
-    // its end), whose size is q, plus one when the step into k0 carried
-    int64_t apos = 0;
-    if (s > 0) {
-        const int64_t ca = bk.q + (w.rem < bk.r ? 1 : 0);
-        apos = p0 - ca + (lane < ca ? lane : ca - 1);
-    }
-    const double ax0 = (double)(XP ? XP[apos] : apos);
-    const double ay0 = (double)YP[apos];
     __syncthreads();
 
     // the bucket's first point stands unless an area beats -1 (areas are >= 0,
@@ -234,20 +234,25 @@ __device__ inline void seg_walk(const XT *__restrict__ XP, const YT *__restrict_
         }
         return bo;
     };
-    const int first = pick(ax0, ay0, 0);
-    const int tab_end = sb[nk - 1]; // points of buckets 0 .. nk-2
-    for (int r = lane; r < tab_end; r += kSegStarts) {
-        int lo = 0, hi = nk - 1; // bucket of r: the last i with sb[i] <= r
-        while (hi - lo > 1) {
-            const int mid = (lo + hi) >> 1;
-            if (sb[mid] <= r)
-                lo = mid;
-            else
-                hi = mid;
+    int first = 0;
+    if (active) {
+        first = pick(ax0, ay0, 0);
+        const int tab_end = sb[nk - 1]; // points of buckets 0 .. nk-2
+        for (int r = lane; r < tab_end; r += kSegStarts) {
+            int lo = 0, hi = nk - 1; // bucket of r: the last i with sb[i] <= r
+            while (hi - lo > 1) {
+                const int mid = (lo + hi) >> 1;
+                if (sb[mid] <= r)
+                    lo = mid;
+                else
+                    hi = mid;
+            }
+            T[r] = (uint8_t)pick(sx[r], sy[r], lo + 1);
         }
-        T[r] = (uint8_t)pick(sx[r], sy[r], lo + 1);
     }
     __syncthreads();
+    if (!active)
+        return;
 
     uint32_t words[kSegLen / 4];
 #pragma unroll
@@ -271,8 +276,8 @@ __device__ inline void seg_walk(const XT *__restrict__ XP, const YT *__restrict_
 // Phase 2: follow the true start through the segments. The start of segment
 // t+1 is the last pick of segment t walked from its own start: one LDS lookup
 // per segment, by thread 0, with the finals staged in LDS windows of
-// kChaseWindow segments by the whole workgroup. Runs in a later kernel than
-// the walks, so their finals are visible without any fence. The starts go to
+// kChaseWindow segments by the whole workgroup. Runs after the walks, in a
+// later kernel or after a workgroup barrier that follows them. The starts go to
 // `start` (global) and are visible to the whole workgroup on return.
 __device__ inline void seg_link(const uint8_t *finals, uint8_t *start, int64_t S, uint8_t *F)
 {

@@ -179,9 +179,10 @@ inline size_t seg_start_bytes(int64_t B)
 inline size_t seg_path_bytes(int64_t B) { return (size_t)seg_count(B) * kSegStarts * kSegLen; }
 inline size_t seg_finals_bytes(int64_t B) { return (size_t)seg_count(B) * kSegStarts; }
 
-hipError_t launch_init_keys(unsigned long long *keys, int64_t nb, hipStream_t s);
+// `ticket` (optional): cleared for a k_preselect_tail launch that follows.
+hipError_t launch_init_keys(unsigned long long *keys, int64_t nb, hipStream_t s, unsigned int *ticket = nullptr);
 hipError_t launch_minmax_bin_reduce(const float *y, const MinMaxGeom &g, int unroll, unsigned long long *keys,
-                                    hipStream_t s);
+                                    hipStream_t s, unsigned int *ticket = nullptr);
 // Bins per workgroup of the tiled compaction (1024 threads, 4 slabs), and the
 // bin count above which it replaces the one-workgroup compaction: that one
 // walks every bin in rounds of 4096 (nb = 32768: 105 us with the means).
@@ -193,6 +194,16 @@ hipError_t launch_compact_tiled(const unsigned long long *keys, const Split &bin
                                 hipStream_t s);
 hipError_t launch_preselect_compact(const unsigned long long *keys, const Split &bins, int64_t n, const int64_t *x,
                                     const float *y, int64_t *P, int64_t *XP, float *YP, int64_t *m_out, hipStream_t s);
+// The fused tail (compaction, means, segmented chain, output): one
+// workgroup of kTailThreads per chain segment, for at most kTailBins bins and
+// segments whose points (with the bucket before and after) fit kTailPts.
+constexpr int kTailThreads = 256;
+constexpr int kTailBins = 3840; // keys staged in at most 64 KiB of dynamic LDS
+constexpr int kTailPts = 640;
+bool preselect_tail_fits(int64_t nb, int64_t maxb_bound);
+hipError_t launch_preselect_tail(const unsigned long long *keys, const Split &bins, int64_t n, const int64_t *x,
+                                 const float *y, int64_t B, int stage_cap, int64_t *P, uint8_t *path, uint8_t *finals,
+                                 uint8_t *start, unsigned int *ticket, int64_t *out, hipStream_t s);
 hipError_t launch_preselect_compact_means(const unsigned long long *keys, const Split &bins, int64_t n,
                                           const int64_t *x, const float *y, int64_t *P, int64_t *XP, float *YP,
                                           int64_t *m_out, int64_t B, double *MX, double *MY, hipStream_t s);

@@ -270,7 +270,7 @@ __global__ __launch_bounds__(kSegStarts) void k_lttb_chain_seg(Args a)
     const int64_t m = a.m_ptr ? *a.m_ptr : a.m_const;
     const Split bk = make_split(m - 2, a.B);
     seg_walk(a.XP, a.YP, bk, a.MX, a.MY, (int64_t)blockIdx.x, a.stage_cap, reinterpret_cast<unsigned char *>(lds), a.path,
-             a.finals);
+             a.finals, (int)threadIdx.x);
 }
 
 // Two-level link, step 1: chunk c's composed map, lane l following start

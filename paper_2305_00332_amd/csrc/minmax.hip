@@ -24,8 +24,11 @@
 
 namespace mmlttb {
 
-__global__ __launch_bounds__(256) void k_init_keys(unsigned long long *__restrict__ keys, int64_t nb)
+__global__ __launch_bounds__(256) void k_init_keys(unsigned long long *__restrict__ keys, int64_t nb,
+                                                   unsigned int *__restrict__ ticket)
 {
+    if (ticket && blockIdx.x == 0 && threadIdx.x == 0) // for the tail kernel that follows
+        *ticket = 0u;
     int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; b < nb; b += stride) {
         keys[2 * b] = ~0ull;
@@ -35,8 +38,11 @@ __global__ __launch_bounds__(256) void k_init_keys(unsigned long long *__restric
 
 template <int U>
 __global__ __launch_bounds__(256) void k_minmax_bin_reduce(const float *__restrict__ y, MinMaxGeom g,
-                                                           unsigned long long *__restrict__ keys)
+                                                           unsigned long long *__restrict__ keys,
+                                                           unsigned int *__restrict__ ticket)
 {
+    if (ticket && blockIdx.x == 0 && threadIdx.x == 0) // for the tail kernel that follows
+        *ticket = 0u;
     const int lane = threadIdx.x & (kWave - 1);
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
     const int64_t waves = (int64_t)gridDim.x * (blockDim.x / kWave);
@@ -117,6 +123,134 @@ __global__ __launch_bounds__(1024) void k_preselect_compact_means(
         bucket_mean_one(XP, YP, bk, m, k, MX[k], MY[k]);
 }
 
+// The whole tail of a small preselection, one workgroup per chain segment
+// (buckets [g*kSegLen, (g+1)*kSegLen)), two launches per call in all: every
+// workgroup counts the points each bin keeps (the same decoding as the
+// compaction) into per-bin start slots in LDS, so it knows m and every
+// bucket's place in P; it decodes just the points its segment reads (the
+// bucket before it for the start points, its own buckets, the one after for
+// the last mean), takes the next-bucket means and walks its segment as
+// k_lttb_chain_seg does (section 2.2.1, LTTB). It stores the original index of
+// its own buckets' points in P; the last workgroup to finish (a device-scope
+// ticket, cleared by the stream kernel before this launch) links the segments
+// and writes every pick.
+__global__ __launch_bounds__(kTailThreads) void k_preselect_tail(
+    const unsigned long long *__restrict__ keys, Split bins, int64_t n, const int64_t *__restrict__ x,
+    const float *__restrict__ y, int64_t B, int stage_cap, int64_t *__restrict__ P, uint8_t *__restrict__ path,
+    uint8_t *__restrict__ finals, uint8_t *__restrict__ start, unsigned int *__restrict__ ticket,
+    int64_t *__restrict__ out)
+{
+    __shared__ int32_t cum[kTailBins + 1]; // points kept by the bins before bin b
+    __shared__ int64_t sxv[kTailPts];
+    __shared__ float syv[kTailPts];
+    __shared__ double smx[kSegLen], smy[kSegLen];
+    __shared__ int wave_tot[17];
+    __shared__ int s_last;
+    // dynamic LDS: the bins' keys (bin b at b + b/16, one pad entry per 16
+    // bins), then the segment walk's area, then the link's window
+    extern __shared__ double dyn_lds[];
+    unsigned char *dyn = reinterpret_cast<unsigned char *>(dyn_lds);
+    ulonglong2 *skeys = reinterpret_cast<ulonglong2 *>(dyn_lds);
+    const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
+    const int64_t nb = bins.parts;
+    const ulonglong2 *keys2 = reinterpret_cast<const ulonglong2 *>(keys);
+    for (int64_t b = tid; b < nb; b += kTailThreads)
+        skeys[b + (b >> 4)] = keys2[b];
+    __syncthreads();
+    constexpr int kPer = (kTailBins + kTailThreads - 1) / kTailThreads;
+    int c[kPer], own = 0;
+    {
+        const int64_t b0 = (int64_t)tid * kPer;
+        SplitWalker bw; // this thread's consecutive bins, one division in all
+        bw.init(bins, b0 < nb ? b0 : nb);
+#pragma unroll
+        for (int u = 0; u < kPer; ++u) {
+            const int64_t b = b0 + u;
+            c[u] = 0;
+            if (b < nb) {
+                const int64_t blo = bw.lo, len = bw.next_lo(bins) - blo;
+                const ulonglong2 kk = skeys[b + (b >> 4)];
+                int64_t i0, i1;
+                float v0, v1;
+                c[u] = decode_bin(kk.x, kk.y, blo, len, i0, i1, v0, v1);
+                bw.advance(bins);
+            }
+            own += c[u];
+        }
+    }
+    int total;
+    int run = block_exclusive_scan(own, wave_tot, total);
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+        const int64_t b = (int64_t)tid * kPer + u;
+        if (b < nb)
+            cum[b] = run;
+        run += c[u];
+    }
+    if (tid == 0)
+        cum[nb] = total;
+    __syncthreads();
+    const int64_t m = (int64_t)total + 2;
+    const Split bk = make_split(m - 2, B);
+    const int64_t g = blockIdx.x, k0 = g * kSegLen, k1 = (k0 + kSegLen < B) ? k0 + kSegLen : B;
+    const int64_t pa = k0 == 0 ? 0 : 1 + split_lo(bk, k0 - 1);
+    const int64_t pb = k1 < B ? 1 + split_lo(bk, k1 + 1) : m;
+    const int64_t own0 = 1 + split_lo(bk, k0), own1 = 1 + split_lo(bk, k1);
+    for (int64_t p = pa + tid; p < pb; p += kTailThreads) {
+        int64_t idx;
+        float yv;
+        if (p == 0 || p == m - 1) {
+            idx = p == 0 ? 0 : n - 1;
+            yv = y[idx];
+        } else {
+            const int32_t q = (int32_t)(p - 1);
+            int lo = 0, hi = (int)nb; // the bin of kept point q: the last b with cum[b] <= q
+            while (hi - lo > 1) {
+                const int mid = (lo + hi) >> 1;
+                if (cum[mid] <= q)
+                    lo = mid;
+                else
+                    hi = mid;
+            }
+            const int64_t blo = split_lo(bins, lo), len = split_lo(bins, lo + 1) - blo;
+            const ulonglong2 kk = skeys[lo + (lo >> 4)];
+            int64_t i0, i1;
+            float v0, v1;
+            (void)decode_bin(kk.x, kk.y, blo, len, i0, i1, v0, v1);
+            const bool second = q > cum[lo];
+            idx = second ? i1 : i0;
+            yv = second ? v1 : v0;
+        }
+        sxv[p - pa] = x ? x[idx] : idx;
+        syv[p - pa] = yv;
+        if (p >= own0 && p < own1)
+            P[p] = idx;
+    }
+    __syncthreads();
+    const int64_t *XPl = sxv - pa; // indexed by position in P
+    const float *YPl = syv - pa;
+    for (int64_t k = k0 + tid; k < k1; k += kTailThreads)
+        bucket_mean_one(XPl, YPl, bk, m, k, smx[k - k0], smy[k - k0]);
+    __syncthreads();
+    seg_walk(XPl, YPl, bk, smx - k0, smy - k0, g, stage_cap, dyn, path, finals, lane, wave == 0);
+    __threadfence(); // this segment's path, finals and P before the ticket
+    __syncthreads();
+    if (tid == 0)
+        s_last = atomicAdd(ticket, 1u) == gridDim.x - 1;
+    __syncthreads();
+    if (!s_last)
+        return;
+    __threadfence(); // every other segment's writes after the ticket
+    const int64_t S = gridDim.x;
+    seg_link(finals, start, S, dyn);
+    for (int64_t k = tid; k < B; k += kTailThreads)
+        out[k + 1] = P[seg_pick(path, start, bk, k)];
+    if (tid == 0) {
+        out[0] = 0;
+        out[B + 1] = n - 1;
+    }
+}
+
 // Tiled compaction, for many bins: tile t is bins [t*kCompactTileBins,
 // (t+1)*kCompactTileBins), one workgroup of 1024 threads (one round of
 // compact_bin_range) each. Three launches: the tiles' point counts; one
@@ -178,32 +312,32 @@ __global__ __launch_bounds__(1024) void k_compact_tiles(const unsigned long long
 
 // ---------------------------------------------------------------- launches
 
-hipError_t launch_init_keys(unsigned long long *keys, int64_t nb, hipStream_t s)
+hipError_t launch_init_keys(unsigned long long *keys, int64_t nb, hipStream_t s, unsigned int *ticket)
 {
     int64_t blocks = (nb + 255) / 256;
     blocks = blocks < 1 ? 1 : (blocks > 4096 ? 4096 : blocks);
-    hipLaunchKernelGGL(k_init_keys, dim3((unsigned)blocks), dim3(256), 0, s, keys, nb);
+    hipLaunchKernelGGL(k_init_keys, dim3((unsigned)blocks), dim3(256), 0, s, keys, nb, ticket);
     return hipGetLastError();
 }
 
 hipError_t launch_minmax_bin_reduce(const float *y, const MinMaxGeom &g, int unroll, unsigned long long *keys,
-                                    hipStream_t s)
+                                    hipStream_t s, unsigned int *ticket)
 {
     const int64_t blocks = stream_blocks(g);
     if (blocks > 0x7fffffff)
         return hipErrorInvalidConfiguration;
     switch (unroll) {
     case 1:
-        hipLaunchKernelGGL(k_minmax_bin_reduce<1>, dim3((unsigned)blocks), dim3(256), 0, s, y, g, keys);
+        hipLaunchKernelGGL(k_minmax_bin_reduce<1>, dim3((unsigned)blocks), dim3(256), 0, s, y, g, keys, ticket);
         break;
     case 2:
-        hipLaunchKernelGGL(k_minmax_bin_reduce<2>, dim3((unsigned)blocks), dim3(256), 0, s, y, g, keys);
+        hipLaunchKernelGGL(k_minmax_bin_reduce<2>, dim3((unsigned)blocks), dim3(256), 0, s, y, g, keys, ticket);
         break;
     case 8:
-        hipLaunchKernelGGL(k_minmax_bin_reduce<8>, dim3((unsigned)blocks), dim3(256), 0, s, y, g, keys);
+        hipLaunchKernelGGL(k_minmax_bin_reduce<8>, dim3((unsigned)blocks), dim3(256), 0, s, y, g, keys, ticket);
         break;
     default:
-        hipLaunchKernelGGL(k_minmax_bin_reduce<4>, dim3((unsigned)blocks), dim3(256), 0, s, y, g, keys);
+        hipLaunchKernelGGL(k_minmax_bin_reduce<4>, dim3((unsigned)blocks), dim3(256), 0, s, y, g, keys, ticket);
         break;
     }
     return hipGetLastError();
@@ -243,6 +377,28 @@ hipError_t launch_preselect_compact_means(const unsigned long long *keys, const 
 {
     hipLaunchKernelGGL(k_preselect_compact_means, dim3(1), dim3(1024), 0, s, keys, bins, n, x, y, P, XP, YP, m_out, B,
                        MX, MY);
+    return hipGetLastError();
+}
+
+bool preselect_tail_fits(int64_t nb, int64_t maxb_bound)
+{
+    return nb <= kTailBins && (kSegLen + 2) * maxb_bound + 2 <= kTailPts;
+}
+
+hipError_t launch_preselect_tail(const unsigned long long *keys, const Split &bins, int64_t n, const int64_t *x,
+                                 const float *y, int64_t B, int stage_cap, int64_t *P, uint8_t *path, uint8_t *finals,
+                                 uint8_t *start, unsigned int *ticket, int64_t *out, hipStream_t s)
+{
+    const int64_t S = (B + kSegLen - 1) / kSegLen;
+    if (S > 0x7fffffff)
+        return hipErrorInvalidConfiguration;
+    const int64_t nb = bins.parts;
+    const size_t keyb = (size_t)(nb + nb / 16 + 1) * 16, walk = seg_walk_lds_bytes(stage_cap),
+                 link = (size_t)kChaseWindow * kSegStarts;
+    size_t lds = keyb > walk ? keyb : walk;
+    lds = lds > link ? lds : link;
+    hipLaunchKernelGGL(k_preselect_tail, dim3((unsigned)S), dim3(kTailThreads), lds, s, keys,
+                       bins, n, x, y, B, stage_cap, P, path, finals, start, ticket, out);
     return hipGetLastError();
 }
 

@@ -186,7 +186,8 @@ def test_profile_call_spans_cover_their_kernels():
     """Each successful call leaves one whole-call span, at least as long as the
     kernels launched inside it; a call rejected on the host leaves none."""
     y = _dev(_series("walk", 2_000_001, 5))
-    names = ("init_keys", "minmax_bin_reduce", "preselect_compact_means", "lttb_chain_seg", "lttb_chain")
+    names = ("init_keys", "minmax_bin_reduce", "preselect_tail", "preselect_compact_means", "lttb_chain_seg",
+             "lttb_chain")
     ops.minmaxlttb(y, 1000, 4)
     torch.cuda.synchronize()
     ops.profile_enable(True)
