@@ -133,6 +133,8 @@ def main():
     ap.add_argument("--serve-min-requests", type=int, default=2000)
     ap.add_argument("--serve-arena", type=int, default=1 << 30, help="device arena bytes of each serving form")
     ap.add_argument("--serve-oracle-sample", type=int, default=256)
+    ap.add_argument("--serve-chunks", type=int, default=4,
+                    help="each rate's stream in this many consecutive chunks, both forms on each, order alternating")
     ap.add_argument("--burst", type=int, default=2000)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (the reference kernel for HBM counter scaling)")
@@ -859,6 +861,11 @@ def bench_batched(args):
     torch.cuda.synchronize()
     ops.profile_enable(False)
     plain_spans = ops.profile_samples("call_minmaxlttb")
+    # the plain form's kernels alone: the sum of every launch's own event-timed
+    # duration (no host gaps inside or between calls)
+    plain_kernel_ms = sum(ops.profile_read(k)[0] for k in (
+        "iota", "init_keys", "minmax_bin_reduce", "preselect_tail", "preselect_all", "preselect_compact_means",
+        "preselect_compact", "bucket_mean", "lttb_chain", "lttb_chain_seg"))
     pts = int(lengths.sum())
     res = {"workload": f"{count} series, lengths log-uniform in [1e3, 1e7] (seed 4), float32 random walk + "
                        f"N(0, 0.5^2), int64 irregular x; n_out in {{200, 500, 1000, 2000}}, r_ps=4",
@@ -866,8 +873,11 @@ def bench_batched(args):
            "plain_ms": round(t_plain * 1e3, 4), "plain_gpts_per_s": round(pts / t_plain / 1e9, 3),
            "speedup_vs_plain": round(t_plain / t_batched, 3),
            "plain_device_ms": round(float(sum(plain_spans)), 4) if len(plain_spans) == len(segs) else None,
-           "speedup_vs_plain_device": (round(float(sum(plain_spans)) / (t_batched * 1e3), 3)
-                                       if len(plain_spans) == len(segs) else None),
+           "plain_device_ms_note": "summed call spans, with every launch bracketed by timing events (the host's "
+                                   "launch gaps inside a call included)",
+           "plain_kernel_ms": round(plain_kernel_ms, 4),
+           "plain_kernel_ms_note": "sum of every launch's event-timed duration (the events add a few us per launch)",
+           "speedup_vs_plain_kernels": round(plain_kernel_ms / (t_batched * 1e3), 3),
            "kernel_ms": kern,
            "tuning": ops.get_tuning()._asdict(),
            "graph_replay_ms": round(t_graph * 1e3, 4), "graph_stats": list(graph_stats),
@@ -965,17 +975,50 @@ def bench_served(args):
         return ra.keys() == rb.keys() and all(
             ra[k].error is None and rb[k].error is None and np.array_equal(ra[k].result, rb[k].result) for k in ra)
 
+    def combine(parts):
+        """One summary of a form's runs over consecutive chunks of a stream."""
+        done = [r for _, d in parts for r in d]
+        ok = [r for r in done if r.error is None]
+        lat = np.array([r.latency for r in ok], dtype=np.float64) * 1e3
+        span = sum(sm["span_s"] for sm, _ in parts)
+        steps = sum(sm["steps"] for sm, _ in parts)
+        out = {"requests": len(ok), "errors": len(done) - len(ok)}
+        if lat.size:
+            out.update({"p50_ms": round(float(np.percentile(lat, 50)), 4),
+                        "p99_ms": round(float(np.percentile(lat, 99)), 4),
+                        "mean_ms": round(float(lat.mean()), 4),
+                        "gpts_per_s": round(sum(r.n for r in ok) / max(span, 1e-9) / 1e9, 3)})
+        out.update({"span_s": round(span, 4),
+                    "busy_frac": round(sum(sm["busy_frac"] * sm["span_s"] for sm, _ in parts) / max(span, 1e-9), 4),
+                    "steps": steps, "mean_batch": round(len(done) / max(steps, 1), 2),
+                    "max_in_flight": max(sm["max_in_flight"] for sm, _ in parts),
+                    "max_device_bytes": max(sm["max_device_bytes"] for sm, _ in parts)})
+        return out, done
+
     per_rate = {}
     identical = True
+    chunks = max(1, args.serve_chunks)
     for rate in rates:
         n_req = max(args.serve_min_requests, int(rate * args.serve_seconds))
         reqs = poisson_requests(rate, n_req, lengths, seed=50 + int(rate))
         warm = poisson_requests(rate, 50, lengths, seed=7)
-        entry, results = {}, {}
         for name in forms:
             serve(name, warm)
-            log(f"served: rate {rate:g}/s, {n_req} requests, {name}")
-            entry[name], results[name] = serve(name, reqs)
+        # the stream in consecutive chunks, each served by both forms in
+        # alternating order, so drift in the machine's state falls on both
+        runs = {name: [] for name in forms}
+        for c, idx in enumerate(np.array_split(np.arange(n_req), chunks)):
+            if idx.size == 0:
+                continue
+            t0 = reqs[idx[0]].arrival
+            sub = [type(r)(r.rid, r.series, r.lo, r.hi, r.n_out, r.r_ps, r.arrival - t0) for r in (reqs[i] for i in idx)]
+            for name in (list(forms) if c % 2 == 0 else list(forms)[::-1]):
+                log(f"served: rate {rate:g}/s, chunk {c + 1}/{chunks} ({idx.size} requests), {name}")
+                runs[name].append(serve(name, sub))
+        entry, results = {}, {}
+        for name in forms:
+            entry[name], results[name] = combine(runs[name])
+        entry["interleaved_chunks"] = chunks
         identical = identical and same(results["batched"], results["plain"])
         b, p = entry["batched"], entry["plain"]
         entry["p99_ratio_plain_over_batched"] = round(p["p99_ms"] / b["p99_ms"], 3) if b.get("p99_ms") else None

@@ -297,13 +297,15 @@ int mmlttb_m4(const float *y, int64_t n, int64_t n_out, int64_t *out_idx, int64_
 int mmlttb_everynth(int64_t n, int64_t n_out, int64_t *out_idx, void *stream);
 
 /* Graph replay of batched calls. With max_graphs > 0, a batched call on a
- * non-default stream is captured into a HIP graph (segment-table upload from
- * a pinned host copy plus every kernel) the first time its exact arguments are
- * seen (pointers, stream, x kind, tuning, segment table), and replayed by
- * later calls with the same arguments; at most max_graphs graphs are kept
- * (least recently used evicted, after its last replay completes). The cache
- * holds pinned HOST memory only. 0 (the default) disables it and releases
- * every graph. Process-wide; not thread-safe with concurrent calls.
+ * non-default stream is captured into a HIP graph (every kernel, reading the
+ * header and segment table from a device copy that the cache allocates and
+ * fills once at capture) the first time its exact arguments are seen
+ * (pointers, stream, x kind, tuning, segment table), and replayed by later
+ * calls with the same arguments; at most max_graphs graphs are kept (least
+ * recently used evicted, after its last replay completes). The cache holds
+ * one device table copy (about 12 KB plus 184 bytes per segment) per graph.
+ * 0 (the default) disables it and releases every graph. Process-wide; not
+ * thread-safe with concurrent calls.
  * mmlttb_graph_cache_stats reports entries held, replays and captures since
  * the cache was last disabled. */
 int mmlttb_set_graph_cache(int max_graphs);

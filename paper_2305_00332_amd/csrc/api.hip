@@ -755,14 +755,16 @@ void fill_table(char *dst, const BatchPlan &plan)
 }
 
 // Enqueue the batched kernels; the header and segment table are already
-// (being) copied into ws on stream s.
+// (being) copied into ws on stream s, or, when `table` is given, held there
+// (device memory laid out as the start of ws).
 int enqueue_batch(const BatchPlan &plan, int xk, const int64_t *x_base, const float *y_base, int64_t *out_idx_base,
-                  void *ws, hipStream_t s)
+                  void *ws, hipStream_t s, const void *table = nullptr)
 {
     const BatchHeader &h = plan.h;
     BatchPtrs b;
-    b.hdr = at<BatchHeader>(ws, 0);
-    b.segs = at<BatchSeg>(ws, h.off_segs);
+    const void *tb = table ? table : ws;
+    b.hdr = at<BatchHeader>(const_cast<void *>(tb), 0);
+    b.segs = at<BatchSeg>(const_cast<void *>(tb), h.off_segs);
     b.n_segs = h.n_segs;
     b.xk = xk;
     b.x_base = x_base;
@@ -813,7 +815,7 @@ struct GraphEntry {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     hipEvent_t done = nullptr; // recorded after the entry's latest launch
-    void *pinned = nullptr;    // header + segment table, source of the upload node
+    void *table = nullptr;     // device copy of the header + segment table the captured kernels read
     uint64_t last_use = 0;
 };
 
@@ -863,15 +865,15 @@ GraphEntry *graph_find(uint64_t hash, const std::vector<char> &key)
 void graph_release(GraphEntry &e)
 {
     if (e.done)
-        (void)hipEventSynchronize(e.done); // its last replay no longer reads the pinned table
+        (void)hipEventSynchronize(e.done); // its last replay no longer reads the table
     if (e.exec)
         (void)hipGraphExecDestroy(e.exec);
     if (e.graph)
         (void)hipGraphDestroy(e.graph);
     if (e.done)
         (void)hipEventDestroy(e.done);
-    if (e.pinned)
-        (void)hipHostFree(e.pinned);
+    if (e.table)
+        (void)hipFree(e.table);
 }
 
 void graph_evict_oldest()
@@ -1426,26 +1428,35 @@ int mmlttb_minmaxlttb_batched(int xk, const int64_t *x_base, const float *y_base
         rc = enqueue_batch(plan, xk, x_base, y_base, out_idx_base, ws, s);
         return rc ? rc : ok();
     }
-    // capture: table upload from a pinned copy owned by the graph entry, then the kernels
+    // capture: the kernels alone, reading the header and segment table from a
+    // device copy owned by the graph entry (no upload node, so a replay does
+    // not depend on what the workspace holds)
     GraphEntry ge;
     ge.hash = hash;
     ge.key = std::move(key);
-    if (hipHostMalloc(&ge.pinned, table_bytes, hipHostMallocDefault) != hipSuccess)
-        return fail(MMLTTB_EDEVICE, "pinned table allocation failed");
-    fill_table(static_cast<char *>(ge.pinned), plan);
+    {
+        std::vector<char> staging(table_bytes);
+        fill_table(staging.data(), plan);
+        if (hipMalloc(&ge.table, table_bytes) != hipSuccess) {
+            ge.table = nullptr;
+            return fail(MMLTTB_EDEVICE, "graph table allocation failed");
+        }
+        if (hipMemcpy(ge.table, staging.data(), table_bytes, hipMemcpyHostToDevice) != hipSuccess) {
+            (void)hipFree(ge.table);
+            return fail(MMLTTB_EDEVICE, "graph table copy failed");
+        }
+    }
     const bool prof = g_prof;
     g_prof = false; // no timing events inside a capture
     hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(ws, ge.pinned, table_bytes, hipMemcpyHostToDevice, s);
-    rc = (e == hipSuccess) ? enqueue_batch(plan, xk, x_base, y_base, out_idx_base, ws, s) : MMLTTB_EDEVICE;
+    rc = (e == hipSuccess) ? enqueue_batch(plan, xk, x_base, y_base, out_idx_base, ws, s, ge.table) : MMLTTB_EDEVICE;
     hipGraph_t graph = nullptr;
     hipError_t ec = hipStreamEndCapture(s, &graph);
     g_prof = prof;
     if (e != hipSuccess || rc != MMLTTB_OK || ec != hipSuccess || !graph) {
         if (graph)
             (void)hipGraphDestroy(graph);
-        (void)hipHostFree(ge.pinned);
+        (void)hipFree(ge.table);
         return fail(MMLTTB_EDEVICE, "graph capture failed: %s", hipGetErrorString(e != hipSuccess ? e : ec));
     }
     ge.graph = graph;
@@ -1454,7 +1465,7 @@ int mmlttb_minmaxlttb_batched(int xk, const int64_t *x_base, const float *y_base
         e = hipEventCreateWithFlags(&ge.done, hipEventDisableTiming);
     if (e != hipSuccess) {
         (void)hipGraphDestroy(graph);
-        (void)hipHostFree(ge.pinned);
+        (void)hipFree(ge.table);
         return fail(MMLTTB_EDEVICE, "graph instantiation failed: %s", hipGetErrorString(e));
     }
     e = hipGraphLaunch(ge.exec, s);

@@ -60,6 +60,40 @@ def test_replays_equal_eager_with_eager_work_between():
     assert captures == 1 and hits == 5 and entries == 1
 
 
+@pytest.mark.parametrize("fill", [0x00, 0xFF, 0x5A])
+def test_replay_does_not_read_the_table_from_the_workspace(fill):
+    """The captured kernels read the header and segment table from the
+    graph's own device copy: a replay after the workspace was overwritten
+    (bytes, or another batch's eager call in the same workspace) still equals
+    the eager result of its own batch."""
+    x, y, segs = _batch(11, 24, 200_000)
+    x2, y2, segs2 = _batch(12, 9, 150_000)
+    ref, _ = _eager(y, segs, x)
+    ref2, _ = _eager(y2, segs2, x2)
+    stream = torch.cuda.Stream()
+    nbytes = max(ops.batched_workspace_size(segs), ops.batched_workspace_size(segs2))
+    ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    out = torch.empty_like(ref)
+    table = ops.segment_table(segs)
+    ops.set_graph_cache(4)
+    for i in range(4):
+        if i > 0:
+            ws.fill_(fill)
+        if i == 2:  # another batch, eager on the default stream, in the same workspace
+            out2 = torch.empty_like(ref2)
+            ops.minmaxlttb_batched(y2, segs2, x_base=x2, out=out2, ws=ws)
+            torch.cuda.synchronize()
+            assert torch.equal(out2, ref2)
+        torch.cuda.synchronize()
+        with torch.cuda.stream(stream):
+            out.fill_(-1)
+            ops.minmaxlttb_batched(y, segs, x_base=x, out=out, ws=ws, table=table)  # capture, then replays
+        stream.synchronize()
+        assert torch.equal(out, ref), f"call {i}"
+    entries, hits, captures = ops.graph_cache_stats()
+    assert captures == 1 and hits == 3
+
+
 def test_replay_reads_current_data():
     x, y, segs = _batch(4, 20, 100_000)
     stream = torch.cuda.Stream()
