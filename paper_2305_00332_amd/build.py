@@ -22,7 +22,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libmmlttb.so")
 
-SOURCES = ["minmax.hip", "lttb.hip", "lttb_tables.hip", "batched.hip", "downsamplers.hip", "xbins.hip", "typed.hip", "simplify.hip", "api.hip", "noalloc.hip"]
+SOURCES = ["minmax.hip", "lttb.hip", "lttb_tables.hip", "batched.hip", "downsamplers.hip", "xbins.hip", "typed.hip", "simplify.hip", "host.hip", "api.hip", "api_batched.hip", "noalloc.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
