@@ -200,6 +200,9 @@ __device__ inline void lttb_scan_body(const int64_t *__restrict__ X, const float
     int64_t a0 = s + (int64_t)(((16u - (unsigned)(ya & 15u)) & 15u) >> 2);
     a0 = a0 < e ? a0 : e;
     const int64_t nq = (e - a0) >> 2, nchunks = (nq + 63) >> 6;
+    // slabs: a chunk each, merged evenly when there are more than kSlabs;
+    // with at most kSlabs / 4 chunks, a 64-point row (16 lanes) of a chunk each
+    const bool fine = nchunks * 4 <= kSlabs;
     auto slab_of = [&](int64_t c) { return (int)(nchunks <= kSlabs ? c : (c * kSlabs) / nchunks); };
     float vmax = -kInf, vmin = kInf;
     uint32_t omax = 0, omin = 0;
@@ -238,7 +241,21 @@ __device__ inline void lttb_scan_body(const int64_t *__restrict__ X, const float
             take(p0 + 2, xh.x, yv.z);
             take(p0 + 3, xh.y, yv.w);
         },
-        [&](int64_t c) { flush(true, slab_of(c)); });
+        [&](int64_t c) {
+            if (!fine) {
+                flush(true, slab_of(c));
+                return;
+            }
+            unsigned long long ku = vmax > -kInf ? high_key(vmax, omax) : 0ull;
+            unsigned long long kd = vmin < kInf ? low_key(vmin, omin) : ~0ull;
+            group_minmax(16, kd, ku); // each 16-lane row: one slab
+            if ((lane & 15) == 0) {
+                atomicMax(&s_up[4 * c + (lane >> 4)], ku);
+                atomicMin(&s_dn[4 * c + (lane >> 4)], kd);
+            }
+            vmax = -kInf;
+            vmin = kInf;
+        });
     if (fy.exact()) {
         sy.add_exact_f64(fy.acc);
     } else { // values too far apart in scale: this lane's groups again, exactly
@@ -266,7 +283,7 @@ __device__ inline void lttb_scan_body(const int64_t *__restrict__ X, const float
             vmin = y;
             omin = o;
         }
-        flush(false, head || nchunks == 0 ? 0 : slab_of(nchunks - 1));
+        flush(false, head || nchunks == 0 ? 0 : (fine ? (int)((nq - 1) >> 4) : slab_of(nchunks - 1)));
     }
     __syncthreads();
     for (int i = tid; i < kSlabs; i += blockDim.x) {
@@ -400,10 +417,12 @@ __device__ inline bool chain_drop(double ax, double ay, double bx, double by, do
 
 // Points [lo, hi) of slab i of bucket [s, e), as the first pass filled it:
 // chunks of 256 points from a0 (the first point at a 16-byte boundary of Y)
-// to t0, merged evenly into kSlabs slabs when there are more; the points
-// before a0 belong to slab 0, those from t0 on to the last chunk's slab.
+// to t0, merged evenly into kSlabs slabs when there are more, or split into
+// their 64-point rows when there are at most kSlabs / 4; the points before a0
+// belong to slab 0, those from t0 on to the slab of the last group.
 struct SlabMap {
-    int64_t s, e, a0, t0, nchunks;
+    int64_t s, e, a0, t0, nq, nchunks;
+    bool fine;
     __device__ void init(const float *Y, int64_t s_, int64_t e_)
     {
         s = s_;
@@ -411,17 +430,34 @@ struct SlabMap {
         const uint64_t ya = (uint64_t)(uintptr_t)(Y + s);
         a0 = s + (int64_t)(((16u - (unsigned)(ya & 15u)) & 15u) >> 2);
         a0 = a0 < e ? a0 : e;
-        const int64_t nq = (e - a0) >> 2;
+        nq = (e - a0) >> 2;
         t0 = a0 + 4 * nq;
         nchunks = (nq + 63) >> 6;
+        fine = nchunks * 4 <= kSlabs;
     }
     __device__ int last_slab() const
     {
-        return nchunks == 0 ? 0 : (int)(nchunks <= kSlabs ? nchunks - 1 : ((nchunks - 1) * kSlabs) / nchunks);
+        if (nchunks == 0)
+            return 0;
+        if (fine)
+            return (int)((nq - 1) >> 4);
+        return (int)(nchunks <= kSlabs ? nchunks - 1 : ((nchunks - 1) * kSlabs) / nchunks);
     }
     __device__ void range(int i, int64_t &lo, int64_t &hi) const
     {
-        int64_t c0, c1; // chunks [c0, c1)
+        int64_t c0, c1; // chunks [c0, c1), or 64-point rows when fine
+        if (fine) {
+            lo = a0 + 64 * (int64_t)i;
+            hi = a0 + 64 * (int64_t)(i + 1);
+            hi = hi < t0 ? hi : t0;
+            if (i == 0)
+                lo = s;
+            if (i == last_slab())
+                hi = e;
+            if (hi < lo)
+                hi = lo;
+            return;
+        }
         if (nchunks <= kSlabs) {
             c0 = i < nchunks ? i : nchunks;
             c1 = i < nchunks ? i + 1 : nchunks;
