@@ -112,3 +112,29 @@ def test_group_loads_at_every_alignment(y_off, x_off):
     np.testing.assert_array_equal(got, oracle.lttb(y_np, n_out, x_np))
     got_i = ops.lttb(ybuf[y_off:], n_out).cpu().numpy()
     np.testing.assert_array_equal(got_i, oracle.lttb(y_np, n_out))
+
+
+@pytest.mark.parametrize("per_bucket", [65, 100, 257, 8187, 8192, 8196, 8451])
+@pytest.mark.parametrize("y_off", [0, 3])
+@pytest.mark.parametrize("kind", ["walk", "composite", "spiky"])
+def test_slab_rows_around_32_chunks(per_bucket, y_off, kind):
+    """Buckets of at most 32 chunks of 256 points keep a slab per 64-point row
+    in both passes, longer buckets a slab per chunk: buckets of a few rows and
+    just below, at and above 8192 points, at two alignments of y, equal the
+    oracle and the sequential pass."""
+    n_out = 40
+    n = (n_out - 2) * per_bucket + 2
+    y_np = _y(kind, n, per_bucket + y_off)
+    x_np = _x(per_bucket, n)
+    ybuf = torch.empty(n + y_off, dtype=torch.float32, device=DEV)
+    ybuf[y_off:] = torch.from_numpy(y_np).to(DEV)
+    xd = None if x_np is None else torch.from_numpy(x_np).to(DEV)
+    got = ops.lttb(ybuf[y_off:], n_out, x=xd).cpu().numpy()
+    np.testing.assert_array_equal(got, oracle.lttb(y_np, n_out, x_np))
+    old = ops.get_tuning()
+    try:
+        ops.set_tuning(0, 0, ops.CHAIN_SEQUENTIAL)
+        seq = ops.lttb(ybuf[y_off:], n_out, x=xd).cpu().numpy()
+    finally:
+        ops.set_tuning(*old)
+    np.testing.assert_array_equal(got, seq)

@@ -135,6 +135,34 @@ def test_edge_shapes(n, n_out, r_ps, kind, chain_mode):
         _check_lttb(y, n_out, x, (n + 2) % 4)
 
 
+def _takes_fused_tail(n, n_out, r_ps):
+    """Whether the library runs this call's tail as one fused launch (at most
+    3840 bins, a segmented chain, and a chain segment's points with the
+    bucket before and after within 640 staging slots)."""
+    nb = n_out * r_ps // 2
+    B = n_out - 2
+    mbb = (2 * nb + B - 1) // B
+    return nb < n - 2 and nb <= 3840 and mbb <= 64 and 34 * mbb + 2 <= 640
+
+
+@pytest.mark.parametrize("n_out,r_ps", [(1920, 4), (1921, 4), (3, 2), (4, 2), (5, 3), (33, 2), (34, 2),
+                                        (70, 16), (70, 17), (400, 17), (400, 18), (227, 16), (3840, 2),
+                                        (3841, 2)])
+def test_fused_tail_on_both_sides_of_its_limits(n_out, r_ps, chain_mode):
+    """The fused tail (one workgroup per chain segment, the last one linking)
+    and the three-launch form around the fused tail's limits: 3840 bins,
+    640 staged points per segment, 1, 2 and many segments; both equal to the
+    oracle, for implicit and int64 x and two alignments of y."""
+    n = 1_200_007
+    y = _series("walk", n, n_out * 7 + r_ps)
+    x = synth.to_numpy(synth.irregular_x(n, n_out))
+    fused = _takes_fused_tail(n, n_out, r_ps)
+    assert fused == ((n_out, r_ps) in {(1920, 4), (3, 2), (4, 2), (5, 3), (33, 2), (34, 2), (70, 16), (70, 17),
+                                       (400, 17), (227, 16), (3840, 2)})
+    for off, xs in ((0, None), (3, x)):
+        _check_mmlttb(y, n_out, r_ps, xs, off)
+
+
 def test_signed_zero_and_planted_extremes(chain_mode):
     n = 50_000
     y = np.zeros(n, dtype=np.float32)
