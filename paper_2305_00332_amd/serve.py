@@ -26,6 +26,7 @@ PlainGpuExecutor one single-series call per request (the comparator).
 from __future__ import annotations
 
 import collections
+import ctypes
 import math
 import time
 from dataclasses import dataclass, field
@@ -350,12 +351,65 @@ class Arena:
             del holes[i]
 
 
+class _HipRuntime:
+    """The process's HIP runtime (the one torch loaded: the same shared object,
+    found by its soname) for the serving loop's stream-ordered copies of
+    results to pinned host memory and its completion events, called without
+    torch dispatch in between."""
+
+    DEVICE_TO_HOST = 2
+    DISABLE_TIMING = 2
+    NOT_READY = 600
+
+    def __init__(self):
+        h = ctypes.CDLL("libamdhip64.so.7")
+        vp = ctypes.c_void_p
+        h.hipMemcpyAsync.argtypes = [vp, vp, ctypes.c_size_t, ctypes.c_int, vp]
+        h.hipMemcpyAsync.restype = ctypes.c_int
+        h.hipEventCreateWithFlags.argtypes = [ctypes.POINTER(vp), ctypes.c_uint]
+        h.hipEventCreateWithFlags.restype = ctypes.c_int
+        h.hipEventRecord.argtypes = [vp, vp]
+        h.hipEventRecord.restype = ctypes.c_int
+        h.hipEventQuery.argtypes = [vp]
+        h.hipEventQuery.restype = ctypes.c_int
+        h.hipEventDestroy.argtypes = [vp]
+        h.hipEventDestroy.restype = ctypes.c_int
+        self.h = h
+
+    def event(self):
+        ev = ctypes.c_void_p()
+        rc = self.h.hipEventCreateWithFlags(ctypes.byref(ev), self.DISABLE_TIMING)
+        if rc != 0:
+            raise RuntimeError(f"hipEventCreateWithFlags failed ({rc})")
+        return ev
+
+    def copy_to_host(self, dst, src, nbytes, stream):
+        rc = self.h.hipMemcpyAsync(dst, src, nbytes, self.DEVICE_TO_HOST, stream)
+        if rc != 0:
+            raise RuntimeError(f"hipMemcpyAsync failed ({rc})")
+
+    def record(self, ev, stream):
+        rc = self.h.hipEventRecord(ev, stream)
+        if rc != 0:
+            raise RuntimeError(f"hipEventRecord failed ({rc})")
+
+    def done(self, ev) -> bool:
+        rc = self.h.hipEventQuery(ev)
+        if rc == self.NOT_READY:
+            return False
+        if rc != 0:
+            raise RuntimeError(f"step failed on the device (hipEventQuery: {rc})")
+        return True
+
+
 class GpuExecutor:
     """Runs each admitted set of requests as one batched call on the slot's
     stream (a set of one takes the single-series call, which launches fewer
     kernels and gives the same indices), then copies the indices to the slot's
     pinned host buffer on that stream. Workspace and output of every step come
-    from one device arena of `arena_bytes` allocated here."""
+    from one device arena of `arena_bytes` allocated here. Launches, copies and
+    completion events go through the C ABI and the HIP runtime with raw
+    pointers, so a step costs the host a few calls."""
 
     def __init__(self, y, offsets, lengths, x=None, n_slots: int = 2, arena_bytes: int = 256 << 20,
                  host_capacity: int = 1 << 20):
@@ -370,8 +424,22 @@ class GpuExecutor:
         self.arena = torch.empty(self.capacity, dtype=torch.uint8, device=y.device)
         self.blocks = Arena(self.capacity)
         self.host = [torch.empty(host_capacity, dtype=torch.int64, pin_memory=True) for _ in range(n_slots)]
-        self.done_events = [torch.cuda.Event() for _ in range(n_slots)]
+        self.lib = _lib.load()
+        self.hip = _HipRuntime()
+        self.events = [self.hip.event() for _ in range(n_slots)]
+        self.stream_ptrs = [s.cuda_stream for s in self.streams]
+        self.arena_ptr = self.arena.data_ptr()
+        self.y_ptr = y.data_ptr()
+        self.x_ptr = x.data_ptr() if x is not None else None
+        self.xk = _lib.X_INT64 if x is not None else _lib.X_IMPLICIT
         self._ws_cache = {}
+
+    def __del__(self):
+        try:
+            for ev in getattr(self, "events", []):
+                self.hip.h.hipEventDestroy(ev)
+        except Exception:  # interpreter shutdown
+            pass
 
     def series_len(self, s: int) -> int:
         return int(self.lengths[s])
@@ -395,12 +463,12 @@ class GpuExecutor:
         """The step's exact device memory (workspace sized by the library for
         this step, output indices) as one arena block, or None when it does
         not fit now."""
-        from .ops import batched_workspace_size, segment_table
-
         table = None
         if len(reqs) == 1:
             ws = self._single_ws(reqs[0].n_out, reqs[0].r_ps)
         else:
+            from .ops import segment_table
+
             table = segment_table(self._segs(reqs))
             ws = int(_lib.load().mmlttb_batched_workspace_size(table[0], len(table[0])))
         total_out = sum(min(r.n, r.n_out) for r in reqs)
@@ -431,24 +499,43 @@ class GpuExecutor:
                                           pin_memory=True)
         return self.host[slot][:count]
 
+    def _finish(self, slot, out_ptr, count):
+        """Copy the step's indices to the slot's pinned buffer and record the
+        slot's event, both on the slot's stream."""
+        host = self._host(slot, count)
+        if count:
+            self.hip.copy_to_host(host.data_ptr(), out_ptr, 8 * count, self.stream_ptrs[slot])
+        self.hip.record(self.events[slot], self.stream_ptrs[slot])
+        return host
+
+    def _launch_one(self, r, slot, ws_ptr, ws_bytes, out_ptr):
+        o = int(self.offsets[r.series]) + r.lo
+        xp = None if self.x_ptr is None else self.x_ptr + 8 * o
+        _lib.check(self.lib.mmlttb_minmaxlttb(self.xk, xp, self.y_ptr + 4 * o, r.n, r.n_out, r.r_ps, out_ptr,
+                                              ws_ptr, ws_bytes, self.stream_ptrs[slot]))
+
+    def _launch_single(self, r, slot, token):
+        """A step of one request: the single-series call into the step's block."""
+        base = self.arena_ptr + token["block"][0]
+        ws_bytes = token["ws_each"][0] if token.get("ws_each") else token["ws"]
+        self._launch_one(r, slot, base, ws_bytes, base + token["ws"])
+        k = min(r.n, r.n_out)
+        return (self.events[slot], self._finish(slot, base + token["ws"], k), [0], [k])
+
     def launch(self, reqs, slot, token):
+        if len(reqs) == 1:
+            return self._launch_single(reqs[0], slot, token)
         from .ops import minmaxlttb_batched
 
-        if len(reqs) == 1:
-            return PlainGpuExecutor.launch(self, reqs, slot, token)
         torch = self.torch
         ws, out = self._views(token)
-        stream = self.streams[slot]
-        with torch.cuda.stream(stream):
+        with torch.cuda.stream(self.streams[slot]):
             _, outoff = minmaxlttb_batched(self.y, None, x_base=self.x, out=out, ws=ws, table=token["table"])
-            host = self._host(slot, token["out"])
-            host.copy_(out[: token["out"]], non_blocking=True)
-            ev = self.done_events[slot]
-            ev.record(stream)
-        return (ev, host, outoff, [min(r.n, r.n_out) for r in reqs])
+        host = self._finish(slot, out.data_ptr(), token["out"])
+        return (self.events[slot], host, outoff, [min(r.n, r.n_out) for r in reqs])
 
     def poll(self, handle) -> bool:
-        return handle[0].query()
+        return self.hip.done(handle[0])
 
     def collect(self, handle):
         _, host, outoff, counts = handle
@@ -469,24 +556,18 @@ class PlainGpuExecutor(GpuExecutor):
         return {"block": block, "ws": sum(ws), "ws_each": ws, "out": total_out, "table": None}
 
     def launch(self, reqs, slot, token):
-        from .ops import minmaxlttb
-
-        torch = self.torch
-        ws_all, out = self._views(token)
+        if len(reqs) == 1:
+            return self._launch_single(reqs[0], slot, token)
+        base = self.arena_ptr + token["block"][0]
         ws_each = token.get("ws_each") or [token["ws"]]
-        stream = self.streams[slot]
+        out_ptr = base + token["ws"]
         counts = [min(r.n, r.n_out) for r in reqs]
-        offs = [int(v) for v in np.concatenate([[0], np.cumsum(counts)[:-1]])]
-        with torch.cuda.stream(stream):
-            w = 0
-            for r, o_out, k, wb in zip(reqs, offs, counts, ws_each):
-                o = int(self.offsets[r.series]) + r.lo
-                xs = None if self.x is None else self.x[o: o + r.n]
-                minmaxlttb(self.y[o: o + r.n], r.n_out, r.r_ps, x=xs, out=out[o_out: o_out + k],
-                           ws=ws_all[w: w + wb])
-                w += wb
-            host = self._host(slot, token["out"])
-            host.copy_(out[: token["out"]], non_blocking=True)
-            ev = self.done_events[slot]
-            ev.record(stream)
-        return (ev, host, offs, counts)
+        offs = [0] * len(reqs)
+        w = o_out = 0
+        for i, (r, k, wb) in enumerate(zip(reqs, counts, ws_each)):
+            offs[i] = o_out
+            self._launch_one(r, slot, base + w, wb, out_ptr + 8 * o_out)
+            w += wb
+            o_out += k
+        host = self._finish(slot, out_ptr, token["out"])
+        return (self.events[slot], host, offs, counts)
