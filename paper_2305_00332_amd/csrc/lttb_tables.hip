@@ -325,7 +325,7 @@ __global__ __launch_bounds__(256) void k_lttb_scan(const int64_t *__restrict__ X
 // One side's arc: vertices (x relative to the bucket's first point, y) in
 // increasing x, the float32 slopes of its edges, and the slopes of the lines
 // that stand for it left of its first and right of its last vertex.
-constexpr int kArcSlopes = 8; // touching points that make an arc
+constexpr int kArcSlopes = 12; // touching points that make an arc
 constexpr int kScanU = 8;     // points in flight per thread in the survivor scan
 struct Arc {
     double x[kArcSlopes], y[kArcSlopes];
