@@ -246,7 +246,8 @@ int mmlttb_minmax_simplify(int alg, int xk, const int64_t *x, const float *y, in
     if ((rc = enqueue_preselect(x, y, n, n_out, r_ps, ws, L, P, XP, YP, m, s)))
         return rc;
     // per-point state in LDS when it fits the device's per-workgroup limit
-    const int64_t bytes = simplify_scratch_bytes(cap);
+    const int64_t bytes = simplify_state_lds_bytes(cap);
+    const int64_t tbytes = simplify_tree_lds_bytes(cap);
     int dev = 0, lds_max = 0, lds_optin = 0;
     if (hipGetDevice(&dev) == hipSuccess) {
         if (hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
@@ -256,8 +257,11 @@ int mmlttb_minmax_simplify(int alg, int xk, const int64_t *x, const float *y, in
         lds_max = lds_optin > lds_max ? lds_optin : lds_max;
     }
     bool in_lds = bytes <= (int64_t)lds_max;
-    if (in_lds && bytes > 65536 && simplify_allow_lds((size_t)bytes) != hipSuccess)
-        in_lds = false;
+    bool tree_in_lds = alg == MMLTTB_SIMPLIFY_DP && tbytes + simplify_tree_static_lds() <= (int64_t)lds_max;
+    const size_t want_state = in_lds && bytes > 65536 ? (size_t)bytes : 0;
+    const size_t want_tree = tree_in_lds && tbytes > 65536 ? (size_t)tbytes : 0;
+    if ((want_state || want_tree) && simplify_allow_lds(want_state, want_tree) != hipSuccess)
+        in_lds = tree_in_lds = false;
     SimplifyArgs a;
     a.XP = XP;
     a.YP = YP;
@@ -269,6 +273,7 @@ int mmlttb_minmax_simplify(int alg, int xk, const int64_t *x, const float *y, in
     a.cap_bucket = (cap - 2 + (n_out - 2) - 1) / (n_out - 2); // ceil((m - 2) / B) for any m <= cap
     a.scratch = static_cast<unsigned char *>(ws) + L.total;
     a.in_lds = in_lds ? 1 : 0;
+    a.tree_in_lds = tree_in_lds ? 1 : 0;
     static const char *names[] = {"", "simplify_vw", "simplify_dp", "simplify_llb"};
     MMLTTB_LAUNCH(names[alg], s, launch_simplify(alg, a, s));
     return ok();

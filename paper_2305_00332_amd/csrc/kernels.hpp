@@ -216,7 +216,8 @@ hipError_t launch_m4_compact(const unsigned long long *keys, const Split &bins, 
                              hipStream_t s);
 hipError_t launch_everynth(int64_t n, int64_t n_out, int64_t *out, hipStream_t s);
 // Other simplifiers on the preselected points (1 VW, 2 DP, 3 LLB). Per-point
-// state lives in LDS (in_lds) or at `scratch` in the workspace.
+// state lives in LDS (in_lds) or at `scratch` in the workspace; DP's split
+// tree keeps its most used arrays in LDS when tree_in_lds is set.
 struct SimplifyArgs {
     const int64_t *XP;    // raw x (or the index) of the m points
     const float *YP;      // y of the points
@@ -228,10 +229,16 @@ struct SimplifyArgs {
     int64_t cap_bucket;   // bound on the points of one LTTB bucket (LLB)
     unsigned char *scratch;
     int in_lds;
+    int tree_in_lds;
 };
 int64_t simplify_scratch_bytes(int64_t cap);
+int64_t simplify_state_lds_bytes(int64_t cap); // the greedy loops' state
+int64_t simplify_tree_lds_bytes(int64_t cap);  // DP's split tree (dynamic LDS)
+int64_t simplify_tree_static_lds();            // bound on its static LDS
 hipError_t launch_simplify(int alg, const SimplifyArgs &a, hipStream_t s);
-hipError_t simplify_allow_lds(size_t bytes);
+// Let the LDS forms of the kernels take state_bytes (greedy loops) and
+// tree_bytes (DP's split tree) of dynamic LDS; 0 leaves a limit as it is.
+hipError_t simplify_allow_lds(size_t state_bytes, size_t tree_bytes);
 
 // Value types of the typed path (y) and the per-work-item MinMax partial.
 enum { kYF32 = 0, kYF64 = 1, kYI32 = 2 };

@@ -96,3 +96,49 @@ def test_simplifier_errors():
         ops.minmax_simplify("dp", y, 100, 4, ws=torch.empty(8, dtype=torch.uint8, device=DEV))
     np.testing.assert_array_equal(ops.minmax_simplify("llb", y, 100, 4).cpu().numpy(),
                                   oracle.minmax_simplify("llb", y.cpu().numpy(), 100, 4))
+
+
+# Douglas-Peucker runs as a split tree built a level at a time, ranked by path
+# bottlenecks, with a best-first walk inside the cluster that holds step
+# n_out - 2; trees deeper than 512 levels and walks of more than 256 steps or
+# over more than 512 nodes go to the greedy loop. Each case below takes one of
+# those routes (noted beside it). "noise0" is uniform noise whose first and
+# last values are 0: the whole series' chord is then flat and most of the
+# tree ranks with its root, in a cluster of ~900 nodes at 3000 points; with
+# n <= n_out * r_ps / 2 + 2 every point is preselected.
+def _dp_series(kind, n, seed):
+    if kind == "noise0":
+        y = np.random.default_rng(seed).uniform(-1, 1, n).astype(np.float32)
+        y[0] = y[-1] = 0
+        return y
+    if kind == "zigzag":
+        return (np.where(np.arange(n) % 2 == 0, 1.0, -1.0) + np.arange(n) * 1e-5).astype(np.float32)
+    if kind == "saw":
+        return (np.arange(n) % 1000).astype(np.float32)
+    return _series(kind, n, seed)
+
+
+DP_ROUTES = [
+    ("walk", 200_000, 1000, 4),      # one step in a cluster of two nodes
+    ("noise0", 1500, 200, 16),       # 198 steps inside the root's cluster of 436 nodes
+    ("zigzag", 200_000, 100, 4),     # 10 steps in a cluster of 14
+    ("zigzag", 200_000, 1000, 4),    # 4 steps, a 205-level tree
+    ("saw", 200_000, 20, 4),         # the boundary cluster taken whole (16 nodes)
+    ("const", 200_000, 100, 4),      # a chain n_out - 2 levels deep: every node kept
+    ("ties", 200_000, 100, 4),       # 3 steps in a cluster of 14, a 98-level tree
+    ("ties", 200_000, 600, 2),       # deeper than 512 levels: the greedy loop
+    ("const", 200_000, 1000, 4),     # a chain deeper than 512 levels: the greedy loop
+    ("noise0", 3000, 375, 16),       # 373 steps inside the root's cluster: the greedy loop
+    ("noise0", 3000, 250, 24),       # 248 steps in a cluster of ~900 nodes: the greedy loop
+    ("walk", 200_000, 1015, 4),      # 4062 points: the largest preselection whose tree state fits LDS
+    ("walk", 200_000, 1016, 4),      # 4066 points: the smallest whose tree state goes to the workspace
+    ("zigzag", 200_000, 1300, 8),    # 10402 points: the tree's arrays in the workspace; 4 steps
+    ("noise0", 6000, 1500, 8),       # the workspace, then 1498 steps in the root's cluster: the greedy loop
+]
+
+
+@pytest.mark.parametrize("kind,n,n_out,r_ps", DP_ROUTES, ids=lambda v: str(v))
+def test_dp_split_tree_routes(kind, n, n_out, r_ps):
+    y = _dp_series(kind, n, n + n_out)
+    got = ops.minmax_simplify("dp", _dev(y), n_out, r_ps).cpu().numpy()
+    np.testing.assert_array_equal(got, oracle.minmax_simplify("dp", y, n_out, r_ps))
