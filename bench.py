@@ -635,8 +635,9 @@ def bench_typed(args, reps: int = 10):
 def bench_simplifiers(args, reps: int = 10):
     """MinMax preselection followed by Visvalingam-Whyatt, Douglas-Peucker or
     Longest-Line-Bucket instead of LTTB, on the headline series (n=1e9,
-    n_out and r_ps as the headline): call time, the simplifier kernel's time
-    (one wave on the preselected points), parity with the oracle."""
+    n_out and r_ps as the headline): call time, the simplifier kernels' time
+    on the preselected points (VW and LLB: one wave; DP: the split tree in one
+    workgroup, then the greedy loop's gated launch), parity with the oracle."""
     import numpy as np
     import torch
 
