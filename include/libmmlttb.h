@@ -318,8 +318,9 @@ int mmlttb_graph_cache_stats(int64_t *entries, int64_t *hits, int64_t *captures)
  * bucket in order), 2 segmented (segments walked from every start point in
  * parallel, then linked; used when buckets hold at most 64 points), 3
  * automatic (segmented when possible); tile = points a workgroup stages in
- * LDS for batched series with small bins (2048, 4096 or 8192; bins of at most
- * tile/4 points take that path); batch_unroll and batch_chunk = unroll and
+ * LDS for small bins, of batched series and of single float32 series long
+ * enough for the chunked short-bin stream (2048, 4096 or 8192; bins of at
+ * most tile/4 points take that path); batch_unroll and batch_chunk = unroll and
  * chunk of the batched large-bin stream. The compiled defaults are the best
  * settings measured on MI355X: unroll 4, chunk 2^20, chain 3, tile 4096,
  * batch_unroll 4, batch_chunk 65536 (environment variables MMLTTB_UNROLL,

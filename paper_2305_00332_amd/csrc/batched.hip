@@ -135,17 +135,17 @@ struct SmallTile {
     int nbt, lg;
 };
 
-__device__ inline SmallTile plan_small_tile(const BatchPtrs &b, int64_t t)
+// Tile `tl` of one series (y: the series, keys: its first bin's key pair,
+// bins over its interior, G bins a tile).
+__device__ inline SmallTile plan_series_tile(const float *y, unsigned long long *keys, const Split &bins, int G,
+                                             int64_t tl)
 {
-    const int64_t s = find_owner(b.segs, b.hdr->own_small, b.n_small_tiles, t, [](const BatchSeg &g) { return g.ti0; });
-    const BatchSeg &g = b.segs[s];
     SmallTile T;
-    const int G = g.tile_bins;                 // power of two, 4..256
-    T.lg = 8 - __builtin_ctz((unsigned)G);     // log2 of the lanes per bin (kTileThreads = 2^8)
-    T.nb = g.bins.parts;
-    T.bq = g.bins.q;
-    T.br = g.bins.r;
-    const int64_t bb0 = (t - g.ti0) * G;
+    T.lg = 8 - __builtin_ctz((unsigned)G);     // log2 of the lanes per bin (kTileThreads = 2^8); G a power of two, 4..256
+    T.nb = bins.parts;
+    T.bq = bins.q;
+    T.br = bins.r;
+    const int64_t bb0 = tl * G;
     T.nbt = (int)((bb0 + G < T.nb) ? G : T.nb - bb0); // bins in this tile
     // Bin bb0 + i starts at split_lo(bb0) + i q + floor((rem0 + i r) / nb), with
     // rem0 = bb0 r mod nb; the planner routes only nb < 2^26 here, so every
@@ -156,8 +156,8 @@ __device__ inline SmallTile plan_small_tile(const BatchPtrs &b, int64_t t)
     T.rem0 = t0 - f0 * T.nb;
     T.lo = 1 + bb0 * T.bq + f0;
     T.hi = T.lo + (int64_t)T.nbt * T.bq + div_near(T.rem0 + (int64_t)T.nbt * T.br, T.nb, T.inv);
-    T.y = b.y_base + g.offset;
-    T.keys = b.keys + 2 * (g.key0 + bb0);
+    T.y = y;
+    T.keys = keys + 2 * bb0;
     const uint64_t addr = (uint64_t)(uintptr_t)(T.y + T.lo);
     int64_t head = (int64_t)(((16u - (unsigned)(addr & 15u)) & 15u) >> 2);
     head = head < T.hi - T.lo ? head : T.hi - T.lo;
@@ -165,6 +165,13 @@ __device__ inline SmallTile plan_small_tile(const BatchPtrs &b, int64_t t)
     T.nvec = (T.hi - T.body) >> 2;
     T.tail0 = T.body + 4 * T.nvec;
     return T;
+}
+
+__device__ inline SmallTile plan_small_tile(const BatchPtrs &b, int64_t t)
+{
+    const int64_t s = find_owner(b.segs, b.hdr->own_small, b.n_small_tiles, t, [](const BatchSeg &g) { return g.ti0; });
+    const BatchSeg &g = b.segs[s];
+    return plan_series_tile(b.y_base + g.offset, b.keys + 2 * g.key0, g.bins, g.tile_bins, t - g.ti0);
 }
 
 // Issue the tile's loads: 16-byte loads of the body, plus one head or tail
@@ -246,13 +253,12 @@ __device__ inline void reduce_small_tile(const SmallTile &T, const float *tile, 
 constexpr int kSmallTilesPerBlock = 2;
 static_assert(kSmallTilesPerBlock == 2, "k_batch_small is written for two tiles per workgroup");
 
-template <int kTilePoints>
-__global__ __launch_bounds__(kTileThreads) void k_batch_small(BatchPtrs b)
+// The tiles of this workgroup (plan(t) gives tile t of `total`), into the
+// workgroup's LDS arrays.
+template <int kTilePoints, class Plan>
+__device__ inline void small_tile_pair(int64_t total, Plan plan, float *tile, int32_t *bstart)
 {
-    __shared__ float tile[kTilePoints];
-    __shared__ int32_t bstart[kTileThreads + 1]; // bin starts, relative to the tile's first point
     constexpr int kVec = kTilePoints / 4 / kTileThreads;
-    const int64_t total = b.n_small_tiles;
     const int64_t t0 = (int64_t)blockIdx.x * kSmallTilesPerBlock;
     if (t0 >= total)
         return;
@@ -260,11 +266,11 @@ __global__ __launch_bounds__(kTileThreads) void k_batch_small(BatchPtrs b)
     f32x4 d0[kVec], d1[kVec];
     float hv0, hv1;
     int64_t hq0, hq1;
-    const SmallTile T0 = plan_small_tile(b, t0);
+    const SmallTile T0 = plan(t0);
     load_small_tile(T0, d0, hv0, hq0);
     SmallTile T1;
     if (t1 >= 0)
-        T1 = plan_small_tile(b, t1);
+        T1 = plan(t1);
     stage_small_tile(T0, d0, hv0, hq0, tile, bstart);
     if (t1 >= 0)
         load_small_tile(T1, d1, hv1, hq1);
@@ -276,6 +282,27 @@ __global__ __launch_bounds__(kTileThreads) void k_batch_small(BatchPtrs b)
         __syncthreads();
         reduce_small_tile(T1, tile, bstart);
     }
+}
+
+template <int kTilePoints>
+__global__ __launch_bounds__(kTileThreads) void k_batch_small(BatchPtrs b)
+{
+    __shared__ float tile[kTilePoints];
+    __shared__ int32_t bstart[kTileThreads + 1]; // bin starts, relative to the tile's first point
+    small_tile_pair<kTilePoints>(b.n_small_tiles, [&](int64_t t) { return plan_small_tile(b, t); }, tile, bstart);
+}
+
+// One float32 series' short bins (at most a quarter tile each), G whole bins
+// a tile: the batched small-bin body on a single series, writing every bin's
+// key pair (no key initialisation).
+template <int kTilePoints>
+__global__ __launch_bounds__(kTileThreads) void k_minmax_small_tiles(const float *y, Split bins, int G, int64_t n_tiles,
+                                                                     unsigned long long *keys)
+{
+    __shared__ float tile[kTilePoints];
+    __shared__ int32_t bstart[kTileThreads + 1];
+    small_tile_pair<kTilePoints>(n_tiles, [&](int64_t t) { return plan_series_tile(y, keys, bins, G, t); }, tile,
+                                 bstart);
 }
 
 // One workgroup per series: compaction (the means follow in k_batch_means).
@@ -485,6 +512,39 @@ hipError_t launch_batch_small(const BatchPtrs &b, int tile, hipStream_t s)
         break;
     default:
         hipLaunchKernelGGL(k_batch_small<4096>, grid, dim3(kTileThreads), 0, s, b);
+        break;
+    }
+    return hipGetLastError();
+}
+
+int small_tile_bins(int64_t maxbin, int64_t nb, int tile)
+{
+    if (maxbin < 1 || maxbin > tile / 4 || nb >= ((int64_t)1 << 26))
+        return 0;
+    int G = 256;
+    while ((int64_t)G * maxbin > tile)
+        G >>= 1;
+    return G;
+}
+
+hipError_t launch_minmax_small_tiles(const float *y, const Split &bins, int tile, unsigned long long *keys,
+                                     hipStream_t s)
+{
+    const int64_t maxbin = bins.q + (bins.r ? 1 : 0);
+    const int G = small_tile_bins(maxbin, bins.parts, tile);
+    if (G == 0)
+        return hipErrorInvalidValue;
+    const int64_t n_tiles = (bins.parts + G - 1) / G;
+    const dim3 grid(cap_grid((n_tiles + kSmallTilesPerBlock - 1) / kSmallTilesPerBlock, 0x7fffffff));
+    switch (tile) {
+    case 2048:
+        hipLaunchKernelGGL(k_minmax_small_tiles<2048>, grid, dim3(kTileThreads), 0, s, y, bins, G, n_tiles, keys);
+        break;
+    case 8192:
+        hipLaunchKernelGGL(k_minmax_small_tiles<8192>, grid, dim3(kTileThreads), 0, s, y, bins, G, n_tiles, keys);
+        break;
+    default:
+        hipLaunchKernelGGL(k_minmax_small_tiles<4096>, grid, dim3(kTileThreads), 0, s, y, bins, G, n_tiles, keys);
         break;
     }
     return hipGetLastError();

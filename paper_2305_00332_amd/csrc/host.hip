@@ -250,6 +250,11 @@ int enqueue_minmax_stream(const float *y, const MinMaxGeom &g, unsigned long lon
 {
     const int64_t maxbin = g.bins.q + (g.bins.r ? 1 : 0);
     if (maxbin < kShortBin && g.bins.len >= kShortBinChunk * kFillItems) { // and at least 2048 chunks
+        if (!ticket && small_tile_bins(maxbin, g.bins.parts, tuning().tile) > 0) {
+            // bins of at most a quarter tile: whole bins per tile, every key written
+            MMLTTB_LAUNCH("minmax_bin_reduce", s, launch_minmax_small_tiles(y, g.bins, tuning().tile, keys, s));
+            return MMLTTB_OK;
+        }
         MMLTTB_LAUNCH("init_keys", s, launch_init_keys(keys, g.bins.parts, s, ticket));
         MMLTTB_LAUNCH("minmax_bin_reduce", s, launch_minmax_stream_chunks(y, g.bins, tuning().unroll, keys, s));
         return MMLTTB_OK;

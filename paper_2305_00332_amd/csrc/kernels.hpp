@@ -41,6 +41,12 @@ constexpr int64_t kShortBin = 4096;
 constexpr int64_t kShortBinChunk = 65536;
 hipError_t launch_minmax_stream_chunks(const float *y, const Split &bins, int unroll, unsigned long long *keys,
                                       hipStream_t s);
+// Bins per small-bin tile for one series' bins of at most maxbin points (0:
+// the bins are too long for `tile`-point tiles, or too many for the tile
+// planner's binary64 bin starts), and the single-series small-bin launch.
+int small_tile_bins(int64_t maxbin, int64_t nb, int tile);
+hipError_t launch_minmax_small_tiles(const float *y, const Split &bins, int tile, unsigned long long *keys,
+                                     hipStream_t s);
 
 // LDS window of the sequential chain, in points.
 constexpr int kChainStage = 1024;

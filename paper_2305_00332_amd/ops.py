@@ -337,7 +337,8 @@ def set_tuning(unroll: int = 0, chunk: int = 0, chain: int = 0, tile: int = 0, b
                batch_chunk: int = 0):
     """Execution tuning (results never depend on it): single-series MinMax loads
     in flight per lane and points per work item, LTTB pass form (1 sequential,
-    2 segmented, 3 automatic), batched small-bin tile points, batched large-bin
+    2 segmented, 3 automatic), small-bin tile points (batched series, and
+    single series' short bins), batched large-bin
     loads in flight and points per work item. Zero keeps the current value, so
     set_tuning(*get_tuning()) restores a saved setting exactly."""
     _lib.check(_lib.load().mmlttb_set_tuning(unroll, chunk, chain, tile, batch_unroll, batch_chunk))

@@ -94,8 +94,9 @@ def test_large_output_sizes(chain_mode):
 
 def test_short_bins_of_a_long_series():
     """A series of 2e8 points with bins of fewer than 4096 points is streamed
-    in fixed chunks of 65536 points across bin ends (wave_stream_bins) rather
-    than one work item per bin: bins of 763 and 3051 points."""
+    rather than one work item per bin: bins of at most a quarter tile (763
+    points) in tiles of whole bins, longer ones (3051) in fixed chunks of
+    65536 points across bin ends (wave_stream_bins)."""
     _say("generating 2e8 random walk on the GPU")
     y = synth.random_walk(200_000_000, 17, device="cuda")
     torch.cuda.synchronize()
@@ -107,3 +108,49 @@ def test_short_bins_of_a_long_series():
         P, m = ops.minmax(y, n_out, r_ps)
         np.testing.assert_array_equal(P[: int(m)].cpu().numpy(), oracle.minmax(y_np, n_out, r_ps))
     del y
+
+
+@pytest.mark.parametrize("tile", [2048, 4096, 8192])
+def test_short_bin_tiles_around_their_limit(tile):
+    """Bins of at most tile / 4 points in a 2e8-point series go to tiles of
+    whole bins (the batched small-bin body on one series); one point more goes
+    to the chunked stream. For each tile size: bins of exactly tile / 4 and
+    tile / 4 + 1 points through MinMaxLTTB, and bins of at most 16 points (256
+    bins a tile) through MinMax."""
+    y = _walk_2e8()
+    y_np = _walk_2e8_np()
+    old = ops.get_tuning()
+    ops.set_tuning(0, 0, 0, tile)
+    try:
+        interior = 200_000_000 - 2
+        for maxbin in (tile // 4, tile // 4 + 1):
+            nb = -(-interior // (maxbin - 1)) - 1  # the fewest bins whose longest has maxbin points
+            while -(-interior // nb) > maxbin:
+                nb += 1
+            assert -(-interior // nb) == maxbin
+            _say(f"tile={tile} minmaxlttb n=2e8 bins of at most {maxbin} points (nb={nb}, r_ps=2)")
+            got = ops.minmaxlttb(y, nb, 2).cpu().numpy()
+            np.testing.assert_array_equal(got, oracle.minmaxlttb(y_np, nb, 2))
+        nb = -(-interior // 16)
+        _say(f"tile={tile} minmax n=2e8 bins of at most 16 points (nb={nb})")
+        P, m = ops.minmax(y, nb, 2)
+        np.testing.assert_array_equal(P[: int(m)].cpu().numpy(), oracle.minmax(y_np, nb, 2))
+    finally:
+        ops.set_tuning(*old)
+
+
+_WALK = {}
+
+
+def _walk_2e8():
+    if "y" not in _WALK:
+        _say("generating 2e8 random walk on the GPU")
+        _WALK["y"] = synth.random_walk(200_000_000, 23, device="cuda")
+        torch.cuda.synchronize()
+    return _WALK["y"]
+
+
+def _walk_2e8_np():
+    if "np" not in _WALK:
+        _WALK["np"] = _walk_2e8().cpu().numpy()
+    return _WALK["np"]
