@@ -364,10 +364,10 @@ __device__ inline void dp_scan(SimplifyState &s, int64_t p, int64_t q, int lane)
 // among the points reaching the best, by atomic minimum; the splits), ranks
 // the clusters by a radix select over (bottleneck priority, bottleneck
 // index), and walks the boundary cluster in one wave. The state (40 bytes a
-// point) sits in LDS up to about 4000 points, else in the workspace. Trees deeper than kDpMaxLevels (below
-// n_out - 2) and boundary walks longer than kDpMaxSteps steps or over more
-// than kDpMaxCluster nodes are left to the greedy loop, which runs after this
-// kernel only when the gate says so.
+// point) sits in LDS up to about 4000 points, else in the workspace. Trees
+// deeper than kDpMaxLevels (below n_out - 2) and boundary walks longer than
+// kDpMaxSteps steps or over more than kDpMaxCluster nodes are left to the
+// greedy loop, which runs after this kernel only when the gate says so.
 constexpr int kDpThreads = 1024;
 constexpr int kDpWaves = kDpThreads / kWave;
 constexpr int kDpMaxLevels = 512;
