@@ -915,6 +915,23 @@ __global__ __launch_bounds__(64) void k_simplify_dp(SimplifyArgs a)
 
 // ------------------------------------------------------------------ LLB
 
+// Buckets of at most kLlbPair points take one lane per (point of the bucket,
+// point of the previous bucket): lane 8 jj + q.
+constexpr int kLlbPair = 8;
+
+// One DPP step of the per-point best over its 8 lanes: the larger length,
+// the lower previous-bucket position on ties.
+template <int CTRL>
+__device__ inline void llb_best_step(double &t, int &q)
+{
+    const double ot = dpp_f64<CTRL>(t);
+    const int oq = dpp_i32<CTRL>(q);
+    if (ot > t || (ot == t && oq < q)) {
+        t = ot;
+        q = oq;
+    }
+}
+
 template <bool kLds>
 __global__ __launch_bounds__(64) void k_simplify_llb(SimplifyArgs a)
 {
@@ -931,7 +948,42 @@ __global__ __launch_bounds__(64) void k_simplify_llb(SimplifyArgs a)
         s.F[0] = 0.0;
     __syncthreads();
     int64_t p0 = 0, p1 = 1;
-    if (a.cap_bucket <= kWave) {
+    if (a.cap_bucket <= kLlbPair) {
+        // every candidate length of a bucket at once: lane (jj, q) takes
+        // point jj of this bucket after point q of the previous one; group q
+        // of the previous step holds that point's longest length
+        const int jj = lane >> 3, q = lane & (kLlbPair - 1);
+        double pf = 0.0; // this group's point's longest length (the first point's: 0)
+        SplitWalker w;
+        w.init(bk, 0);
+        for (int64_t k = 0; k <= B; ++k) {
+            const int64_t s0 = k < B ? 1 + w.lo : m - 1;
+            const int64_t s1 = k < B ? 1 + w.next_lo(bk) : m;
+            if (k < B)
+                w.advance(bk);
+            const int np = (int)(p1 - p0), nc = (int)(s1 - s0);
+            const bool on = jj < nc && q < np;
+            const int64_t j = s0 + (jj < nc ? jj : 0), i = p0 + (q < np ? q : 0);
+            const double xj = s.X[j], yj = s.Y[j], xi = s.X[i], yi = s.Y[i];
+            const double fi = __shfl(pf, kLlbPair * q);
+            const double dx = xj - xi, dy = yj - yi;
+            const double t = fi + sqrt(dx * dx + dy * dy);
+            // the loop below keeps t > best from best = -1, bi = 0: a NaN or a
+            // length not above -1 never wins, and (-1, 0) stays when none does
+            const bool win = on && t > -1.0;
+            double bt = win ? t : -1.0;
+            int bq = win ? q : 0;
+            llb_best_step<0xB1>(bt, bq);  // lanes q ^ 1
+            llb_best_step<0x4E>(bt, bq);  // lanes q ^ 2
+            llb_best_step<0x141>(bt, bq); // lanes 7 - q: the other quad of the group
+            if (q == 0 && jj < nc)
+                s.A[s0 + jj] = (int32_t)(p0 + bq);
+            pf = bt;
+            p0 = s0;
+            p1 = s1;
+        }
+        __syncthreads();
+    } else if (a.cap_bucket <= kWave) {
         // every bucket fits the wave: lane l holds point l of the previous
         // bucket (x, y, longest length) in registers and reads the others'
         // through readlane

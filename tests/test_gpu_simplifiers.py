@@ -142,3 +142,15 @@ def test_dp_split_tree_routes(kind, n, n_out, r_ps):
     y = _dp_series(kind, n, n + n_out)
     got = ops.minmax_simplify("dp", _dev(y), n_out, r_ps).cpu().numpy()
     np.testing.assert_array_equal(got, oracle.minmax_simplify("dp", y, n_out, r_ps))
+
+
+# Longest-Line-Bucket takes one lane per pair of points of consecutive
+# buckets when buckets hold at most 8 points (ceil(2 floor(n_out r_ps / 2) /
+# (n_out - 2)) <= 8: r_ps up to 7 for n_out >= 16), else one lane per point.
+@pytest.mark.parametrize("r_ps", [2, 3, 6, 7, 8])
+@pytest.mark.parametrize("n_out", [3, 4, 50, 1000])
+@pytest.mark.parametrize("kind", ["walk", "ties"])
+def test_llb_around_the_pair_limit(kind, n_out, r_ps):
+    y = _series(kind, 100_000, 7 * n_out + r_ps)
+    got = ops.minmax_simplify("llb", _dev(y), n_out, r_ps).cpu().numpy()
+    np.testing.assert_array_equal(got, oracle.minmax_simplify("llb", y, n_out, r_ps))
