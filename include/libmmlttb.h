@@ -217,9 +217,13 @@ size_t mmlttb_simplify_workspace_size(int64_t n, int64_t n_out, int32_t r_ps);
  *       sqrt((Xj-Xi)^2 + (Yj-Yi)^2) accumulated bucket by bucket; each point
  *       keeps the lowest-index predecessor giving the largest total.
  * out_idx receives exactly min(n, n_out) ascending series indices; n <= n_out
- * returns 0..n-1. Extra limit: 2*floor(n_out*r_ps/2) + 2 <= 2^31-1. One
- * wave runs the simplifier; its per-point state (32 bytes per point) lives in
- * LDS when it fits, else in the workspace. */
+ * returns 0..n-1. Extra limit: 2*floor(n_out*r_ps/2) + 2 <= 2^31-1. VW and
+ * LLB run in one wave (32 bytes of state per point). DP builds the tree of
+ * splits a level at a time in one workgroup (40 bytes per point) and keeps
+ * the points a step-by-step greedy loop would keep; trees deeper than 512
+ * levels or more than 256 steps inside the last-ranked group of nodes go to
+ * that greedy loop itself (one wave). State lives in LDS when it fits, else in
+ * the workspace. */
 int mmlttb_minmax_simplify(int alg, int xk, const int64_t *x, const float *y, int64_t n, int64_t n_out, int32_t r_ps,
                            int64_t *out_idx, void *ws, size_t ws_bytes, void *stream);
 
