@@ -221,9 +221,9 @@ size_t mmlttb_simplify_workspace_size(int64_t n, int64_t n_out, int32_t r_ps);
  * LLB run in one wave (32 bytes of state per point). DP builds the tree of
  * splits a level at a time in one workgroup (40 bytes per point) and keeps
  * the points a step-by-step greedy loop would keep; trees deeper than 512
- * levels or more than 256 steps inside the last-ranked group of nodes go to
- * that greedy loop itself (one wave). State lives in LDS when it fits, else in
- * the workspace. */
+ * levels, and series whose last-ranked group of nodes needs more than 256
+ * step-by-step picks or holds more than 512 nodes, go to that greedy loop
+ * itself (one wave). State lives in LDS when it fits, else in the workspace. */
 int mmlttb_minmax_simplify(int alg, int xk, const int64_t *x, const float *y, int64_t n, int64_t n_out, int32_t r_ps,
                            int64_t *out_idx, void *ws, size_t ws_bytes, void *stream);
 
